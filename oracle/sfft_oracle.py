@@ -1,0 +1,421 @@
+"""Plain FP64 CPU oracle of the flat-window voting sparse FFT (the sFFT1.0 row of
+Table 1: flat filter, statistics location, energy estimation, voting framework).
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or run anything in this package.
+It shares no code, tables or constants with the HIP library and imports nothing
+from it; the product path never calls it.
+
+Everything is computed in float64 / exact Python or int64 integers, step by step
+in the order the paper gives them, with no blocking or fusion:
+
+  permutation (time scaling Eq.(7) + time shift Eq.(6), permuted-spectrum
+  identity Eq.(9)) -> flat window (sinc Eq.(12) x Gaussian Eq.(13)) ->
+  aliasing into B buckets (Eq.(11)) -> B-point DFT of the buckets -> keep the
+  2K largest buckets and vote ("probability and statistics" location method)
+  -> energy-concentration estimate per located frequency, combined over the
+  random bucketizations by a coordinate-wise median -> K largest -> formula
+  method (Eq.(2)) for the residual energy check.
+
+Where the paper is silent or garbled the readings used here are the ones listed
+in the design notes (window width from the Fig. 1 example, round-half-up
+bucket hash, strict-majority vote threshold, median combiner, ...); each is
+restated at the function that uses it.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Ratio between the flat window length and the Gaussian standard deviation,
+# fixed by the Fig. 1 example of the flat-filter section: N=2048, B=16,
+# Gaussian std = B*sqrt(log2 N) = 53.066 and window support 516, so
+# std = support / (2 * C_G).
+C_G = 516.0 / (2.0 * 16.0 * math.sqrt(11.0))
+
+_MASK64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------------------
+# Random draws: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), written from its
+# published definition: a Weyl counter with increment 0x9E3779B97F4A7C15 and a
+# two-multiply xor-shift finaliser.
+# ---------------------------------------------------------------------------
+def splitmix64(seed: int, n: int) -> list[int]:
+    """First ``n`` outputs of SplitMix64 seeded with ``seed`` (as Python ints)."""
+    state = seed & _MASK64
+    out = []
+    for _ in range(n):
+        state = (state + 0x9E3779B97F4A7C15) & _MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def draw_permutations(N: int, L: int, seed: int, n_resid: int = 0):
+    """Random scaling sigma (odd, so invertible mod N = 2^m) and shift tau per
+    bucketization, drawn in the order sigma_0, tau_0, sigma_1, tau_1, ...;
+    then ``n_resid`` residual-check time positions t_j from the same stream.
+
+    The voting framework uses random frequency scaling per bucketization
+    (voting-framework section); the random shift makes the phase of Eq.(9)
+    random as well.
+    """
+    draws = splitmix64(seed, 2 * L + n_resid)
+    sigma = np.array([(draws[2 * r] & (N - 1)) | 1 for r in range(L)], dtype=np.int64)
+    tau = np.array([draws[2 * r + 1] & (N - 1) for r in range(L)], dtype=np.int64)
+    tpos = np.array([draws[2 * L + j] & (N - 1) for j in range(n_resid)], dtype=np.int64)
+    return sigma, tau, tpos
+
+
+def modinv(sigma: int, N: int) -> int:
+    """sigma^{-1} mod N (sigma odd, N a power of two)."""
+    return pow(int(sigma), -1, int(N))
+
+
+# ---------------------------------------------------------------------------
+# Notation section: DFT with 1/N on the forward transform (Eq.(1)-(2)).
+# ---------------------------------------------------------------------------
+def dft_bruteforce(x: np.ndarray) -> np.ndarray:
+    """O(N^2) evaluation of Eq.(2): xhat_i = (1/N) sum_j x_j w^{ij}, w = e^{-2 pi i/N}."""
+    x = np.asarray(x, dtype=np.complex128)
+    N = x.shape[0]
+    jk = np.outer(np.arange(N), np.arange(N)) % N  # exact integer exponent
+    F = np.exp(-2j * np.pi * jk / N) / N
+    return F @ x
+
+
+def dft(x: np.ndarray) -> np.ndarray:
+    """Eq.(2) through a library FFT: numpy's forward FFT divided by N."""
+    x = np.asarray(x, dtype=np.complex128)
+    return np.fft.fft(x) / x.shape[0]
+
+
+# ---------------------------------------------------------------------------
+# Signal operations (Eq.(6)-(8)) as explicit matrices, for small N.
+# ---------------------------------------------------------------------------
+def shift_matrix(N: int, tau: int) -> np.ndarray:
+    """S_tau of Eq.(6): entry 1 where j - tau == k (mod N)."""
+    S = np.zeros((N, N))
+    for j in range(N):
+        S[j, (j - tau) % N] = 1.0
+    return S
+
+
+def scaling_matrix(N: int, sigma: int) -> np.ndarray:
+    """P_sigma of Eq.(7): entry 1 where sigma*j == k (mod N)."""
+    P = np.zeros((N, N))
+    for j in range(N):
+        P[j, (sigma * j) % N] = 1.0
+    return P
+
+
+def freqshift_matrix(N: int, b: int) -> np.ndarray:
+    """V_b of Eq.(8): diagonal w^{b j}."""
+    j = np.arange(N)
+    return np.diag(np.exp(-2j * np.pi * ((b * j) % N) / N))
+
+
+def permute(x: np.ndarray, sigma: int, tau: int) -> np.ndarray:
+    """x'_i = x_{(sigma*i + tau) mod N}: scaling then shifting of the time index.
+    (Eq.(9) family with no frequency offset; tau here equals -sigma*tau_paper.)"""
+    N = x.shape[0]
+    i = np.arange(N, dtype=np.int64)
+    return x[(sigma * i + tau) % N]
+
+
+# ---------------------------------------------------------------------------
+# Flat filter (flat-filter section, Eq.(12)-(13)).
+# ---------------------------------------------------------------------------
+def flat_window(w: int, B: int, c_g: float = C_G) -> np.ndarray:
+    """g_n for n in [0, w): Gaussian (Eq.(13)) times sinc (Eq.(12)), both centred
+    at n = w/2.
+
+    Eq.(12) is printed with its argument garbled; its centre value 1/B fixes the
+    reading sinc_B(t) = sin(pi t / B) / (pi t), sinc_B(0) = 1/B (a boxcar of
+    width N/B bins in frequency). The Gaussian std is tied to the window length
+    by the Fig. 1 example: s = w / (2 c_g).
+    """
+    n = np.arange(w, dtype=np.float64)
+    t = n - w / 2.0
+    s = w / (2.0 * c_g)
+    gauss = np.exp(-0.5 * (t / s) ** 2)
+    sinc = np.empty(w)
+    nz = t != 0
+    sinc[nz] = np.sin(np.pi * t[nz] / B) / (np.pi * t[nz])
+    sinc[~nz] = 1.0 / B
+    return gauss * sinc
+
+
+def gain_table(g: np.ndarray, N: int, B: int) -> np.ndarray:
+    """Gtab[o] = sum_n g_n e^{+2 pi i n o / N} for o in [-N/2B, N/2B), as an array
+    indexed by o + N/2B; exact FP64 sum with the exponent reduced mod N in integers.
+
+    This is N * ghat_{-o}: the weight with which a frequency sitting o bins away
+    from its bucket centre lands in that bucket (convolution theorem Eq.(4),
+    composition of a bucket Eq.(14))."""
+    M = N // B
+    w = g.shape[0]
+    out = np.empty(M, dtype=np.complex128)
+    n = np.arange(w, dtype=np.int64)
+    for k, o in enumerate(range(-M // 2, M // 2)):
+        m = (n * o) % N
+        out[k] = np.sum(g * np.exp(2j * np.pi * m / N))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Bucket hash (flat-filter example: bucket = round(f / (N/B)), 64/128 -> 1).
+# ---------------------------------------------------------------------------
+def bucket_of(p, N: int, B: int):
+    """Bucket of permuted frequency p: round-half-up of p/(N/B), taken mod B
+    (the top half-bucket wraps to bucket 0)."""
+    M = N // B
+    return ((np.asarray(p, dtype=np.int64) + M // 2) // M) % B
+
+
+def offset_in_bucket(p, N: int, B: int):
+    """Signed distance o = p - h*(N/B) of permuted frequency p from the centre
+    of its bucket h, wrapped into [-N/2B, N/2B)."""
+    M = N // B
+    p = np.asarray(p, dtype=np.int64)
+    h = bucket_of(p, N, B)
+    return ((p - h * M + N // 2) % N) - N // 2
+
+
+# ---------------------------------------------------------------------------
+# Stage 1: bucketization through the flat filter.
+# ---------------------------------------------------------------------------
+def bucketize(x: np.ndarray, g: np.ndarray, sigma: int, tau: int, B: int) -> np.ndarray:
+    """One random bucketization.
+
+    y_i = g_i x_{(sigma i + tau) mod N} for i < w (window applied to the
+    permuted signal); u_b = sum over i == b (mod B) of y_i (aliasing, Eq.(11));
+    uhat = B-point DFT of u without the 1/N factor, so that for an isolated
+    frequency f, uhat[h] = Gtab[o] * xhat_f * e^{+2 pi i tau f / N}."""
+    N = x.shape[0]
+    w = g.shape[0]
+    i = np.arange(w, dtype=np.int64)
+    y = g * x[(sigma * i + tau) % N]
+    u = np.zeros(B, dtype=np.complex128)
+    np.add.at(u, i % B, y)
+    return np.fft.fft(u)
+
+
+def select_buckets(uhat: np.ndarray, dK: int):
+    """Indices of the dK largest |uhat|^2 (ties -> lower bucket index), sorted,
+    and the relative gap between the dK-th and (dK+1)-th energies."""
+    E = uhat.real ** 2 + uhat.imag ** 2
+    B = E.shape[0]
+    order = np.lexsort((np.arange(B), -E))
+    J = np.sort(order[:dK])
+    if dK < B:
+        e_in, e_out = E[order[dK - 1]], E[order[dK]]
+        margin = (e_in - e_out) / e_in if e_in > 0 else 0.0
+    else:
+        margin = math.inf
+    return J, float(margin)
+
+
+# ---------------------------------------------------------------------------
+# Stage 2a: location by probability and statistics (voting).
+# ---------------------------------------------------------------------------
+def vote_counts(J_list, sigma, N: int, B: int) -> np.ndarray:
+    """c_f = number of bucketizations r whose selected set J_r holds the bucket
+    of sigma_r f, for every frequency f in [0, N)."""
+    f = np.arange(N, dtype=np.int64)
+    c = np.zeros(N, dtype=np.int64)
+    for r, J in enumerate(J_list):
+        chosen = np.zeros(B, dtype=bool)
+        chosen[np.asarray(J, dtype=np.int64)] = True
+        c += chosen[bucket_of((int(sigma[r]) * f) % N, N, B)]
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Stage 2b: estimation by energy concentration, median over bucketizations.
+# ---------------------------------------------------------------------------
+def loop_estimates(I, uhat_list, sigma, tau, G, N: int, B: int) -> np.ndarray:
+    """e[r, k] = uhat_r[h] * e^{-2 pi i (tau_r f mod N)/N} / Gtab[o] for f = I[k]:
+    the bucket value divided by the filter gain at the frequency's offset, with
+    the shift phase of Eq.(9) removed."""
+    M = N // B
+    I = np.asarray(I, dtype=np.int64)
+    L = len(uhat_list)
+    e = np.empty((L, I.shape[0]), dtype=np.complex128)
+    for r in range(L):
+        p = (int(sigma[r]) * I) % N
+        h = bucket_of(p, N, B)
+        o = offset_in_bucket(p, N, B)
+        phase = np.exp(-2j * np.pi * ((int(tau[r]) * I) % N) / N)
+        e[r] = uhat_list[r][h] * phase / G[o + M // 2]
+    return e
+
+
+def median_combine(e: np.ndarray) -> np.ndarray:
+    """Coordinate-wise median over bucketizations (mean of the two middle values
+    when the count is even)."""
+    return np.median(e.real, axis=0) + 1j * np.median(e.imag, axis=0)
+
+
+def finalize(I, v, K: int):
+    """K candidates of largest |v|^2 (ties -> lower frequency), ascending by
+    frequency, padded with (-1, 0) when fewer than K candidates exist.
+    Also returns the relative gap between the K-th and (K+1)-th |v|^2."""
+    I = np.asarray(I, dtype=np.int64)
+    mag = v.real ** 2 + v.imag ** 2
+    order = np.lexsort((I, -mag))
+    top = order[:K]
+    sel = np.argsort(I[top], kind="stable")
+    idx = np.full(K, -1, dtype=np.int64)
+    val = np.zeros(K, dtype=np.complex128)
+    n = top.shape[0]
+    idx[:n] = I[top][sel]
+    val[:n] = v[top][sel]
+    if I.shape[0] > K:
+        a, b = mag[order[K - 1]], mag[order[K]]
+        margin = (a - b) / a if a > 0 else 0.0
+    else:
+        margin = math.inf
+    return idx, val, float(margin)
+
+
+# ---------------------------------------------------------------------------
+# Formula method (Eq.(2) inverted for the K known frequencies): residual energy.
+# ---------------------------------------------------------------------------
+def residual_energy(x: np.ndarray, idx, val, tpos):
+    """(E_res, E_in) over time positions tpos:
+    E_res = mean_t |x_t - sum_k v_k e^{+2 pi i (t f_k mod N)/N}|^2,
+    E_in = mean_t |x_t|^2. Padding entries (idx < 0) are ignored."""
+    x = np.asarray(x, dtype=np.complex128)
+    N = x.shape[0]
+    idx = np.asarray(idx, dtype=np.int64)
+    val = np.asarray(val, dtype=np.complex128)
+    keep = idx >= 0
+    f, v = idx[keep], val[keep]
+    t = np.asarray(tpos, dtype=np.int64)
+    xt = x[t]
+    if f.shape[0]:
+        m = np.outer(t, f) % N
+        model = (np.exp(2j * np.pi * m / N) * v[None, :]).sum(axis=1)
+    else:
+        model = np.zeros_like(xt)
+    d = xt - model
+    e_res = float(np.mean(d.real ** 2 + d.imag ** 2))
+    e_in = float(np.mean(xt.real ** 2 + xt.imag ** 2))
+    return e_res, e_in
+
+
+# ---------------------------------------------------------------------------
+# The whole path.
+# ---------------------------------------------------------------------------
+@dataclass
+class OracleResult:
+    idx: np.ndarray                  # int64[K], ascending, -1 padded
+    val: np.ndarray                  # complex128[K], 0 padded
+    e_res: float = 0.0
+    e_in: float = 0.0
+    trace: dict = field(default_factory=dict)
+
+
+def check_params(N, K, B, L, w, d=2):
+    def pow2(v):
+        return v > 0 and (v & (v - 1)) == 0
+    if not (pow2(N) and 16 <= N <= (1 << 30)):
+        raise ValueError("N must be a power of two in [16, 2^30]")
+    if not (pow2(B) and 2 <= B and N // B >= 2):
+        raise ValueError("B must be a power of two with N/B >= 2")
+    if not (K >= 1 and 1 <= d * K <= B):
+        raise ValueError("need 1 <= d*K <= B")
+    if not (1 <= L <= 32):
+        raise ValueError("L must be in [1, 32]")
+    if not (2 <= w <= N and w % 2 == 0):
+        raise ValueError("w must be even and in [2, N]")
+
+
+def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
+         T: int | None = None, c_g: float = C_G, sigma=None, tau=None,
+         n_resid: int = 4096, tpos=None) -> OracleResult:
+    """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout."""
+    x = np.asarray(x, dtype=np.complex128)
+    N = x.shape[0]
+    check_params(N, K, B, L, w, d)
+    if T is None:
+        T = L // 2 + 1                       # strict majority of the L votes
+    if sigma is None:
+        sigma, tau, tp = draw_permutations(N, L, seed, n_resid)
+        if tpos is None:
+            tpos = tp
+    sigma = np.asarray(sigma, dtype=np.int64)
+    tau = np.asarray(tau, dtype=np.int64)
+    if tpos is None:
+        tpos = np.zeros(0, dtype=np.int64)
+    sigma_inv = np.array([modinv(s, N) for s in sigma], dtype=np.int64)
+
+    g = flat_window(w, B, c_g)
+    G = gain_table(g, N, B)
+    uhat = [bucketize(x, g, int(sigma[r]), int(tau[r]), B) for r in range(L)]
+    sel = [select_buckets(u, d * K) for u in uhat]
+    J = [s[0] for s in sel]
+    counts = vote_counts(J, sigma, N, B)
+    I = np.nonzero(counts >= T)[0].astype(np.int64)
+    e = loop_estimates(I, uhat, sigma, tau, G, N, B)
+    v = median_combine(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
+    idx, val, fmargin = finalize(I, v, K)
+    e_res, e_in = residual_energy(x, idx, val, tpos) if len(tpos) else (0.0, 0.0)
+    trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,
+                 J=J, select_margin=[s[1] for s in sel], counts=counts, I=I,
+                 e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos))
+    return OracleResult(idx=idx, val=val, e_res=e_res, e_in=e_in, trace=trace)
+
+
+# ---------------------------------------------------------------------------
+# Error metrics of the experimental platform (L0 / L1 / L2 against the best
+# K-term approximation) and the approximation factor of Eq.(5).
+# ---------------------------------------------------------------------------
+def best_k_term(xhat: np.ndarray, K: int):
+    """Support and values of the K largest |xhat| (ties -> lower index)."""
+    mag = np.abs(xhat)
+    order = np.lexsort((np.arange(xhat.shape[0]), -mag))[:K]
+    order = np.sort(order)
+    return order.astype(np.int64), xhat[order]
+
+
+def recovery_errors(xhat: np.ndarray, idx, val, K: int) -> dict:
+    """L0 = best-support frequencies missed; L1 = (1/K) sum of |error| over the
+    union of supports; L2 = l2 error over that union; C = the Eq.(5) ratio
+    ||xhat - x'||_2 / ||xhat - yhat||_2 (inf when the best K-term error is 0)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    val = np.asarray(val, dtype=np.complex128)
+    keep = idx >= 0
+    idx, val = idx[keep], val[keep]
+    bsup, bval = best_k_term(xhat, K)
+    rec = dict(zip(idx.tolist(), val.tolist()))
+    best = dict(zip(bsup.tolist(), bval.tolist()))
+    union = sorted(set(rec) | set(best))
+    diffs = np.array([rec.get(f, 0.0) - best.get(f, 0.0) for f in union], dtype=np.complex128)
+    L0 = len(set(best) - set(rec))
+    L1 = float(np.sum(np.abs(diffs)) / K)
+    L2 = float(np.sqrt(np.sum(np.abs(diffs) ** 2)))
+    xp = np.zeros_like(xhat)
+    xp[idx] = val
+    num = float(np.linalg.norm(xhat - xp))
+    yp = np.zeros_like(xhat)
+    yp[bsup] = bval
+    den = float(np.linalg.norm(xhat - yp))
+    C = num / den if den > 0 else (0.0 if num == 0 else math.inf)
+    return dict(L0=L0, L1=L1, L2=L2, C=C)
+
+
+def sampled_fraction(N: int, w: int, sigma, tau) -> float:
+    """Fraction of the N time samples read by the L bucketizations."""
+    hit = np.zeros(N, dtype=bool)
+    i = np.arange(w, dtype=np.int64)
+    for s, t in zip(sigma, tau):
+        hit[(int(s) * i + int(t)) % N] = True
+    return float(hit.mean())
