@@ -1,0 +1,230 @@
+/*
+ * sfft.h - C ABI of the MI355X (gfx950) flat-window voting sparse FFT.
+ *
+ * The library recovers the K largest Fourier coefficients of a length-N
+ * complex64 signal x with the sFFT1.0 method of Table 1 of "Empirical
+ * Evaluation of Typical Sparse Fast Fourier Transform Algorithms"
+ * (arXiv 2012.08238): flat filter, probability-and-statistics (voting)
+ * location, energy-concentration estimation, voting framework. Per random
+ * bucketization r < L it permutes the time index (i -> sigma_r*i + tau_r mod N,
+ * Eq.(6)-(7), spectrum identity Eq.(9)), windows w samples with the flat
+ * filter (sinc Eq.(12) x Gaussian Eq.(13)), aliases them into B buckets
+ * (Eq.(11)) and takes a B-point FFT; the d*K largest buckets vote for the
+ * frequencies they hash, frequencies with at least T votes are estimated from
+ * their buckets (median over the L bucketizations) and the K largest are
+ * returned. An optional FP64 residual (formula method, Eq.(2)) checks the
+ * result on S seeded time samples.
+ *
+ * Conventions
+ *  - The forward DFT carries 1/N (Eq.(2)): a unit-magnitude tone in x returns
+ *    a value of magnitude ~1.
+ *  - N and B are powers of two, 16 <= N <= 2^30, N/B >= 2, 1 <= d*K <= B,
+ *    1 <= L <= 32, w even with 2 <= w <= N, K <= 4096. Anything else returns
+ *    SFFT_E_INVALID synchronously and changes nothing.
+ *  - "Device" pointers are HIP device memory on the plan's device; "host"
+ *    pointers are ordinary host memory. complex64 is two packed floats
+ *    (re, im), complex128 two packed doubles.
+ *  - Outputs: out_idx int64[K] ascending frequency indices, padded with -1;
+ *    out_val complex64[K] matching values, padded with 0.
+ *  - Every call that launches GPU work is asynchronous on the given stream
+ *    (NULL = the default stream) and never synchronises the host; results are
+ *    valid once that stream has reached the call.
+ *  - No exception crosses the ABI. Errors return a negative sfft_status; the
+ *    message of the last error on the calling thread is sfft_last_error().
+ *    A HIP error observed by a call is reported as SFFT_E_DEVICE by that call.
+ *  - The library is deterministic: the same plan and input give bitwise the
+ *    same output, alone or inside a batch.
+ */
+#ifndef SFFT_MI355X_H
+#define SFFT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfft_plan_s* sfft_plan_t;     /* owns device tables + one workspace */
+typedef struct sfft_batch_s* sfft_batch_t;   /* owns per-signal workspaces + a HIP graph */
+typedef struct sfft_server_s* sfft_server_t; /* owns queue, plan cache, streams */
+typedef void* sfft_stream_t;                 /* a hipStream_t */
+
+typedef enum {
+    SFFT_OK = 0,
+    SFFT_E_INVALID = -1,     /* bad argument or parameter set */
+    SFFT_E_NOMEM = -2,       /* device or host allocation failed */
+    SFFT_E_DEVICE = -3,      /* a HIP call failed (including sticky errors of earlier work) */
+    SFFT_E_UNSUPPORTED = -4, /* valid request this build does not implement */
+    SFFT_E_BUSY = -5,        /* plan still executing on another stream; or server full */
+    SFFT_E_NOTFOUND = -6     /* unknown ticket */
+} sfft_status;
+
+/* Plan flags. */
+#define SFFT_FLAG_NO_RESIDUAL 0x1u  /* skip the FP64 residual step */
+#define SFFT_FLAG_FOLD_GATHER 0x2u  /* force the gather form of the bucketization */
+#define SFFT_FLAG_FOLD_STRIP  0x4u  /* force the streamed column-strip form */
+
+/* Full parameter set. Fill with sfft_params_init() and then override fields. */
+typedef struct {
+    int64_t N;              /* signal length, power of two */
+    int32_t K;              /* number of coefficients returned */
+    int32_t B;              /* number of buckets per bucketization, power of two */
+    int32_t L;              /* number of random bucketizations (loops) */
+    int32_t d;              /* buckets kept per loop = d*K (the location method keeps 2K: d = 2) */
+    int64_t w;              /* flat window length (time support), even */
+    uint64_t seed;          /* SplitMix64 seed of sigma_r, tau_r and the residual samples */
+    int32_t vote_threshold; /* T; 0 selects the strict majority floor(L/2)+1 */
+    int32_t n_resid;        /* S residual time samples; 0 selects 4096 */
+    double gauss_c;         /* window length / (2 * Gaussian std); 0 selects the Fig. 1 ratio 4.861870431316438 */
+    uint32_t flags;         /* SFFT_FLAG_* */
+    int32_t strip_cols;     /* tile width of the strip bucketization (power of two); 0 = automatic */
+    const uint32_t* sigma;  /* optional host uint32[L]: explicit odd scalings (NULL = draw from seed) */
+    const uint32_t* tau;    /* optional host uint32[L]: explicit shifts; required iff sigma is given */
+} sfft_params;
+
+/* Resolved plan description (what the plan actually runs). */
+typedef struct {
+    int64_t N, w;
+    int32_t K, B, L, d, T, n_resid;
+    int32_t fold_mode;      /* 0 = gather, 1 = strip */
+    int32_t strip_cols;
+    int64_t cand_cap;       /* capacity of the candidate list = (L-T+1)*d*K*N/B */
+    size_t table_bytes;     /* resident device tables */
+    size_t workspace_bytes; /* one execution's device workspace */
+    double sampled_fraction_expected; /* 1-(1-w/N)^L (Table 2, sFFT1.0 sampling, log N -> L) */
+} sfft_plan_desc;
+
+/* Host copies of one execution's intermediates (all pointers host, caller-owned,
+ * any may be NULL to skip). Sizes in elements. */
+typedef struct {
+    float* uhat;            /* float[2*L*B]: bucket spectra after the B-point FFT, [loop][bucket] (re, im) */
+    uint32_t* jbits;        /* uint32[L*B/32]: selected-bucket bitmaps, bit h of word h/32 of loop r */
+    uint32_t* jlist;        /* uint32[L*d*K]: selected buckets per loop, ascending */
+    uint32_t* cand;         /* uint32[cand_cap]: frequencies with >= T votes, unordered */
+    int64_t cand_count;     /* out: number of valid entries written to cand */
+} sfft_trace;
+
+/* ---- parameters and plans --------------------------------------------------------- */
+
+/* Fill *p with N, K, B, L, w and the defaults (d=2, seed=0, T=floor(L/2)+1,
+ * S=4096, Fig. 1 Gaussian ratio, no flags). Host only; no device work. */
+sfft_status sfft_params_init(sfft_params* p, int64_t N, int32_t K, int32_t B, int32_t L, int64_t w);
+
+/* Build a plan on the current HIP device: validates, draws sigma_r (odd) and
+ * tau_r from SplitMix64(seed) in the order sigma_0, tau_0, sigma_1, ...,
+ * followed by the S residual positions; inverts sigma_r mod N; builds the flat
+ * window (Eq.(12) x Eq.(13), FP64), the gain table
+ * Gtab[o] = sum_n g_n e^{+2 pi i n o/N}, o in [-N/2B, N/2B) (FP64; Eq.(14)),
+ * FFT twiddles and FP64 residual phase tables; uploads them and allocates one
+ * workspace. Synchronous (the only host->device crossing of the plan). */
+sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int32_t K, int32_t B, int32_t L, int64_t w);
+sfft_status sfft_plan_ex(sfft_plan_t* out, const sfft_params* p);
+
+/* Release a plan. Waits for the plan's in-flight work first. */
+sfft_status sfft_destroy(sfft_plan_t p);
+
+/* Host copies of sigma_r, sigma_r^{-1} mod N and tau_r (uint32[L] each; any may be NULL). */
+sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau);
+
+/* Resolved description of the plan. */
+sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out);
+
+/* Host-only build of the plan's FP64 tables without any device (for checking
+ * the host logic): sigma, sigma_inv, tau uint32[L]; tpos uint32[S];
+ * window double[w]; gain double[2*(N/B)] as (re, im) pairs for
+ * o = -N/2B .. N/2B-1. Any pointer may be NULL. */
+sfft_status sfft_host_tables(const sfft_params* p, uint32_t* sigma, uint32_t* sigma_inv,
+                             uint32_t* tau, uint32_t* tpos, double* window, double* gain);
+
+/* ---- execution -------------------------------------------------------------------- */
+
+/* Run the whole path on x_dev (device complex64[N], read only during the call)
+ * into out_idx (device int64[K]) and out_val (device complex64[K]).
+ * Asynchronous on `stream`. Returns SFFT_E_BUSY if the plan's previous
+ * execution was issued on a different stream and has not finished. */
+sfft_status sfft_execute(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val,
+                         sfft_stream_t stream);
+
+/* As sfft_execute, and also writes out_resid (device double[2], may be NULL):
+ * [0] = mean_t |x_t - sum_k v_k e^{+2 pi i t f_k/N}|^2, [1] = mean_t |x_t|^2 over the
+ * S residual samples, computed in FP64 (formula method). */
+sfft_status sfft_execute_ex(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val,
+                            double* out_resid, sfft_stream_t stream);
+
+/* Synchronously copy the intermediates of the plan's last execution to host
+ * buffers (waits for that execution). For parity checking. */
+sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t);
+
+/* ---- batches (uneven sizes, one HIP graph) ------------------------------------------ */
+
+/* A batch of n signals, signal i run with plans[i] (plans may repeat: each
+ * signal gets its own workspace). The sequence of batched launches is captured
+ * into one HIP graph on first run and replayed afterwards. The plans must
+ * outlive the batch. */
+sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32_t n);
+
+/* Run the batch: x_dev[i] device complex64[N_i]; out_idx[i] device int64[K_i];
+ * out_val[i] device complex64[K_i]; out_resid NULL or an array of n device
+ * double[2] (entries may be NULL). Asynchronous on `stream`; a batch runs one
+ * call at a time (SFFT_E_BUSY while its previous run is unfinished on another
+ * stream). Each signal's result is bitwise the one sfft_execute gives alone. */
+sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx,
+                           void* const* out_val, double* const* out_resid, sfft_stream_t stream);
+sfft_status sfft_batch_destroy(sfft_batch_t b);
+
+/* One-shot convenience: create, run once, destroy (the graph is not kept). */
+sfft_status sfft_execute_batch(const sfft_plan_t* plans, const void* const* x_dev,
+                               int64_t* const* out_idx, void* const* out_val,
+                               double* const* out_resid, int32_t n, sfft_stream_t stream);
+
+/* ---- serving ---------------------------------------------------------------------- */
+
+typedef struct {
+    uint64_t submitted, completed, rejected, failed;
+    uint64_t batches;           /* GPU launches of batches */
+    double p50_latency_s, p99_latency_s, mean_latency_s;
+    size_t hbm_in_use, hbm_peak; /* admitted workspace + resident plan bytes */
+    uint64_t plan_cache_hits, plan_cache_misses, plan_cache_evictions;
+} sfft_server_stats;
+
+/* Serving loop: a worker thread admits submitted requests while their HBM
+ * footprint (workspace, plus plan tables when not resident) fits in
+ * hbm_budget_bytes and fewer than max_inflight requests are on the GPU, forms
+ * batches from what is admitted (continuous batching: requests arriving while
+ * others run join the next batch), and runs batches on n_streams streams so
+ * that they overlap. Plans are cached by parameter set and kept resident. */
+sfft_status sfft_server_create(sfft_server_t* out, size_t hbm_budget_bytes, int32_t max_inflight,
+                               int32_t n_streams);
+
+/* Queue one request. x_dev, out_idx, out_val (and out_resid, may be NULL) as in
+ * sfft_execute_ex; they must stay valid until the ticket completes. Returns
+ * SFFT_E_INVALID for a bad parameter set (only this request is rejected) and
+ * SFFT_E_NOMEM if the request alone can never fit the budget. */
+sfft_status sfft_server_submit(sfft_server_t s, const sfft_params* p, const void* x_dev,
+                               int64_t* out_idx, void* out_val, double* out_resid, uint64_t* ticket);
+
+/* Non-blocking status of a ticket: *done = 1 when its outputs are complete on
+ * the device; *latency_s = completion - submission time; *req_status the
+ * request's own status. A completed ticket can be polled until it is released. */
+sfft_status sfft_server_poll(sfft_server_t s, uint64_t ticket, int32_t* done, double* latency_s,
+                             int32_t* req_status);
+
+/* Block until the ticket completes, then as sfft_server_poll, and forget it. */
+sfft_status sfft_server_wait(sfft_server_t s, uint64_t ticket, double* latency_s, int32_t* req_status);
+
+sfft_status sfft_server_stats_get(sfft_server_t s, sfft_server_stats* out);
+
+/* Drain all work and release everything. */
+sfft_status sfft_server_destroy(sfft_server_t s);
+
+/* ---- misc ------------------------------------------------------------------------- */
+
+const char* sfft_status_string(sfft_status s);
+const char* sfft_last_error(void);
+const char* sfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFFT_MI355X_H */

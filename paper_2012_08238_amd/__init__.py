@@ -1,0 +1,250 @@
+"""MI355X (gfx950) flat-window voting sparse FFT.
+
+Thin Python binding of the C ABI declared in ``include/sfft.h``: argument
+marshalling only. Every step of the transform runs in the HIP kernels of
+``libsfft_mi355x.so``; torch supplies device memory and streams. There is no
+CPU fallback: if the library has not been built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _capi
+from ._capi import (SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, SFFT_FLAG_NO_RESIDUAL,  # noqa: F401
+                    SfftError, check, load)
+
+__all__ = ["PlanParams", "Plan", "Batch", "Server", "host_tables", "load", "SfftError",
+           "SFFT_FLAG_FOLD_GATHER", "SFFT_FLAG_FOLD_STRIP", "SFFT_FLAG_NO_RESIDUAL"]
+
+
+@dataclass
+class PlanParams:
+    N: int
+    K: int
+    B: int
+    L: int
+    w: int
+    seed: int = 0
+    d: int = 2
+    vote_threshold: int = 0
+    n_resid: int = 0
+    gauss_c: float = 0.0
+    flags: int = 0
+    strip_cols: int = 0
+    sigma: np.ndarray | None = None
+    tau: np.ndarray | None = None
+
+    def to_c(self):
+        """Return (Params struct, keep-alive list)."""
+        lib = load()
+        p = _capi.Params()
+        check(lib.sfft_params_init(C.byref(p), self.N, self.K, self.B, self.L, self.w), "sfft_params_init")
+        p.seed = self.seed & ((1 << 64) - 1)
+        p.d = self.d
+        p.vote_threshold = self.vote_threshold
+        p.n_resid = self.n_resid
+        p.gauss_c = self.gauss_c
+        p.flags = self.flags
+        p.strip_cols = self.strip_cols
+        keep = []
+        if self.sigma is not None:
+            s = np.ascontiguousarray(self.sigma, dtype=np.uint32)
+            t = np.ascontiguousarray(self.tau, dtype=np.uint32)
+            keep += [s, t]
+            p.sigma = s.ctypes.data_as(C.POINTER(C.c_uint32))
+            p.tau = t.ctypes.data_as(C.POINTER(C.c_uint32))
+        return p, keep
+
+
+def _ptr(a) -> int:
+    return 0 if a is None else int(a.data_ptr())
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def host_tables(params: PlanParams) -> dict:
+    """FP64 host tables of a plan, built without a device (sfft_host_tables)."""
+    lib = load()
+    p, keep = params.to_c()
+    L, w, M = params.L, params.w, params.N // params.B
+    S = 0 if params.flags & SFFT_FLAG_NO_RESIDUAL else (params.n_resid or 4096)
+    out = dict(sigma=np.zeros(L, np.uint32), sigma_inv=np.zeros(L, np.uint32), tau=np.zeros(L, np.uint32),
+               tpos=np.zeros(max(S, 1), np.uint32), window=np.zeros(w, np.float64),
+               gain=np.zeros(2 * M, np.float64))
+    check(lib.sfft_host_tables(C.byref(p), *(out[k].ctypes.data for k in
+                                             ("sigma", "sigma_inv", "tau", "tpos", "window", "gain"))),
+          "sfft_host_tables")
+    out["tpos"] = out["tpos"][:S]
+    out["gain"] = out["gain"][0::2] + 1j * out["gain"][1::2]
+    del keep
+    return out
+
+
+class Plan:
+    """A resident plan: device tables + one workspace on the current device."""
+
+    def __init__(self, N: int, K: int, B: int, L: int, w: int, **kw):
+        self.params = PlanParams(N, K, B, L, w, **kw)
+        lib = load()
+        p, keep = self.params.to_c()
+        h = C.c_void_p()
+        check(lib.sfft_plan_ex(C.byref(h), C.byref(p)), "sfft_plan_ex")
+        self._h = h
+        del keep
+        self.desc = self.describe()
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def describe(self) -> dict:
+        d = _capi.PlanDesc()
+        check(load().sfft_plan_describe(self._h, C.byref(d)), "sfft_plan_describe")
+        return {f: getattr(d, f) for f, _ in _capi.PlanDesc._fields_}
+
+    def perms(self):
+        L = self.params.L
+        s, si, t = (np.zeros(L, np.uint32) for _ in range(3))
+        check(load().sfft_plan_get_perms(self._h, s.ctypes.data, si.ctypes.data, t.ctypes.data),
+              "sfft_plan_get_perms")
+        return s, si, t
+
+    def outputs(self, device=None):
+        import torch
+        K = self.params.K
+        idx = torch.empty(K, dtype=torch.int64, device=device or "cuda")
+        val = torch.empty(K, dtype=torch.complex64, device=device or "cuda")
+        res = torch.empty(2, dtype=torch.float64, device=device or "cuda")
+        return idx, val, res
+
+    def execute(self, x, out_idx, out_val, out_resid=None, stream=None) -> None:
+        """Asynchronous execution on `stream` (default: torch's current stream)."""
+        import torch
+        if x.dtype != torch.complex64 or not x.is_cuda or x.numel() != self.params.N or not x.is_contiguous():
+            raise ValueError("x must be a contiguous complex64 CUDA tensor of length N")
+        check(load().sfft_execute_ex(self._h, _ptr(x), _ptr(out_idx), _ptr(out_val), _ptr(out_resid),
+                                     _stream_handle(stream)), "sfft_execute_ex")
+
+    def __call__(self, x, stream=None, residual: bool = False):
+        idx, val, res = self.outputs(x.device)
+        self.execute(x, idx, val, res, stream)
+        return (idx, val, res) if residual else (idx, val)
+
+    def trace(self) -> dict:
+        """Host copies of the last execution's intermediates (synchronous)."""
+        d = self.desc
+        L, B, dK, cap = d["L"], d["B"], d["d"] * d["K"], d["cand_cap"]
+        wpl = (B + 31) // 32
+        uh = np.zeros(2 * L * B, np.float32)
+        jb = np.zeros(L * wpl, np.uint32)
+        jl = np.zeros(L * dK, np.uint32)
+        cd = np.zeros(max(cap, 1), np.uint32)
+        t = _capi.Trace(uh.ctypes.data_as(C.POINTER(C.c_float)), jb.ctypes.data_as(C.POINTER(C.c_uint32)),
+                        jl.ctypes.data_as(C.POINTER(C.c_uint32)), cd.ctypes.data_as(C.POINTER(C.c_uint32)), 0)
+        check(load().sfft_plan_read_trace(self._h, C.byref(t)), "sfft_plan_read_trace")
+        uhat = (uh[0::2] + 1j * uh[1::2]).reshape(L, B)
+        return dict(uhat=uhat, jbits=jb.reshape(L, wpl), jlist=jl.reshape(L, dK),
+                    cand=cd[:t.cand_count].copy())
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            check(load().sfft_destroy(self._h), "sfft_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(vals):
+    arr = (C.c_void_p * len(vals))()
+    for i, v in enumerate(vals):
+        arr[i] = v
+    return arr
+
+
+class Batch:
+    """Uneven batch of signals run as one HIP graph of batched launches."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        hs = _ptr_array([p.handle.value for p in self.plans])
+        h = C.c_void_p()
+        check(load().sfft_batch_create(C.byref(h), hs, len(self.plans)), "sfft_batch_create")
+        self._h = h
+
+    def run(self, xs, idxs, vals, resids=None, stream=None) -> None:
+        n = len(self.plans)
+        if not (len(xs) == len(idxs) == len(vals) == n):
+            raise ValueError("one x, idx and val per plan")
+        xa = _ptr_array([_ptr(x) for x in xs])
+        ia = _ptr_array([_ptr(i) for i in idxs])
+        va = _ptr_array([_ptr(v) for v in vals])
+        ra = _ptr_array([_ptr(r) for r in resids]) if resids is not None else None
+        check(load().sfft_batch_run(self._h, xa, ia, va, ra, _stream_handle(stream)), "sfft_batch_run")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            check(load().sfft_batch_destroy(self._h), "sfft_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over the C ABI (continuous batching, HBM admission)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 64, n_streams: int = 2):
+        h = C.c_void_p()
+        check(load().sfft_server_create(C.byref(h), hbm_budget_bytes, max_inflight, n_streams),
+              "sfft_server_create")
+        self._h = h
+
+    def submit(self, params: PlanParams, x, out_idx, out_val, out_resid=None) -> int:
+        p, keep = params.to_c()
+        t = C.c_uint64()
+        check(load().sfft_server_submit(self._h, C.byref(p), _ptr(x), _ptr(out_idx), _ptr(out_val),
+                                        _ptr(out_resid), C.byref(t)), "sfft_server_submit")
+        del keep
+        return t.value
+
+    def poll(self, ticket: int):
+        done, lat, st = C.c_int32(), C.c_double(), C.c_int32()
+        check(load().sfft_server_poll(self._h, ticket, C.byref(done), C.byref(lat), C.byref(st)),
+              "sfft_server_poll")
+        return bool(done.value), lat.value, st.value
+
+    def wait(self, ticket: int):
+        lat, st = C.c_double(), C.c_int32()
+        check(load().sfft_server_wait(self._h, ticket, C.byref(lat), C.byref(st)), "sfft_server_wait")
+        return lat.value, st.value
+
+    def stats(self) -> dict:
+        s = _capi.ServerStats()
+        check(load().sfft_server_stats_get(self._h, C.byref(s)), "sfft_server_stats_get")
+        return {f: getattr(s, f) for f, _ in _capi.ServerStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            check(load().sfft_server_destroy(self._h), "sfft_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,270 @@
+// Batches of uneven signals: every stage is launched once over all signals of
+// the batch (workgroup -> signal through a per-launch prefix array), and the
+// launch sequence is captured once into a HIP graph and replayed.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "host.hpp"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace sfft;
+
+namespace {
+
+enum StepKind { kFold = 0, kFft = 1, kVote = 2, kFin = 3, kRes = 4 };
+
+struct Step {
+    StepKind kind;
+    uint32_t param;   // fold mode / log2B / lmax / vote staged flag
+    uint32_t units;
+    uint32_t lds;
+    size_t prefix_off;  // index into the prefix array of n+1 entries
+};
+
+}  // namespace
+
+struct sfft_batch_s {
+    int device = 0;
+    int32_t n = 0;
+    std::vector<sfft_plan_t> plans;
+    char* d_ws = nullptr;
+    SigDesc* d_descs = nullptr;
+    IoDesc* d_ios = nullptr;
+    IoDesc* h_ios = nullptr;  // pinned staging of the per-run I/O pointers
+    uint32_t* d_prefix = nullptr;
+    std::vector<Step> steps;
+    std::vector<IoDesc> last_io;
+    bool io_valid = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+    size_t ws_bytes = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+void batch_free(sfft_batch_t b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->d_ws) (void)hipFree(b->d_ws);
+    if (b->d_descs) (void)hipFree(b->d_descs);
+    if (b->d_ios) (void)hipFree(b->d_ios);
+    if (b->d_prefix) (void)hipFree(b->d_prefix);
+    if (b->h_ios) (void)hipHostFree(b->h_ios);
+    delete b;
+}
+
+sfft_status issue_steps(sfft_batch_t b, hipStream_t s) {
+    for (const Step& st : b->steps) {
+        Launch a{};
+        a.descs = b->d_descs;
+        a.ios = b->d_ios;
+        a.prefix = b->d_prefix + st.prefix_off;
+        a.nsig = (uint32_t)b->n;
+        hipError_t e = hipSuccess;
+        switch (st.kind) {
+            case kFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
+            case kFft: e = launch_fft_select(a, st.param, st.units, s); break;
+            case kVote: e = launch_vote(a, st.units, st.lds, s); break;
+            case kFin: e = launch_finalize(a, st.param, st.units, s); break;
+            case kRes: e = launch_residual(a, st.units, s); break;
+        }
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+    }
+    return SFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32_t n) {
+    if (!out || !plans || n < 1) return set_error(SFFT_E_INVALID, "need an output pointer and n >= 1 plans");
+    *out = nullptr;
+    for (int32_t i = 0; i < n; ++i)
+        if (!plans[i]) return set_error(SFFT_E_INVALID, "null plan in batch");
+    const int dev = plan_device(plans[0]);
+    for (int32_t i = 1; i < n; ++i)
+        if (plan_device(plans[i]) != dev) return set_error(SFFT_E_INVALID, "all plans of a batch must be on one device");
+    auto* b = new (std::nothrow) sfft_batch_s();
+    if (!b) return set_error(SFFT_E_NOMEM, "host allocation");
+    b->device = dev;
+    b->n = n;
+    b->plans.assign(plans, plans + n);
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "hipSetDevice");
+    }
+    // one workspace per signal
+    std::vector<size_t> ws_off(n);
+    size_t tot = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        ws_off[i] = tot;
+        tot += (workspace_layout(plan_resolved(plans[i])).total + 255) & ~size_t(255);
+    }
+    b->ws_bytes = tot;
+    if (hipMalloc(&b->d_ws, tot) != hipSuccess || hipMalloc(&b->d_descs, sizeof(SigDesc) * n) != hipSuccess ||
+        hipMalloc(&b->d_ios, sizeof(IoDesc) * n) != hipSuccess ||
+        hipHostMalloc(&b->h_ios, sizeof(IoDesc) * n, hipHostMallocDefault) != hipSuccess) {
+        batch_free(b);
+        return set_error(SFFT_E_NOMEM, "batch allocation");
+    }
+    e = hipMemset(b->d_ws, 0, tot);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "workspace clear");
+    }
+    std::vector<SigDesc> descs(n);
+    for (int32_t i = 0; i < n; ++i)
+        descs[i] = make_desc(plan_resolved(plans[i]), const_cast<char*>(plan_tables(plans[i])), b->d_ws + ws_off[i]);
+    e = hipMemcpy(b->d_descs, descs.data(), sizeof(SigDesc) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "descriptor upload");
+    }
+    // one launch per stage and variant, each with its own prefix over all n signals
+    std::vector<uint32_t> prefix;
+    auto add_step = [&](StepKind kind, uint32_t param, uint32_t lds, auto units_of) {
+        const size_t off = prefix.size();
+        uint32_t acc = 0;
+        prefix.push_back(0);
+        for (int32_t i = 0; i < n; ++i) {
+            acc += units_of(plan_resolved(plans[i]));
+            prefix.push_back(acc);
+        }
+        if (acc == 0) {
+            prefix.resize(off);
+            return;
+        }
+        b->steps.push_back(Step{kind, param, acc, lds, off});
+    };
+    for (uint32_t mode = 0; mode < 2; ++mode) {
+        uint32_t lds = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const Resolved& R = plan_resolved(plans[i]);
+            if (R.mode == mode && mode == 1) lds = std::max(lds, R.strip_lds);
+        }
+        add_step(kFold, mode, lds, [&](const Resolved& R) { return R.mode == mode ? R.fold_units : 0u; });
+    }
+    for (uint32_t lb = 1; lb <= 14; ++lb)
+        add_step(kFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
+    for (uint32_t staged = 0; staged < 2; ++staged) {
+        uint32_t lds = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const Resolved& R = plan_resolved(plans[i]);
+            if ((R.vote_lds > 0) == (staged == 1)) lds = std::max(lds, R.vote_lds);
+        }
+        add_step(kVote, staged, staged ? lds : 0,
+                 [&](const Resolved& R) { return ((R.vote_lds > 0) == (staged == 1)) ? R.vote_units : 0u; });
+    }
+    for (uint32_t lm = 4; lm <= 32; lm <<= 1)
+        add_step(kFin, lm, 0, [&](const Resolved& R) { return R.lmax == lm ? 1u : 0u; });
+    add_step(kRes, 0, 0, [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
+    if (hipMalloc(&b->d_prefix, prefix.size() * 4) != hipSuccess) {
+        batch_free(b);
+        return set_error(SFFT_E_NOMEM, "prefix allocation");
+    }
+    e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "batch setup");
+    }
+    b->last_io.resize(n);
+    *out = b;
+    return SFFT_OK;
+}
+
+sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx, void* const* out_val,
+                           double* const* out_resid, sfft_stream_t stream) {
+    if (!b || !x_dev || !out_idx || !out_val) return set_error(SFFT_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(b->mu);
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (b->launched && s != b->last_stream) {
+        const hipError_t q = hipEventQuery(b->done);
+        if (q == hipErrorNotReady) return set_error(SFFT_E_BUSY, "batch is executing on another stream");
+        if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    std::vector<IoDesc> io(b->n);
+    for (int32_t i = 0; i < b->n; ++i) {
+        if (!x_dev[i] || !out_idx[i] || !out_val[i]) return set_error(SFFT_E_INVALID, "null signal or output pointer");
+        if (reinterpret_cast<uintptr_t>(x_dev[i]) & 15u) return set_error(SFFT_E_INVALID, "x_dev must be 16-byte aligned");
+        io[i] = IoDesc{reinterpret_cast<const float2*>(x_dev[i]), out_idx[i], reinterpret_cast<float2*>(out_val[i]),
+                       out_resid ? out_resid[i] : nullptr};
+    }
+    const bool same = b->io_valid && memcmp(io.data(), b->last_io.data(), sizeof(IoDesc) * b->n) == 0;
+    if (!same) {
+        // the pinned staging buffer may still feed the previous run's copy
+        if (b->launched) {
+            e = hipEventSynchronize(b->done);
+            if (e != hipSuccess) return hip_fail(e, "wait for previous batch run");
+        }
+        memcpy(b->h_ios, io.data(), sizeof(IoDesc) * b->n);
+        e = hipMemcpyAsync(b->d_ios, b->h_ios, sizeof(IoDesc) * b->n, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "I/O descriptor upload");
+        b->last_io = io;
+        b->io_valid = true;
+    }
+    if (!b->exec) {
+        e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+        const sfft_status st = issue_steps(b, b->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != SFFT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture end");
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return hip_fail(e, "graph instantiate");
+        }
+    }
+    e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    e = hipEventRecord(b->done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    b->last_stream = s;
+    b->launched = true;
+    return SFFT_OK;
+}
+
+sfft_status sfft_batch_destroy(sfft_batch_t b) {
+    if (!b) return set_error(SFFT_E_INVALID, "null batch");
+    (void)hipSetDevice(b->device);
+    if (b->launched) (void)hipEventSynchronize(b->done);
+    batch_free(b);
+    return SFFT_OK;
+}
+
+sfft_status sfft_execute_batch(const sfft_plan_t* plans, const void* const* x_dev, int64_t* const* out_idx,
+                               void* const* out_val, double* const* out_resid, int32_t n, sfft_stream_t stream) {
+    sfft_batch_t b = nullptr;
+    sfft_status st = sfft_batch_create(&b, plans, n);
+    if (st != SFFT_OK) return st;
+    st = sfft_batch_run(b, x_dev, out_idx, out_val, out_resid, stream);
+    sfft_batch_destroy(b);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+// C ABI of the gfx950 sparse FFT: plans, single execution, batches, traces.
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "host.hpp"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace sfft {
+
+thread_local std::string g_last_error;
+
+sfft_status set_error(sfft_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+sfft_status hip_fail(hipError_t e, const char* what) {
+    return set_error(SFFT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+hipError_t init_kernel_attributes() {
+    static std::once_flag once;
+    static hipError_t status = hipSuccess;
+    std::call_once(once, [] { status = set_kernel_attributes_impl(); });
+    return status;
+}
+
+// Fill a device descriptor with the plan tables at `tab` and the workspace at `ws`.
+SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
+    const TabLayout t = table_layout(R);
+    const WsLayout w = workspace_layout(R);
+    SigDesc d{};
+    d.sigma = reinterpret_cast<const uint32_t*>(tab + t.sigma);
+    d.sigma_inv = reinterpret_cast<const uint32_t*>(tab + t.sigma_inv);
+    d.tau = reinterpret_cast<const uint32_t*>(tab + t.tau);
+    d.gT = reinterpret_cast<const float*>(tab + t.gT);
+    d.invG = reinterpret_cast<const float2*>(tab + t.invG);
+    d.tw = reinterpret_cast<const float2*>(tab + t.tw);
+    d.tpos = reinterpret_cast<const uint32_t*>(tab + t.tpos);
+    d.rt_hi = reinterpret_cast<const double2*>(tab + t.rt_hi);
+    d.rt_lo = reinterpret_cast<const double2*>(tab + t.rt_lo);
+    d.uhat = reinterpret_cast<float2*>(ws + w.uhat);
+    d.jbits = reinterpret_cast<uint32_t*>(ws + w.jbits);
+    d.jlist = reinterpret_cast<uint32_t*>(ws + w.jlist);
+    d.cand = reinterpret_cast<uint32_t*>(ws + w.cand);
+    d.est = reinterpret_cast<float2*>(ws + w.est);
+    d.keys = reinterpret_cast<uint64_t*>(ws + w.keys);
+    d.rpart = reinterpret_cast<double*>(ws + w.rpart);
+    d.resid_own = reinterpret_cast<double*>(ws + w.resid_own);
+    d.ctr = reinterpret_cast<uint32_t*>(ws + w.ctr);
+    d.N = R.N;
+    d.maskN = R.N - 1;
+    d.log2N = R.log2N;
+    d.B = R.B;
+    d.log2B = R.log2B;
+    d.M = R.M;
+    d.log2M = R.log2M;
+    d.L = R.L;
+    d.w = R.w;
+    d.Mw = R.Mw;
+    d.K = R.K;
+    d.dK = R.dK;
+    d.T = R.T;
+    d.S = R.S;
+    d.cap = R.cap;
+    d.rsh = R.rsh;
+    d.mode = R.mode;
+    d.C = R.C;
+    d.log2C = R.log2C;
+    d.strips = R.B / R.C;
+    d.vote_units = R.vote_units;
+    d.resid_blocks = R.resid_blocks;
+    d.lmax = R.lmax;
+    return d;
+}
+
+// Launch the five stages for one signal (nsig == 0 form of Launch).
+sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc& io, hipStream_t s) {
+    Launch a{};
+    a.descs = d_desc;
+    a.ios = nullptr;
+    a.prefix = nullptr;
+    a.nsig = 0;
+    a.one_io = io;
+    HIP_TRY(launch_fold(a, R.mode, R.fold_units, R.strip_lds, s), "bucketization launch");
+    HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
+    HIP_TRY(launch_vote(a, R.vote_units, R.vote_lds, s), "vote launch");
+    HIP_TRY(launch_finalize(a, R.lmax, 1, s), "estimate launch");
+    if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, s), "residual launch");
+    return SFFT_OK;
+}
+
+}  // namespace sfft
+
+using namespace sfft;
+
+// ------------------------------------------------------------------ plan object
+struct sfft_plan_s {
+    Resolved R;
+    int device = 0;
+    char* d_tab = nullptr;
+    char* d_ws = nullptr;
+    SigDesc* d_desc = nullptr;
+    size_t tab_bytes = 0, ws_bytes = 0;
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+    std::mutex mu;
+};
+
+namespace sfft {
+
+sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
+    if (!out) return set_error(SFFT_E_INVALID, "null output pointer");
+    *out = nullptr;
+    Resolved R;
+    std::string err;
+    sfft_status st = resolve_params(p, &R, &err);
+    if (st != SFFT_OK) return set_error(st, err);
+    HostTables T;
+    build_tables(R, &T);
+    auto* pl = new (std::nothrow) sfft_plan_s();
+    if (!pl) return set_error(SFFT_E_NOMEM, "host allocation");
+    pl->R = std::move(R);
+    const Resolved& Rr = pl->R;
+    auto cleanup = [&](sfft_status s) {
+        if (pl->d_tab) (void)hipFree(pl->d_tab);
+        if (pl->d_ws) (void)hipFree(pl->d_ws);
+        if (pl->d_desc) (void)hipFree(pl->d_desc);
+        if (pl->done) (void)hipEventDestroy(pl->done);
+        delete pl;
+        return s;
+    };
+    hipError_t e = hipGetDevice(&pl->device);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+    e = init_kernel_attributes();
+    if (e != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
+    const TabLayout tl = table_layout(Rr);
+    const WsLayout wl = workspace_layout(Rr);
+    pl->tab_bytes = tl.total;
+    pl->ws_bytes = wl.total;
+    if (hipMalloc(&pl->d_tab, tl.total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device tables"));
+    if (hipMalloc(&pl->d_ws, wl.total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device workspace"));
+    if (hipMalloc(&pl->d_desc, sizeof(SigDesc)) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device descriptor"));
+    std::vector<char> h(tl.total, 0);
+    memcpy(&h[tl.sigma], Rr.sigma.data(), Rr.L * 4);
+    memcpy(&h[tl.sigma_inv], Rr.sigma_inv.data(), Rr.L * 4);
+    memcpy(&h[tl.tau], Rr.tau.data(), Rr.L * 4);
+    if (Rr.S) memcpy(&h[tl.tpos], Rr.tpos.data(), (size_t)Rr.S * 4);
+    memcpy(&h[tl.gT], T.gT.data(), T.gT.size() * 4);
+    memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
+    memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
+    memcpy(&h[tl.rt_hi], T.rt_hi.data(), T.rt_hi.size() * 8);
+    memcpy(&h[tl.rt_lo], T.rt_lo.data(), T.rt_lo.size() * 8);
+    e = hipMemcpy(pl->d_tab, h.data(), tl.total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "table upload"));
+    e = hipMemset(pl->d_ws, 0, wl.total);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "workspace clear"));
+    const SigDesc d = make_desc(Rr, pl->d_tab, pl->d_ws);
+    e = hipMemcpy(pl->d_desc, &d, sizeof(SigDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "descriptor upload"));
+    e = hipEventCreateWithFlags(&pl->done, hipEventDisableTiming);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "event"));
+    *out = pl;
+    return SFFT_OK;
+}
+
+const Resolved& plan_resolved(sfft_plan_t p) { return p->R; }
+const char* plan_tables(sfft_plan_t p) { return p->d_tab; }
+int plan_device(sfft_plan_t p) { return p->device; }
+size_t plan_table_bytes(sfft_plan_t p) { return p->tab_bytes; }
+size_t plan_ws_bytes(sfft_plan_t p) { return p->ws_bytes; }
+
+}  // namespace sfft
+
+namespace {
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+sfft_status check_busy(sfft_plan_t p, hipStream_t s) {
+    if (p->launched && s != p->last_stream) {
+        const hipError_t q = hipEventQuery(p->done);
+        if (q == hipErrorNotReady) return set_error(SFFT_E_BUSY, "plan is executing on another stream");
+        if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    return SFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sfft_version(void) { return "sfft-mi355x 0.1 (gfx950)"; }
+
+const char* sfft_last_error(void) { return g_last_error.c_str(); }
+
+const char* sfft_status_string(sfft_status s) {
+    switch (s) {
+        case SFFT_OK: return "ok";
+        case SFFT_E_INVALID: return "invalid argument";
+        case SFFT_E_NOMEM: return "out of memory";
+        case SFFT_E_DEVICE: return "device error";
+        case SFFT_E_UNSUPPORTED: return "unsupported";
+        case SFFT_E_BUSY: return "busy";
+        case SFFT_E_NOTFOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+sfft_status sfft_params_init(sfft_params* p, int64_t N, int32_t K, int32_t B, int32_t L, int64_t w) {
+    if (!p) return set_error(SFFT_E_INVALID, "null params");
+    memset(p, 0, sizeof(*p));
+    p->N = N;
+    p->K = K;
+    p->B = B;
+    p->L = L;
+    p->w = w;
+    p->d = 2;
+    return SFFT_OK;
+}
+
+sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int32_t K, int32_t B, int32_t L, int64_t w) {
+    sfft_params p;
+    sfft_params_init(&p, N, K, B, L, w);
+    return plan_create(p, out);
+}
+
+sfft_status sfft_plan_ex(sfft_plan_t* out, const sfft_params* p) {
+    if (!p) return set_error(SFFT_E_INVALID, "null params");
+    return plan_create(*p, out);
+}
+
+sfft_status sfft_destroy(sfft_plan_t p) {
+    if (!p) return set_error(SFFT_E_INVALID, "null plan");
+    (void)hipSetDevice(p->device);
+    if (p->launched) (void)hipEventSynchronize(p->done);
+    (void)hipFree(p->d_tab);
+    (void)hipFree(p->d_ws);
+    (void)hipFree(p->d_desc);
+    (void)hipEventDestroy(p->done);
+    delete p;
+    return SFFT_OK;
+}
+
+sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau) {
+    if (!p) return set_error(SFFT_E_INVALID, "null plan");
+    const Resolved& R = p->R;
+    if (sigma) memcpy(sigma, R.sigma.data(), R.L * 4);
+    if (sigma_inv) memcpy(sigma_inv, R.sigma_inv.data(), R.L * 4);
+    if (tau) memcpy(tau, R.tau.data(), R.L * 4);
+    return SFFT_OK;
+}
+
+sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out) {
+    if (!p || !out) return set_error(SFFT_E_INVALID, "null argument");
+    const Resolved& R = p->R;
+    out->N = R.N;
+    out->w = R.w;
+    out->K = (int32_t)R.K;
+    out->B = (int32_t)R.B;
+    out->L = (int32_t)R.L;
+    out->d = (int32_t)R.d;
+    out->T = (int32_t)R.T;
+    out->n_resid = (int32_t)R.S;
+    out->fold_mode = (int32_t)R.mode;
+    out->strip_cols = (int32_t)R.C;
+    out->cand_cap = R.cap;
+    out->table_bytes = p->tab_bytes;
+    out->workspace_bytes = p->ws_bytes;
+    out->sampled_fraction_expected = 1.0 - pow(1.0 - (double)R.w / (double)R.N, (double)R.L);
+    return SFFT_OK;
+}
+
+sfft_status sfft_host_tables(const sfft_params* p, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau,
+                             uint32_t* tpos, double* window, double* gain) {
+    if (!p) return set_error(SFFT_E_INVALID, "null params");
+    Resolved R;
+    std::string err;
+    const sfft_status st = resolve_params(*p, &R, &err);
+    if (st != SFFT_OK) return set_error(st, err);
+    if (sigma) memcpy(sigma, R.sigma.data(), R.L * 4);
+    if (sigma_inv) memcpy(sigma_inv, R.sigma_inv.data(), R.L * 4);
+    if (tau) memcpy(tau, R.tau.data(), R.L * 4);
+    if (tpos && R.S) memcpy(tpos, R.tpos.data(), (size_t)R.S * 4);
+    if (window || gain) {
+        HostTables T;
+        build_tables(R, &T);
+        if (window) memcpy(window, T.window.data(), (size_t)R.w * 8);
+        if (gain)
+            for (uint32_t k = 0; k < R.M; ++k) {
+                gain[2 * k] = T.gain[k].real();
+                gain[2 * k + 1] = T.gain[k].imag();
+            }
+    }
+    return SFFT_OK;
+}
+
+sfft_status sfft_execute_ex(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val, double* out_resid,
+                            sfft_stream_t stream) {
+    if (!p || !x_dev || !out_idx || !out_val) return set_error(SFFT_E_INVALID, "null argument");
+    if (!aligned16(x_dev)) return set_error(SFFT_E_INVALID, "x_dev must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(out_val) & 7u) || (reinterpret_cast<uintptr_t>(out_idx) & 7u) ||
+        (reinterpret_cast<uintptr_t>(out_resid) & 7u))
+        return set_error(SFFT_E_INVALID, "outputs must be 8-byte aligned");
+    std::lock_guard<std::mutex> lk(p->mu);
+    HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    sfft_status st = check_busy(p, s);
+    if (st != SFFT_OK) return st;
+    HIP_TRY(hipGetLastError(), "earlier device work");
+    IoDesc io{reinterpret_cast<const float2*>(x_dev), out_idx, reinterpret_cast<float2*>(out_val), out_resid};
+    st = launch_single(p->R, p->d_desc, io, s);
+    if (st != SFFT_OK) return st;
+    HIP_TRY(hipEventRecord(p->done, s), "hipEventRecord");
+    p->last_stream = s;
+    p->launched = true;
+    return SFFT_OK;
+}
+
+sfft_status sfft_execute(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val, sfft_stream_t stream) {
+    return sfft_execute_ex(p, x_dev, out_idx, out_val, nullptr, stream);
+}
+
+sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t) {
+    if (!p || !t) return set_error(SFFT_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+    if (p->launched) HIP_TRY(hipEventSynchronize(p->done), "wait for execution");
+    const Resolved& R = p->R;
+    const WsLayout w = workspace_layout(R);
+    const size_t wpl = (R.B + 31) / 32;
+    if (t->uhat) HIP_TRY(hipMemcpy(t->uhat, p->d_ws + w.uhat, (size_t)R.L * R.B * 8, hipMemcpyDeviceToHost), "copy uhat");
+    if (t->jbits) HIP_TRY(hipMemcpy(t->jbits, p->d_ws + w.jbits, (size_t)R.L * wpl * 4, hipMemcpyDeviceToHost), "copy jbits");
+    if (t->jlist) HIP_TRY(hipMemcpy(t->jlist, p->d_ws + w.jlist, (size_t)R.L * R.dK * 4, hipMemcpyDeviceToHost), "copy jlist");
+    uint32_t ctr[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(ctr, p->d_ws + w.ctr, 16, hipMemcpyDeviceToHost), "copy counters");
+    const uint32_t n = std::min(ctr[0], R.cap);
+    t->cand_count = n;
+    if (t->cand && n) HIP_TRY(hipMemcpy(t->cand, p->d_ws + w.cand, (size_t)n * 4, hipMemcpyDeviceToHost), "copy candidates");
+    return SFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Shared host/device definitions of the gfx950 sparse-FFT path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfft {
+
+constexpr int kMaxL = 32;        // loops supported (bitmaps, median sorting network)
+constexpr int kMaxK = 4096;      // outputs supported (final sort in LDS)
+constexpr int kMaxFftLds = 16384;  // largest B transformed inside one workgroup's LDS
+
+// Per-signal execution descriptor: plan tables (read only, shared by every
+// execution of a plan) plus one workspace. Lives in device memory; kernels
+// read it through uniform (scalar) loads.
+struct SigDesc {
+    // plan tables
+    const uint32_t* sigma;      // [L] odd scalings
+    const uint32_t* sigma_inv;  // [L] inverses mod N
+    const uint32_t* tau;        // [L] shifts
+    const float* gT;            // [B][Mw] window, gT[b*Mw+m] = g[b + m*B] (0 beyond w)
+    const float2* invG;         // [M] 1/Gtab[o], o = -M/2 .. M/2-1
+    const float2* tw;           // [B] e^{-2 pi i m/B}
+    const uint32_t* tpos;       // [S] residual sample positions
+    const double2* rt_hi;       // [N >> rsh] e^{+2 pi i (hi << rsh)/N}
+    const double2* rt_lo;       // [1 << rsh] e^{+2 pi i lo/N}
+    // workspace
+    float2* uhat;               // [L][B] bucket values, then their B-point DFT
+    uint32_t* jbits;            // [L][B/32] selected buckets
+    uint32_t* jlist;            // [L][dK] selected buckets, ascending
+    uint32_t* cand;             // [cap] frequencies with >= T votes
+    float2* est;                // [cap] median estimates
+    uint64_t* keys;             // [cap] ordering keys of the estimates
+    double* rpart;              // [2 * resid_blocks] residual partial sums
+    double* resid_own;          // [2] residual when the caller gives no buffer
+    uint32_t* ctr;              // [4] counters: 0 candidates, 1 residual blocks done
+    // sizes
+    uint32_t N, maskN, log2N;
+    uint32_t B, log2B;
+    uint32_t M, log2M;          // M = N/B (bucket width in bins = rows of the strip view)
+    uint32_t L, w, Mw;          // Mw = ceil(w/B) window taps per bucket
+    uint32_t K, dK, T, S, cap, rsh;
+    uint32_t mode;              // 0 gather, 1 strip
+    uint32_t C, log2C, strips;  // strip bucketization tile: C columns x M rows
+    uint32_t vote_units;        // vote workgroups
+    uint32_t resid_blocks;      // residual workgroups
+    uint32_t lmax;              // power of two >= L used by the median network
+};
+
+// Per-signal caller buffers of one execution.
+struct IoDesc {
+    const float2* x;            // [N]
+    int64_t* out_idx;           // [K]
+    float2* out_val;            // [K]
+    double* out_resid;          // [2] or nullptr
+};
+
+// Kernel argument: either one signal (nsig == 0: desc = descs[0], io = one_io,
+// unit = blockIdx.x) or a batch (unit -> signal through prefix[0..nsig]).
+struct Launch {
+    const SigDesc* descs;
+    const IoDesc* ios;
+    const uint32_t* prefix;     // [nsig+1] exclusive prefix of units per signal
+    uint32_t nsig;
+    IoDesc one_io;
+};
+
+constexpr uint32_t kVoteNT = 256;
+constexpr uint32_t kVotePerThread = 16;
+constexpr uint32_t kVoteUnit = kVoteNT * kVotePerThread;  // candidates per vote workgroup
+constexpr uint32_t kFoldNT = 256;
+constexpr uint32_t kFftNT = 256;
+constexpr uint32_t kFinNT = 256;
+constexpr uint32_t kResNT = 256;
+constexpr uint32_t kStripLdsBytes = 65536;  // strip tile budget
+
+}  // namespace sfft

@@ -1,0 +1,86 @@
+// Host-side plan logic (pure C++, no device calls): parameter validation,
+// random permutations, FP64 window / gain / twiddle / phase tables.
+#pragma once
+
+#include <stdint.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+
+namespace sfft {
+
+// Every derived size of a validated parameter set.
+struct Resolved {
+    uint32_t N, K, B, L, d, w, T, S;
+    uint32_t dK, M, Mw, cap, rsh, lmax;
+    uint32_t log2N, log2B, log2M;
+    uint32_t mode, C, log2C;    // bucketization form (0 gather, 1 strip) and strip width
+    uint64_t seed;
+    double gauss_c;
+    uint32_t flags;
+    std::vector<uint32_t> sigma, sigma_inv, tau, tpos;
+    // units per stage
+    uint32_t fold_units, vote_units, resid_blocks, vote_lds, strip_lds;
+};
+
+struct HostTables {
+    std::vector<double> window;                 // g_n, n < w
+    std::vector<std::complex<double>> gain;     // Gtab[o], o = -M/2 .. M/2-1
+    std::vector<float> gT;                      // [B][Mw]
+    std::vector<float> invG;                    // [M] (re, im) pairs of 1/Gtab
+    std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
+    std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N} split on bits
+};
+
+constexpr double kDefaultGaussC = 4.861870431316438;  // 516 / (2 * 16 * sqrt(11)), Fig. 1 example
+
+// Validate p and derive every size. On failure returns a status and sets *err.
+sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err);
+
+// FP64 tables of a resolved plan (window, gain, and the float tables the GPU reads).
+void build_tables(const Resolved& R, HostTables* t);
+
+// SplitMix64 (Steele, Lea & Flood 2014): Weyl counter + xor-shift-multiply finaliser.
+struct SplitMix64 {
+    uint64_t state;
+    explicit SplitMix64(uint64_t seed) : state(seed) {}
+    uint64_t next() {
+        state += 0x9E3779B97F4A7C15ull;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+// Inverse of an odd a modulo 2^64 by Newton's iteration x <- x (2 - a x), which
+// doubles the number of correct low bits each step (a*a == 1 mod 8 for odd a).
+inline uint64_t inverse_mod_2_64(uint64_t a) {
+    uint64_t x = a;
+    for (int i = 0; i < 5; ++i) x *= 2ull - a * x;
+    return x;
+}
+
+inline bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+inline uint32_t ilog2(uint64_t v) {
+    uint32_t r = 0;
+    while ((1ull << r) < v) ++r;
+    return r;
+}
+
+// Device workspace layout of one execution (byte offsets, 256-aligned).
+struct WsLayout {
+    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, total;
+};
+WsLayout workspace_layout(const Resolved& R);
+
+// Device table layout (byte offsets into one allocation).
+struct TabLayout {
+    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rt_hi, rt_lo, total;
+};
+TabLayout table_layout(const Resolved& R);
+
+}  // namespace sfft

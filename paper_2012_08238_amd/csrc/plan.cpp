@@ -1,0 +1,243 @@
+// Host-side plan logic: validation, permutations, FP64 tables.
+#include <math.h>
+
+#include <algorithm>
+#include <thread>
+
+#include "common.hpp"
+#include "host.hpp"
+
+namespace sfft {
+
+namespace {
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+}  // namespace
+
+sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err) {
+    Resolved R{};
+    auto bad = [&](const char* m) {
+        *err = m;
+        return SFFT_E_INVALID;
+    };
+    if (!is_pow2((uint64_t)p.N) || p.N < 16 || p.N > (int64_t(1) << 30))
+        return bad("N must be a power of two in [16, 2^30]");
+    if (p.B < 2 || !is_pow2((uint64_t)p.B) || p.N / p.B < 2) return bad("B must be a power of two >= 2 with N/B >= 2");
+    if (p.K < 1 || p.K > kMaxK) return bad("K must be in [1, 4096]");
+    if (p.d < 1 || (int64_t)p.d * p.K > p.B) return bad("need 1 <= d*K <= B");
+    if (p.L < 1 || p.L > kMaxL) return bad("L must be in [1, 32]");
+    if (p.w < 2 || p.w > p.N || (p.w & 1)) return bad("w must be even and in [2, N]");
+    const int32_t T = p.vote_threshold ? p.vote_threshold : p.L / 2 + 1;
+    if (T < 1 || T > p.L) return bad("vote threshold must be in [1, L]");
+    if (p.n_resid < 0 || p.n_resid > (1 << 24)) return bad("n_resid must be in [0, 2^24]");
+    if (p.gauss_c < 0 || !isfinite(p.gauss_c)) return bad("gauss_c must be >= 0 and finite");
+    if ((p.sigma == nullptr) != (p.tau == nullptr)) return bad("sigma and tau must be given together");
+    if ((p.flags & SFFT_FLAG_FOLD_GATHER) && (p.flags & SFFT_FLAG_FOLD_STRIP))
+        return bad("FOLD_GATHER and FOLD_STRIP are exclusive");
+    if (p.B > kMaxFftLds) {
+        *err = "B > 16384 is not supported by this build";
+        return SFFT_E_UNSUPPORTED;
+    }
+    R.N = (uint32_t)p.N;
+    R.K = (uint32_t)p.K;
+    R.B = (uint32_t)p.B;
+    R.L = (uint32_t)p.L;
+    R.d = (uint32_t)p.d;
+    R.w = (uint32_t)p.w;
+    R.T = (uint32_t)T;
+    R.S = (p.flags & SFFT_FLAG_NO_RESIDUAL) ? 0u : (p.n_resid ? (uint32_t)p.n_resid : 4096u);
+    R.seed = p.seed;
+    R.gauss_c = p.gauss_c > 0 ? p.gauss_c : kDefaultGaussC;
+    R.flags = p.flags;
+    R.dK = R.d * R.K;
+    R.M = R.N / R.B;
+    R.Mw = (R.w + R.B - 1) / R.B;
+    R.log2N = ilog2(R.N);
+    R.log2B = ilog2(R.B);
+    R.log2M = ilog2(R.M);
+    R.rsh = (R.log2N + 1) / 2;
+    uint32_t lm = 4;
+    while (lm < R.L) lm <<= 1;
+    R.lmax = lm;
+    const uint64_t cap = (uint64_t)(R.L - R.T + 1) * R.dK * R.M;
+    if (cap >= (1ull << 31)) {
+        *err = "candidate capacity (L-T+1)*d*K*N/B exceeds 2^31";
+        return SFFT_E_UNSUPPORTED;
+    }
+    R.cap = (uint32_t)cap;
+
+    // random permutations: sigma_r odd, tau_r, then the residual positions
+    R.sigma.resize(R.L);
+    R.tau.resize(R.L);
+    R.sigma_inv.resize(R.L);
+    SplitMix64 rng(p.seed);
+    for (uint32_t r = 0; r < R.L; ++r) {
+        R.sigma[r] = (uint32_t)((rng.next() & (R.N - 1)) | 1u);
+        R.tau[r] = (uint32_t)(rng.next() & (R.N - 1));
+    }
+    R.tpos.resize(R.S);
+    for (uint32_t j = 0; j < R.S; ++j) R.tpos[j] = (uint32_t)(rng.next() & (R.N - 1));
+    if (p.sigma) {
+        for (uint32_t r = 0; r < R.L; ++r) {
+            if (!(p.sigma[r] & 1u) || p.sigma[r] >= R.N || p.tau[r] >= R.N)
+                return bad("explicit sigma must be odd and < N, tau < N");
+            R.sigma[r] = p.sigma[r];
+            R.tau[r] = p.tau[r];
+        }
+    }
+    for (uint32_t r = 0; r < R.L; ++r)
+        R.sigma_inv[r] = (uint32_t)(inverse_mod_2_64(R.sigma[r]) & (R.N - 1));
+
+    // bucketization form: stream full-height column strips when the L windows
+    // touch most of the signal's cache lines (L*w/N > 1/8), else gather.
+    uint32_t C = 0;
+    if (p.strip_cols) {
+        if (!is_pow2((uint64_t)p.strip_cols) || (uint32_t)p.strip_cols > R.B) return bad("strip_cols must be a power of two <= B");
+        C = (uint32_t)p.strip_cols;
+    } else {
+        C = std::min<uint32_t>(R.B, std::max<uint32_t>(2u, kStripLdsBytes / (8u * R.M)));
+    }
+    const bool strip_ok = (uint64_t)R.M * C * 8ull <= 131072ull && (C >= 2 || R.M * 8ull <= 131072ull);
+    if (p.flags & SFFT_FLAG_FOLD_STRIP) {
+        if (!strip_ok) return bad("strip bucketization tile does not fit in LDS for this N/B");
+        R.mode = 1;
+    } else if (p.flags & SFFT_FLAG_FOLD_GATHER) {
+        R.mode = 0;
+    } else {
+        R.mode = (strip_ok && 8ull * R.L * R.w > R.N) ? 1u : 0u;
+    }
+    R.C = C;
+    R.log2C = ilog2(C);
+    R.strip_lds = R.M * C * 8u;
+    R.fold_units = R.mode ? R.B / C : (R.L * R.B + kFoldNT - 1) / kFoldNT;
+    R.vote_units = (R.cap + kVoteUnit - 1) / kVoteUnit;
+    const uint32_t wpl = (R.B + 31) / 32;
+    R.vote_lds = (R.L * wpl * 4u <= 65536u) ? R.L * wpl * 4u : 0u;
+    R.resid_blocks = (R.S + kResNT - 1) / kResNT;
+    *out = std::move(R);
+    return SFFT_OK;
+}
+
+void build_tables(const Resolved& R, HostTables* t) {
+    const double pi = 3.14159265358979323846;
+    const uint32_t N = R.N, B = R.B, M = R.M, w = R.w;
+    // flat window: Gaussian (Eq.(13)) times sinc (Eq.(12), read as
+    // sin(pi t/B)/(pi t) with centre value 1/B), centred at n = w/2,
+    // Gaussian std = w / (2 gauss_c)
+    t->window.resize(w);
+    const double s = (double)w / (2.0 * R.gauss_c);
+    for (uint32_t n = 0; n < w; ++n) {
+        const double tt = (double)n - (double)w / 2.0;
+        const double gauss = exp(-0.5 * (tt / s) * (tt / s));
+        const double sinc = (tt == 0.0) ? 1.0 / (double)B : sin(pi * tt / (double)B) / (pi * tt);
+        t->window[n] = gauss * sinc;
+    }
+    // e^{+2 pi i m/N} = hi[m >> rsh] * lo[m & (2^rsh - 1)]
+    const uint32_t nlo = 1u << R.rsh, nhi = N >> R.rsh;
+    t->rt_lo.resize(2 * (size_t)nlo);
+    t->rt_hi.resize(2 * (size_t)nhi);
+    for (uint32_t m = 0; m < nlo; ++m) {
+        const double a = 2.0 * pi * (double)m / (double)N;
+        t->rt_lo[2 * m] = cos(a);
+        t->rt_lo[2 * m + 1] = sin(a);
+    }
+    for (uint32_t m = 0; m < nhi; ++m) {
+        const double a = 2.0 * pi * (double)((uint64_t)m << R.rsh) / (double)N;
+        t->rt_hi[2 * m] = cos(a);
+        t->rt_hi[2 * m + 1] = sin(a);
+    }
+    // gain table Gtab[o] = sum_n g_n e^{+2 pi i (n o mod N)/N}, exact FP64 sum
+    t->gain.assign(M, std::complex<double>(0.0, 0.0));
+    const uint32_t lomask = nlo - 1;
+    auto work = [&](uint32_t k0, uint32_t k1) {
+        for (uint32_t k = k0; k < k1; ++k) {
+            const int64_t o = (int64_t)k - (int64_t)(M / 2);
+            const uint32_t step = (uint32_t)((o % (int64_t)N + (int64_t)N) % (int64_t)N);
+            double re = 0.0, im = 0.0;
+            uint32_t m = 0;  // n * o mod N, advanced by step
+            for (uint32_t n = 0; n < w; ++n) {
+                const double* hi = &t->rt_hi[2 * (size_t)(m >> R.rsh)];
+                const double* lo = &t->rt_lo[2 * (size_t)(m & lomask)];
+                const double c = hi[0] * lo[0] - hi[1] * lo[1];
+                const double sn = hi[0] * lo[1] + hi[1] * lo[0];
+                re += t->window[n] * c;
+                im += t->window[n] * sn;
+                m = (m + step) & (N - 1);
+            }
+            t->gain[k] = std::complex<double>(re, im);
+        }
+    };
+    const uint64_t work_total = (uint64_t)M * w;
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (work_total < (1u << 20)) nth = 1;
+    nth = std::min<unsigned>(nth, M);
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i < nth; ++i) {
+        const uint32_t k0 = (uint32_t)((uint64_t)M * i / nth), k1 = (uint32_t)((uint64_t)M * (i + 1) / nth);
+        th.emplace_back(work, k0, k1);
+    }
+    for (auto& x : th) x.join();
+    // device tables
+    t->gT.assign((size_t)B * R.Mw, 0.0f);
+    for (uint32_t b = 0; b < B; ++b)
+        for (uint32_t m = 0; m < R.Mw; ++m) {
+            const uint64_t i = (uint64_t)b + (uint64_t)m * B;
+            if (i < w) t->gT[(size_t)b * R.Mw + m] = (float)t->window[i];
+        }
+    t->invG.resize(2 * (size_t)M);
+    for (uint32_t k = 0; k < M; ++k) {
+        const std::complex<double> inv = 1.0 / t->gain[k];
+        t->invG[2 * k] = (float)inv.real();
+        t->invG[2 * k + 1] = (float)inv.imag();
+    }
+    t->tw.resize(2 * (size_t)B);
+    for (uint32_t m = 0; m < B; ++m) {
+        const double a = -2.0 * pi * (double)m / (double)B;
+        t->tw[2 * m] = (float)cos(a);
+        t->tw[2 * m + 1] = (float)sin(a);
+    }
+}
+
+WsLayout workspace_layout(const Resolved& R) {
+    WsLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 16));
+        return o;
+    };
+    const size_t wpl = (R.B + 31) / 32;
+    l.uhat = take((size_t)R.L * R.B * 8);
+    l.jbits = take((size_t)R.L * wpl * 4);
+    l.jlist = take((size_t)R.L * R.dK * 4);
+    l.cand = take((size_t)R.cap * 4);
+    l.est = take((size_t)R.cap * 8);
+    l.keys = take((size_t)R.cap * 8);
+    l.rpart = take((size_t)std::max<uint32_t>(R.resid_blocks, 1) * 16);
+    l.resid_own = take(16);
+    l.ctr = take(16);
+    l.total = off;
+    return l;
+}
+
+TabLayout table_layout(const Resolved& R) {
+    TabLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 16));
+        return o;
+    };
+    l.sigma = take((size_t)R.L * 4);
+    l.sigma_inv = take((size_t)R.L * 4);
+    l.tau = take((size_t)R.L * 4);
+    l.tpos = take((size_t)R.S * 4);
+    l.gT = take((size_t)R.B * R.Mw * 4);
+    l.invG = take((size_t)R.M * 8);
+    l.tw = take((size_t)R.B * 8);
+    l.rt_hi = take((size_t)(R.N >> R.rsh) * 16);
+    l.rt_lo = take((size_t)(1u << R.rsh) * 16);
+    l.total = off;
+    return l;
+}
+
+}  // namespace sfft

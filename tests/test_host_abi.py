@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI library: it loads, exports every declared entry
+point, validates parameters, and its host-built FP64 tables and permutations
+equal the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle.sfft_oracle as O
+import paper_2012_08238_amd as S
+from paper_2012_08238_amd import _capi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sfft.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), f"missing export {n}"
+    assert {n for n, _, _ in _capi.SIGNATURES} == set(names)
+
+
+def test_version_and_status_strings():
+    lib = S.load()
+    assert b"gfx950" in lib.sfft_version()
+    assert lib.sfft_status_string(-1) == b"invalid argument"
+
+
+@pytest.mark.parametrize("bad", [
+    dict(N=1000), dict(N=8), dict(B=3), dict(B=1 << 14), dict(B=16), dict(K=0), dict(K=600), dict(L=0), dict(L=33),
+    dict(w=511), dict(w=0), dict(w=1 << 15), dict(vote_threshold=9), dict(n_resid=-1)])
+def test_parameter_validation(bad):
+    kw = dict(N=1 << 14, K=10, B=128, L=5, w=512)
+    kw.update(bad)
+    with pytest.raises(S.SfftError) as e:
+        S.host_tables(S.PlanParams(**kw))
+    assert e.value.status in (_capi.SFFT_E_INVALID, _capi.SFFT_E_UNSUPPORTED)
+
+
+def test_unsupported_large_B():
+    with pytest.raises(S.SfftError) as e:
+        S.host_tables(S.PlanParams(N=1 << 22, K=200, B=1 << 15, L=9, w=1 << 18))
+    assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N,K,B,L,w,seed", [
+    (1 << 14, 10, 128, 5, 512, 0), (1 << 14, 10, 128, 5, 512, 12345),
+    (1 << 20, 50, 1024, 7, 8192, 7), (1 << 12, 3, 64, 9, 256, 99)])
+def test_permutations_match_oracle(N, K, B, L, w, seed):
+    t = S.host_tables(S.PlanParams(N, K, B, L, w, seed=seed, n_resid=64))
+    sigma, tau, tpos = O.draw_permutations(N, L, seed, 64)
+    assert np.array_equal(t["sigma"], sigma.astype(np.uint32))
+    assert np.array_equal(t["tau"], tau.astype(np.uint32))
+    assert np.array_equal(t["tpos"], tpos.astype(np.uint32))
+    inv = np.array([O.modinv(s, N) for s in sigma], dtype=np.uint32)
+    assert np.array_equal(t["sigma_inv"], inv)
+
+
+def test_explicit_permutations():
+    sig = np.array([3, 5, 7], np.uint32)
+    tau = np.array([1, 0, 100], np.uint32)
+    t = S.host_tables(S.PlanParams(1 << 10, 2, 16, 3, 64, sigma=sig, tau=tau))
+    assert np.array_equal(t["sigma"], sig) and np.array_equal(t["tau"], tau)
+    with pytest.raises(S.SfftError):
+        S.host_tables(S.PlanParams(1 << 10, 2, 16, 3, 64, sigma=np.array([2, 5, 7], np.uint32), tau=tau))
+
+
+@pytest.mark.parametrize("N,B,w", [(1 << 14, 128, 512), (1 << 12, 64, 1024), (1 << 16, 256, 2048),
+                                   (1 << 10, 16, 96)])
+def test_window_and_gain_match_oracle(N, B, w):
+    t = S.host_tables(S.PlanParams(N, 1, B, 3, w))
+    g = O.flat_window(w, B)
+    G = O.gain_table(g, N, B)
+    assert np.max(np.abs(t["window"] - g)) <= 1e-13 * np.max(np.abs(g))
+    assert np.max(np.abs(t["gain"] - G)) <= 1e-13 * np.max(np.abs(G))
+
+
+def test_gauss_c_override():
+    t = S.host_tables(S.PlanParams(1 << 12, 1, 32, 3, 256, gauss_c=3.0))
+    g = O.flat_window(256, 32, 3.0)
+    assert np.max(np.abs(t["window"] - g)) <= 1e-13 * np.max(np.abs(g))
