@@ -171,6 +171,12 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
  * stream). Each signal's result is bitwise the one sfft_execute gives alone. */
 sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx,
                            void* const* out_val, double* const* out_resid, sfft_stream_t stream);
+/* As sfft_batch_run, and also records the caller's HIP events (hipEvent_t, may
+ * be NULL) on `stream` immediately before and after the batch's bucketization
+ * launches, so that hipEventElapsedTime gives that stage's device time. */
+sfft_status sfft_batch_run_timed(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx,
+                                 void* const* out_val, double* const* out_resid, sfft_stream_t stream,
+                                 void* ev_fold_begin, void* ev_fold_end);
 sfft_status sfft_batch_destroy(sfft_batch_t b);
 
 /* One-shot convenience: create, run once, destroy (the graph is not kept). */

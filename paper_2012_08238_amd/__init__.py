@@ -193,6 +193,15 @@ class Batch:
         ra = _ptr_array([_ptr(r) for r in resids]) if resids is not None else None
         check(load().sfft_batch_run(self._h, xa, ia, va, ra, _stream_handle(stream)), "sfft_batch_run")
 
+    def run_timed(self, xs, idxs, vals, resids, ev_begin, ev_end, stream=None) -> None:
+        """As run(); records HipEvent ev_begin / ev_end around the bucketization."""
+        xa = _ptr_array([_ptr(x) for x in xs])
+        ia = _ptr_array([_ptr(i) for i in idxs])
+        va = _ptr_array([_ptr(v) for v in vals])
+        ra = _ptr_array([_ptr(r) for r in resids]) if resids is not None else None
+        check(load().sfft_batch_run_timed(self._h, xa, ia, va, ra, _stream_handle(stream),
+                                          ev_begin.handle, ev_end.handle), "sfft_batch_run_timed")
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             check(load().sfft_batch_destroy(self._h), "sfft_batch_destroy")

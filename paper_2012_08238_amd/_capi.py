@@ -66,6 +66,9 @@ SIGNATURES = [
     ("sfft_batch_create", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32]),
     ("sfft_batch_run", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    ("sfft_batch_run_timed", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                       C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
+                                       C.c_void_p, C.c_void_p]),
     ("sfft_batch_destroy", C.c_int, [C.c_void_p]),
     ("sfft_execute_batch", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),

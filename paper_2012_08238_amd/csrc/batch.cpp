@@ -42,8 +42,10 @@ struct sfft_batch_s {
     std::vector<IoDesc> last_io;
     bool io_valid = false;
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // two graphs: [0] the bucketization launches, [1] every later stage, so a
+    // caller can bracket the bucketization with its own events
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
     hipStream_t last_stream = nullptr;
     bool launched = false;
@@ -55,8 +57,10 @@ namespace {
 
 void batch_free(sfft_batch_t b) {
     if (!b) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->d_ws) (void)hipFree(b->d_ws);
@@ -67,8 +71,10 @@ void batch_free(sfft_batch_t b) {
     delete b;
 }
 
-sfft_status issue_steps(sfft_batch_t b, hipStream_t s) {
+// part 0: bucketization steps, part 1: the others
+sfft_status issue_steps(sfft_batch_t b, hipStream_t s, int part) {
     for (const Step& st : b->steps) {
+        if ((st.kind == kFold) != (part == 0)) continue;
         Launch a{};
         a.descs = b->d_descs;
         a.ios = b->d_ios;
@@ -190,8 +196,9 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
     return SFFT_OK;
 }
 
-sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx, void* const* out_val,
-                           double* const* out_resid, sfft_stream_t stream) {
+static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx,
+                             void* const* out_val, double* const* out_resid, sfft_stream_t stream,
+                             void* ev_fold_begin, void* ev_fold_end) {
     if (!b || !x_dev || !out_idx || !out_val) return set_error(SFFT_E_INVALID, "null argument");
     std::lock_guard<std::mutex> lk(b->mu);
     hipError_t e = hipSetDevice(b->device);
@@ -222,10 +229,11 @@ sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* co
         b->last_io = io;
         b->io_valid = true;
     }
-    if (!b->exec) {
+    for (int part = 0; part < 2; ++part) {
+        if (b->exec[part]) continue;
         e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        const sfft_status st = issue_steps(b, b->cap_stream);
+        const sfft_status st = issue_steps(b, b->cap_stream, part);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (st != SFFT_OK) {
@@ -233,20 +241,41 @@ sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* co
             return st;
         }
         if (e != hipSuccess) return hip_fail(e, "graph capture end");
-        b->graph = g;
-        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        b->graph[part] = g;
+        e = hipGraphInstantiate(&b->exec[part], g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            b->exec = nullptr;
+            b->exec[part] = nullptr;
             return hip_fail(e, "graph instantiate");
         }
     }
-    e = hipGraphLaunch(b->exec, s);
+    if (ev_fold_begin) {
+        e = hipEventRecord(reinterpret_cast<hipEvent_t>(ev_fold_begin), s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    e = hipGraphLaunch(b->exec[0], s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    if (ev_fold_end) {
+        e = hipEventRecord(reinterpret_cast<hipEvent_t>(ev_fold_end), s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    e = hipGraphLaunch(b->exec[1], s);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     e = hipEventRecord(b->done, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     b->last_stream = s;
     b->launched = true;
     return SFFT_OK;
+}
+
+sfft_status sfft_batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx, void* const* out_val,
+                           double* const* out_resid, sfft_stream_t stream) {
+    return batch_run(b, x_dev, out_idx, out_val, out_resid, stream, nullptr, nullptr);
+}
+
+sfft_status sfft_batch_run_timed(sfft_batch_t b, const void* const* x_dev, int64_t* const* out_idx,
+                                 void* const* out_val, double* const* out_resid, sfft_stream_t stream,
+                                 void* ev_fold_begin, void* ev_fold_end) {
+    return batch_run(b, x_dev, out_idx, out_val, out_resid, stream, ev_fold_begin, ev_fold_end);
 }
 
 sfft_status sfft_batch_destroy(sfft_batch_t b) {

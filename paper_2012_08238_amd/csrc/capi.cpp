@@ -71,6 +71,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.L = R.L;
     d.w = R.w;
     d.Mw = R.Mw;
+    d.Mw4 = R.Mw4;
     d.K = R.K;
     d.dK = R.dK;
     d.T = R.T;

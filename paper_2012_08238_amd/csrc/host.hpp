@@ -15,7 +15,7 @@ namespace sfft {
 // Every derived size of a validated parameter set.
 struct Resolved {
     uint32_t N, K, B, L, d, w, T, S;
-    uint32_t dK, M, Mw, cap, rsh, lmax;
+    uint32_t dK, M, Mw, Mw4, cap, rsh, lmax;
     uint32_t log2N, log2B, log2M;
     uint32_t mode, C, log2C;    // bucketization form (0 gather, 1 strip) and strip width
     uint64_t seed;
@@ -29,7 +29,7 @@ struct Resolved {
 struct HostTables {
     std::vector<double> window;                 // g_n, n < w
     std::vector<std::complex<double>> gain;     // Gtab[o], o = -M/2 .. M/2-1
-    std::vector<float> gT;                      // [B][Mw]
+    std::vector<float> gT;                      // [B][Mw4]
     std::vector<float> invG;                    // [M] (re, im) pairs of 1/Gtab
     std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
     std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N} split on bits

@@ -51,6 +51,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.dK = R.d * R.K;
     R.M = R.N / R.B;
     R.Mw = (R.w + R.B - 1) / R.B;
+    R.Mw4 = (R.Mw + 3u) & ~3u;
     R.log2N = ilog2(R.N);
     R.log2B = ilog2(R.B);
     R.log2M = ilog2(R.M);
@@ -91,12 +92,13 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     // touch most of the signal's cache lines (L*w/N > 1/8), else gather.
     uint32_t C = 0;
     if (p.strip_cols) {
-        if (!is_pow2((uint64_t)p.strip_cols) || (uint32_t)p.strip_cols > R.B) return bad("strip_cols must be a power of two <= B");
+        if (!is_pow2((uint64_t)p.strip_cols) || p.strip_cols < 2 || (uint32_t)p.strip_cols > R.B)
+            return bad("strip_cols must be a power of two in [2, B]");
         C = (uint32_t)p.strip_cols;
     } else {
         C = std::min<uint32_t>(R.B, std::max<uint32_t>(2u, kStripLdsBytes / (8u * R.M)));
     }
-    const bool strip_ok = (uint64_t)R.M * C * 8ull <= 131072ull && (C >= 2 || R.M * 8ull <= 131072ull);
+    const bool strip_ok = C >= 2 && (uint64_t)R.M * C * 8ull <= 131072ull;
     if (p.flags & SFFT_FLAG_FOLD_STRIP) {
         if (!strip_ok) return bad("strip bucketization tile does not fit in LDS for this N/B");
         R.mode = 1;
@@ -177,11 +179,11 @@ void build_tables(const Resolved& R, HostTables* t) {
     }
     for (auto& x : th) x.join();
     // device tables
-    t->gT.assign((size_t)B * R.Mw, 0.0f);
+    t->gT.assign((size_t)B * R.Mw4, 0.0f);
     for (uint32_t b = 0; b < B; ++b)
         for (uint32_t m = 0; m < R.Mw; ++m) {
             const uint64_t i = (uint64_t)b + (uint64_t)m * B;
-            if (i < w) t->gT[(size_t)b * R.Mw + m] = (float)t->window[i];
+            if (i < w) t->gT[(size_t)b * R.Mw4 + m] = (float)t->window[i];
         }
     t->invG.resize(2 * (size_t)M);
     for (uint32_t k = 0; k < M; ++k) {
@@ -231,7 +233,7 @@ TabLayout table_layout(const Resolved& R) {
     l.sigma_inv = take((size_t)R.L * 4);
     l.tau = take((size_t)R.L * 4);
     l.tpos = take((size_t)R.S * 4);
-    l.gT = take((size_t)R.B * R.Mw * 4);
+    l.gT = take((size_t)R.B * R.Mw4 * 4);
     l.invG = take((size_t)R.M * 8);
     l.tw = take((size_t)R.B * 8);
     l.rt_hi = take((size_t)(R.N >> R.rsh) * 16);
