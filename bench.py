@@ -76,6 +76,8 @@ def main() -> int:
     ap.add_argument("--latency-runs", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--strip-cols", type=int, default=0, help="bucketization tile width (0 = plan default)")
+    ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -97,7 +99,8 @@ def main() -> int:
         x, f, tones = make_signal_torch(N, K, SNR_DB, derive_seed(0, i), dev)
         xs.append(x)
         truth.append((f, tones))
-    plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED)
+    plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols,
+                  flags=S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0)
     desc = plan.desc
     batch = S.Batch([plan] * M)
     idx = torch.empty((M, K), dtype=torch.int64, device=dev)
@@ -133,7 +136,7 @@ def main() -> int:
     # single-request latency (one signal, alone, synchronised)
     lat = []
     li, lv, lr = plan.outputs(dev)
-    for r in range(args.latency_runs + 3):
+    for r in range(args.latency_runs + 3 if args.latency_runs > 0 else 0):
         torch.cuda.synchronize()
         a = time.perf_counter()
         plan.execute(xs[r % M], li, lv, lr)
@@ -190,8 +193,9 @@ def main() -> int:
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
                    "strip_cols": desc["strip_cols"], "parallelism": "single-gpu"},
-        "latency": {"p50_ms": round(percentile(lat, 0.5) * 1e3, 4), "p99_ms": round(percentile(lat, 0.99) * 1e3, 4),
-                    "source": "single request, sfft_execute alone + stream sync", "runs": len(lat)},
+        "latency": ({"p50_ms": round(percentile(lat, 0.5) * 1e3, 4), "p99_ms": round(percentile(lat, 0.99) * 1e3, 4),
+                     "source": "single request, sfft_execute alone + stream sync", "runs": len(lat)}
+                    if lat else None),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,

@@ -64,6 +64,7 @@ typedef enum {
 #define SFFT_FLAG_NO_RESIDUAL 0x1u  /* skip the FP64 residual step */
 #define SFFT_FLAG_FOLD_GATHER 0x2u  /* force the gather form of the bucketization */
 #define SFFT_FLAG_FOLD_STRIP  0x4u  /* force the streamed column-strip form */
+#define SFFT_FLAG_XCD_ORDER   0x8u  /* bucketization: give each XCD a contiguous range of column strips */
 
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {

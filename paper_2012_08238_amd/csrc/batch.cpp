@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <map>
+#include <set>
 #include <mutex>
 #include <vector>
 
@@ -50,6 +51,7 @@ struct sfft_batch_s {
     hipStream_t last_stream = nullptr;
     bool launched = false;
     size_t ws_bytes = 0;
+    uint32_t xcd_order = 1;
     std::mutex mu;
 };
 
@@ -80,13 +82,14 @@ sfft_status issue_steps(sfft_batch_t b, hipStream_t s, int part) {
         a.ios = b->d_ios;
         a.prefix = b->d_prefix + st.prefix_off;
         a.nsig = (uint32_t)b->n;
+        a.xcd_order = st.kind == kFold ? b->xcd_order : 0u;
         hipError_t e = hipSuccess;
         switch (st.kind) {
             case kFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
             case kFft: e = launch_fft_select(a, st.param, st.units, s); break;
             case kVote: e = launch_vote(a, st.units, st.lds, s); break;
-            case kFin: e = launch_finalize(a, st.param, st.units, s); break;
-            case kRes: e = launch_residual(a, st.units, s); break;
+            case kFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
+            case kRes: e = launch_residual(a, st.units, st.lds, s); break;
         }
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
@@ -158,13 +161,15 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
         }
         b->steps.push_back(Step{kind, param, acc, lds, off});
     };
-    for (uint32_t mode = 0; mode < 2; ++mode) {
+    std::set<uint32_t> variants;
+    for (int32_t i = 0; i < n; ++i) variants.insert(plan_resolved(plans[i]).fold_variant);
+    for (const uint32_t v : variants) {
         uint32_t lds = 0;
         for (int32_t i = 0; i < n; ++i) {
             const Resolved& R = plan_resolved(plans[i]);
-            if (R.mode == mode && mode == 1) lds = std::max(lds, R.strip_lds);
+            if (R.fold_variant == v && R.mode == 1) lds = std::max(lds, R.strip_lds);
         }
-        add_step(kFold, mode, lds, [&](const Resolved& R) { return R.mode == mode ? R.fold_units : 0u; });
+        add_step(kFold, v, lds, [&](const Resolved& R) { return R.fold_variant == v ? R.fold_units : 0u; });
     }
     for (uint32_t lb = 1; lb <= 14; ++lb)
         add_step(kFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
@@ -177,9 +182,21 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
         add_step(kVote, staged, staged ? lds : 0,
                  [&](const Resolved& R) { return ((R.vote_lds > 0) == (staged == 1)) ? R.vote_units : 0u; });
     }
+    auto max_of = [&](auto pred, auto field) {
+        uint32_t v = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const Resolved& R = plan_resolved(plans[i]);
+            if (pred(R)) v = std::max(v, field(R));
+        }
+        return v;
+    };
     for (uint32_t lm = 4; lm <= 32; lm <<= 1)
-        add_step(kFin, lm, 0, [&](const Resolved& R) { return R.lmax == lm ? 1u : 0u; });
-    add_step(kRes, 0, 0, [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
+        add_step(kFin, lm, max_of([&](const Resolved& R) { return R.lmax == lm; }, [](const Resolved& R) { return R.fin_lds; }),
+                 [&](const Resolved& R) { return R.lmax == lm ? 1u : 0u; });
+    add_step(kRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
+             [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
+    b->xcd_order = 1;
+    for (int32_t i = 0; i < n; ++i) b->xcd_order &= plan_resolved(plans[i]).xcd_order;
     if (hipMalloc(&b->d_prefix, prefix.size() * 4) != hipSuccess) {
         batch_free(b);
         return set_error(SFFT_E_NOMEM, "prefix allocation");

@@ -50,8 +50,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.invG = reinterpret_cast<const float2*>(tab + t.invG);
     d.tw = reinterpret_cast<const float2*>(tab + t.tw);
     d.tpos = reinterpret_cast<const uint32_t*>(tab + t.tpos);
-    d.rt_hi = reinterpret_cast<const double2*>(tab + t.rt_hi);
-    d.rt_lo = reinterpret_cast<const double2*>(tab + t.rt_lo);
+    d.ph = reinterpret_cast<const double2*>(tab + t.ph);
     d.uhat = reinterpret_cast<float2*>(ws + w.uhat);
     d.jbits = reinterpret_cast<uint32_t*>(ws + w.jbits);
     d.jlist = reinterpret_cast<uint32_t*>(ws + w.jlist);
@@ -77,12 +76,15 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.T = R.T;
     d.S = R.S;
     d.cap = R.cap;
-    d.rsh = R.rsh;
+    d.pc1 = R.pc1;
+    d.pc2 = R.pc2;
+    d.pc3 = R.pc3;
     d.mode = R.mode;
     d.C = R.C;
     d.log2C = R.log2C;
     d.strips = R.B / R.C;
     d.vote_units = R.vote_units;
+    d.vote_upl = R.vote_upl;
     d.resid_blocks = R.resid_blocks;
     d.lmax = R.lmax;
     return d;
@@ -95,12 +97,14 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     a.ios = nullptr;
     a.prefix = nullptr;
     a.nsig = 0;
+    a.xcd_order = R.xcd_order;
     a.one_io = io;
-    HIP_TRY(launch_fold(a, R.mode, R.fold_units, R.strip_lds, s), "bucketization launch");
+    HIP_TRY(launch_fold(a, R.fold_variant, R.fold_units, R.strip_lds, s), "bucketization launch");
+    a.xcd_order = 0;
     HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
     HIP_TRY(launch_vote(a, R.vote_units, R.vote_lds, s), "vote launch");
-    HIP_TRY(launch_finalize(a, R.lmax, 1, s), "estimate launch");
-    if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, s), "residual launch");
+    HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, s), "estimate launch");
+    if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
     return SFFT_OK;
 }
 
@@ -164,8 +168,7 @@ sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
     memcpy(&h[tl.gT], T.gT.data(), T.gT.size() * 4);
     memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
     memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
-    memcpy(&h[tl.rt_hi], T.rt_hi.data(), T.rt_hi.size() * 8);
-    memcpy(&h[tl.rt_lo], T.rt_lo.data(), T.rt_lo.size() * 8);
+    memcpy(&h[tl.ph], T.ph.data(), T.ph.size() * 8);
     e = hipMemcpy(pl->d_tab, h.data(), tl.total, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "table upload"));
     e = hipMemset(pl->d_ws, 0, wl.total);

@@ -22,10 +22,10 @@ struct SigDesc {
     const float2* invG;         // [M] 1/Gtab[o], o = -M/2 .. M/2-1
     const float2* tw;           // [B] e^{-2 pi i m/B}
     const uint32_t* tpos;       // [S] residual sample positions
-    const double2* rt_hi;       // [N >> rsh] e^{+2 pi i (hi << rsh)/N}
-    const double2* rt_lo;       // [1 << rsh] e^{+2 pi i lo/N}
+    const double2* ph;          // [2^pc1 + 2^pc2 + 2^pc3] e^{+2 pi i m/N} on the three bit fields of m
     // workspace
-    float2* uhat;               // [L][B] bucket values, then their B-point DFT
+    float2* uhat;               // [L][B] bucket values in column order (bucket of column col is
+                                // sigma^{-1}(col - tau) mod B), then their B-point DFT in bucket order
     uint32_t* jbits;            // [L][B/32] selected buckets
     uint32_t* jlist;            // [L][dK] selected buckets, ascending
     uint32_t* cand;             // [cap] frequencies with >= T votes
@@ -39,10 +39,12 @@ struct SigDesc {
     uint32_t B, log2B;
     uint32_t M, log2M;          // M = N/B (bucket width in bins = rows of the strip view)
     uint32_t L, w, Mw, Mw4;     // Mw = ceil(w/B) window taps per bucket, Mw4 = Mw rounded up to 4
-    uint32_t K, dK, T, S, cap, rsh;
+    uint32_t K, dK, T, S, cap;
+    uint32_t pc1, pc2, pc3;     // bit widths of the phase-table fields, pc1 + pc2 + pc3 = log2N
     uint32_t mode;              // 0 gather, 1 strip
     uint32_t C, log2C, strips;  // strip bucketization tile: C columns x M rows
     uint32_t vote_units;        // vote workgroups
+    uint32_t vote_upl;          // vote workgroups per enumerated loop (chunks of kVoteUnit candidates)
     uint32_t resid_blocks;      // residual workgroups
     uint32_t lmax;              // power of two >= L used by the median network
 };
@@ -62,8 +64,11 @@ struct Launch {
     const IoDesc* ios;
     const uint32_t* prefix;     // [nsig+1] exclusive prefix of units per signal
     uint32_t nsig;
+    uint32_t xcd_order;         // 1: consecutive units run on the same XCD (see xcd_unit)
     IoDesc one_io;
 };
+
+constexpr uint32_t kNumXcd = 8;  // MI355X: 8 accelerator complex dies, workgroups dealt round-robin
 
 constexpr uint32_t kVoteNT = 256;
 constexpr uint32_t kVotePerThread = 16;

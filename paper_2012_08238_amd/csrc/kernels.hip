@@ -59,8 +59,18 @@ __device__ __forceinline__ void gst(float2* p, const float2& v) {
 }
 
 // ---------------------------------------------------------------- helpers
+// Workgroups are dealt to the XCDs round-robin (workgroup b runs on XCD b mod 8).
+// Renumber them so that XCD x runs the contiguous unit range starting at
+// x*base + min(x, rem): each XCD then works on neighbouring units (adjacent
+// column strips of the same rows) at the same time. A bijection on [0, grid).
+__device__ __forceinline__ uint32_t xcd_unit(uint32_t blk, uint32_t grid) {
+    const uint32_t x = blk % kNumXcd, i = blk / kNumXcd;
+    const uint32_t base = grid / kNumXcd, rem = grid % kNumXcd;
+    return x * base + min(x, rem) + i;
+}
+
 __device__ __forceinline__ void resolve(const Launch& a, uint32_t& sig, uint32_t& unit) {
-    const uint32_t blk = blockIdx.x;
+    const uint32_t blk = a.xcd_order ? xcd_unit(blockIdx.x, gridDim.x) : blockIdx.x;
     if (a.nsig == 0) {
         sig = 0;
         unit = blk;
@@ -194,7 +204,104 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_kernel(Launch a) {
                 }
             }
         }
-        gst(uhat + (size_t)r * B + b, acc);
+        gst(uhat + (size_t)r * B + col0 + c, acc);   // column order (see fft_select_kernel)
+    }
+}
+
+// Strip form for the common shapes: each thread owns at most IPT (loop, column)
+// items of G4*4 window taps. All tile loads are issued first (branch-free:
+// out-of-tile slots reload the last element); while they are in flight the
+// thread computes its items' buckets and fetches their window taps. The tile
+// then passes through LDS in H row bands (LDS = tile/H, so more workgroups fit
+// per CU); each band delivers the taps whose rows it holds, and the taps are
+// summed in tap order at the end: same taps, same order as the other forms.
+template <int PER, int IPT, int G4, int H>
+__global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
+    extern __shared__ f4v lds4[];
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const float2* x = io_of(a, sig).x;
+    if (unit == 0 && threadIdx.x == 0) {
+        gst(d.ctr + 0, 0u);
+        gst(d.ctr + 1, 0u);
+    }
+    const uint32_t log2C = d.log2C, C = 1u << log2C, R = d.M, B = d.B, log2B = d.log2B;
+    const uint32_t col0 = unit << log2C;
+    const uint32_t log2h = log2C - 1;
+    const uint32_t total = R << log2h;
+    const f4v* xs = reinterpret_cast<const f4v*>(x);
+    f4v v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint32_t k = min(threadIdx.x + j * kFoldNT, total - 1u);
+        const uint32_t row = k >> log2h, c = k & ((1u << log2h) - 1u);
+        v[j] = gld_nt(xs + ((((size_t)row << log2B) + col0) >> 1) + c);
+    }
+    const uint32_t items = d.L << log2C;
+    const uint32_t Mw = d.Mw, w = d.w, maskN = d.maskN;
+    const f4v* gT = reinterpret_cast<const f4v*>(d.gT);
+    uint32_t ri[IPT], ci[IPT], si_[IPT], bi[IPT], qi[IPT];
+    f4v gi[IPT][G4];
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const uint32_t it = threadIdx.x + e * kFoldNT;
+        ri[e] = it >> log2C;
+        ci[e] = it & (C - 1u);
+        if (it < items) {
+            const uint32_t r = ri[e];
+            const uint32_t s = gld(d.sigma + r), sinv = gld(d.sigma_inv + r), tu = gld(d.tau + r);
+            const uint32_t b = (sinv * (col0 + ci[e] - tu)) & (B - 1u);
+            si_[e] = s;
+            bi[e] = b;
+            qi[e] = ((s * b + tu) & maskN) >> log2B;
+#pragma unroll
+            for (int k = 0; k < G4; ++k) gi[e][k] = gld(gT + (size_t)b * G4 + k);
+        }
+    }
+    constexpr int TAPS = G4 * 4;
+    float2 xv[IPT][TAPS];
+    const uint32_t log2band = __builtin_ctz(total) - __builtin_ctz((uint32_t)H);  // float4 per band
+    const uint32_t log2rb = __builtin_ctz(R) - __builtin_ctz((uint32_t)H);       // rows per band
+    const float2* tile = reinterpret_cast<const float2*>(lds4);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        if (h > 0) __syncthreads();   // the previous band has been read
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t k = threadIdx.x + j * kFoldNT;
+            if (k < total && (k >> log2band) == (uint32_t)h) lds4[k - ((uint32_t)h << log2band)] = v[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) {
+            const uint32_t it = threadIdx.x + e * kFoldNT;
+            if (it < items) {
+#pragma unroll
+                for (int m = 0; m < TAPS; ++m) {
+                    const uint32_t row = (qi[e] + si_[e] * (uint32_t)m) & (R - 1u);
+                    if ((uint32_t)m < Mw && (row >> log2rb) == (uint32_t)h)
+                        xv[e][m] = tile[((row & ((1u << log2rb) - 1u)) << log2C) + ci[e]];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const uint32_t it = threadIdx.x + e * kFoldNT;
+        if (it < items) {
+            const uint32_t b = bi[e];
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int m = 0; m < TAPS; ++m) {
+                if ((uint32_t)m < Mw && b + ((uint32_t)m << log2B) < w) {
+                    const float g = gi[e][m >> 2][m & 3];
+                    acc.x = fmaf(g, xv[e][m].x, acc.x);
+                    acc.y = fmaf(g, xv[e][m].y, acc.y);
+                }
+            }
+            gst(d.uhat + (size_t)ri[e] * B + col0 + ci[e], acc);   // column order
+        }
     }
 }
 
@@ -210,11 +317,14 @@ __global__ __launch_bounds__(kFoldNT) void fold_gather_kernel(Launch a) {
         gst(d.ctr + 0, 0u);
         gst(d.ctr + 1, 0u);
     }
-    const uint32_t log2B = d.log2B;
+    const uint32_t log2B = d.log2B, B = d.B;
     const uint32_t it = unit * kFoldNT + threadIdx.x;
     if (it >= (d.L << log2B)) return;
-    const uint32_t r = it >> log2B, b = it & (d.B - 1u);
+    // thread (loop r, column col) computes the bucket b whose samples all sit in
+    // that column, so that the result is stored in column order like the strip form
+    const uint32_t r = it >> log2B, col = it & (B - 1u);
     const uint32_t s = gld(d.sigma + r), tu = gld(d.tau + r);
+    const uint32_t b = (gld(d.sigma_inv + r) * (col - tu)) & (B - 1u);
     const uint32_t Mw = d.Mw, Mw4 = d.Mw4, w = d.w, maskN = d.maskN;
     const f4v* gp = reinterpret_cast<const f4v*>(d.gT) + (size_t)b * (Mw4 >> 2);
     float2 acc = make_float2(0.f, 0.f);
@@ -227,7 +337,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_gather_kernel(Launch a) {
             const uint32_t m = m4 + e;
             const uint32_t i = b + (m << log2B);
             ok[e] = m < Mw && i < w;
-            xv[e] = ok[e] ? gld(x + ((s * i + tu) & maskN)) : make_float2(0.f, 0.f);
+            xv[e] = gld(x + ((s * i + tu) & maskN));   // always in bounds; unused when !ok
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -237,7 +347,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_gather_kernel(Launch a) {
             }
         }
     }
-    gst(d.uhat + it, acc);
+    gst(d.uhat + it, acc);   // = uhat[r * B + col]
 }
 
 // ---------------------------------------------------------------- B-point FFT
@@ -310,6 +420,10 @@ struct FftCfg {
     static constexpr int PADN = B + (B >> 4) + 1;    // one pad element per 16 (bank spread)
     static constexpr int CH = B >= NT ? B / NT : 1;  // energies held per thread
     static constexpr int NW = B >= 32 ? B / 32 : 1;  // bitmap words
+    // candidate capacity of the prefiltered selection: (energy, bucket) pairs
+    // placed in the data region after the bitmap words, a multiple of NT
+    static constexpr int SELCAP_RAW = (PADN * 2 - NW - 64) / 2;
+    static constexpr int SELCAP = (SELCAP_RAW > 4096 ? 4096 : SELCAP_RAW) / NT * NT;
     static constexpr size_t lds_bytes() {
         return (size_t)(PADN + TL + TH) * sizeof(float2) + (256 + 16 + 4) * sizeof(uint32_t);
     }
@@ -372,56 +486,24 @@ __device__ __forceinline__ void fft_passes(float2* lds, const float2* tlo, const
     }
 }
 
-// Selection of the dK largest |uhat|^2 (ties -> lower bucket): radix select on
-// the IEEE bit patterns of the non-negative energies (monotone as unsigned),
-// four 8-bit digits from the top. Digit counts go to an LDS histogram; the
-// first digit (sign + high exponent bits, shared by most buckets) is counted
-// with one atomic per distinct digit per wave.
-template <int LOG2B>
-__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a) {
-    using Cfg = FftCfg<LOG2B>;
-    constexpr int B = Cfg::B, NT = Cfg::NT, CH = Cfg::CH, NW = Cfg::NW;
-    extern __shared__ f4v lds_raw[];
-    float2* data = reinterpret_cast<float2*>(lds_raw);
-    float2* tlo = data + Cfg::PADN;
-    float2* thi = tlo + Cfg::TL;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(thi + Cfg::TH);
-    uint32_t* scan = hist + 256;   // NT/64 <= 16 words
-    uint32_t* bcast = scan + 16;   // [0] digit, [1] remaining rank
-    uint32_t* bits = reinterpret_cast<uint32_t*>(data);  // reuses the data region at the end
-
-    uint32_t sig, r;
-    resolve(a, sig, r);
-    const auto& d = desc_of(a, sig);
-    float2* u = d.uhat + (size_t)r * B;
-    const float2* tw = d.tw;
-    for (int h = threadIdx.x; h < B; h += NT) data[padi(h)] = gld(u + h);
-    for (int j = threadIdx.x; j < Cfg::TL; j += NT) tlo[j] = gld(tw + j);
-    for (int j = threadIdx.x; j < Cfg::TH; j += NT) thi[j] = gld(tw + (j << Cfg::LOG2TL));
-    __syncthreads();
-    fft_passes<LOG2B, 0>(data, tlo, thi);
-    for (int h = threadIdx.x; h < B; h += NT) gst(u + h, data[padi(h)]);
-
-    const bool valid = (int)threadIdx.x * CH < B;
-    uint32_t key[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        key[c] = 0;
-        if (valid) {
-            const float2 v = data[padi(threadIdx.x * CH + c)];
-            key[c] = __float_as_uint(fmaf(v.x, v.x, v.y * v.y));
-        }
-    }
+// k-th largest (1-based; k <= number of valid keys) of the keys held by the
+// block, KPT per thread: radix select on 8-bit digits from the top through an
+// LDS histogram. The first digit (shared by most keys) is counted with one
+// atomic per distinct digit per wave. Returns the value and how many keys equal
+// to it are among the k largest.
+template <int NT, int KPT>
+__device__ __forceinline__ void block_kth_largest(const uint32_t* key, const bool* kv, uint32_t k, uint32_t* hist,
+                                                  uint32_t* bcast, uint32_t& theta, uint32_t& rank) {
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t prefix = 0, pmask = 0, kk = d.dK;
+    uint32_t prefix = 0, pmask = 0, kk = k;
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
         for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const bool act = valid && ((key[c] & pmask) == prefix);
+        for (int c = 0; c < KPT; ++c) {
+            const bool act = kv[c] && ((key[c] & pmask) == prefix);
             const uint32_t dg = (key[c] >> shift) & 255u;
             if (pass == 0) {
                 uint64_t pend = __ballot(act);
@@ -469,45 +551,175 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
         kk = bcast[1];
         __syncthreads();
     }
-    // prefix = energy bits of the dK-th largest; take every key above it and the
-    // kk lowest-index keys equal to it.
+    theta = prefix;
+    rank = kk;
+}
+
+// Mask of this thread's keys (KPT per thread, block order = thread-major) among
+// the k largest: every key above theta and the first `rank` keys equal to it.
+template <int NT, int KPT>
+__device__ __forceinline__ uint64_t select_mask(const uint32_t* key, const bool* kv, uint32_t theta, uint32_t rank,
+                                                uint32_t* scan) {
     uint32_t eq = 0;
 #pragma unroll
-    for (int c = 0; c < CH; ++c) eq += (valid && key[c] == prefix) ? 1u : 0u;
+    for (int c = 0; c < KPT; ++c) eq += (kv[c] && key[c] == theta) ? 1u : 0u;
     uint32_t tot;
     uint32_t eqrank = block_excl_scan<NT>(eq, scan, tot);
     uint64_t selm = 0;
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
+    for (int c = 0; c < KPT; ++c) {
         bool sel = false;
-        if (valid) {
-            if (key[c] > prefix) {
+        if (kv[c]) {
+            if (key[c] > theta) {
                 sel = true;
-            } else if (key[c] == prefix) {
-                sel = eqrank < kk;
+            } else if (key[c] == theta) {
+                sel = eqrank < rank;
                 ++eqrank;
             }
         }
         if (sel) selm |= 1ull << c;
     }
-    for (int i = threadIdx.x; i < NW; i += NT) bits[i] = 0;
+    return selm;
+}
+
+// Write the selected buckets: the bitmap (built in LDS) and the ascending list.
+template <int NT, int KPT, typename IdxF>
+__device__ __forceinline__ void emit_selection(uint64_t selm, IdxF idx_of, uint32_t* bits, int nw, uint32_t* scan,
+                                               uint32_t* jl, uint32_t* jb, uint32_t dK) {
+    for (int i = threadIdx.x; i < nw; i += NT) bits[i] = 0;
     __syncthreads();
-    const uint32_t nsel = (uint32_t)__popcll(selm);
-    uint32_t pos = block_excl_scan<NT>(nsel, scan, tot);
-    uint32_t* jl = d.jlist + (size_t)r * d.dK;
-    const uint32_t dK = d.dK;
+    uint32_t tot;
+    uint32_t pos = block_excl_scan<NT>((uint32_t)__popcll(selm), scan, tot);
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
+    for (int c = 0; c < KPT; ++c) {
         if ((selm >> c) & 1ull) {
-            const uint32_t h = threadIdx.x * CH + c;
+            const uint32_t h = idx_of(c);
             atomicOr(&bits[h >> 5], 1u << (h & 31));
             if (pos < dK) gst(jl + pos, h);
             ++pos;
         }
     }
     __syncthreads();
+    for (int i = threadIdx.x; i < nw; i += NT) gst(jb + i, bits[i]);
+}
+
+// Selection of the dK largest |uhat|^2 (ties -> lower bucket): radix select on
+// the IEEE bit patterns of the non-negative energies (monotone as unsigned),
+// four 8-bit digits from the top. Digit counts go to an LDS histogram; the
+// first digit (sign + high exponent bits, shared by most buckets) is counted
+// with one atomic per distinct digit per wave.
+template <int LOG2B>
+__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a) {
+    using Cfg = FftCfg<LOG2B>;
+    constexpr int B = Cfg::B, NT = Cfg::NT, CH = Cfg::CH, NW = Cfg::NW;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tlo = data + Cfg::PADN;
+    float2* thi = tlo + Cfg::TL;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(thi + Cfg::TH);
+    uint32_t* scan = hist + 256;   // NT/64 <= 16 words
+    uint32_t* bcast = scan + 16;   // [0] digit, [1] remaining rank
+    uint32_t* bits = reinterpret_cast<uint32_t*>(data);  // reuses the data region at the end
+
+    uint32_t sig, r;
+    resolve(a, sig, r);
+    const auto& d = desc_of(a, sig);
+    float2* u = d.uhat + (size_t)r * B;
+    const float2* tw = d.tw;
+    {
+        // the bucketization stored loop r's values in column order: column col
+        // holds bucket b = sigma_r^{-1} (col - tau_r) mod B; place them by bucket
+        const uint32_t sinv = d.sigma_inv[r], tu = d.tau[r];
+        constexpr int LPT = (B + NT - 1) / NT;
+        float2 tmp[LPT];
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int col = min((int)threadIdx.x + q * NT, B - 1);
+            tmp[q] = gld(u + col);
+        }
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const uint32_t col = threadIdx.x + q * NT;
+            if (col < (uint32_t)B) data[padi((int)((sinv * (col - tu)) & (uint32_t)(B - 1)))] = tmp[q];
+        }
+    }
+    for (int j = threadIdx.x; j < Cfg::TL; j += NT) tlo[j] = gld(tw + j);
+    for (int j = threadIdx.x; j < Cfg::TH; j += NT) thi[j] = gld(tw + (j << Cfg::LOG2TL));
+    __syncthreads();
+    fft_passes<LOG2B, 0>(data, tlo, thi);
+    for (int h = threadIdx.x; h < B; h += NT) gst(u + h, data[padi(h)]);
+
+    const bool valid = (int)threadIdx.x * CH < B;
+    uint32_t key[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        key[c] = 0;
+        if (valid) {
+            const float2 v = data[padi(threadIdx.x * CH + c)];
+            key[c] = __float_as_uint(fmaf(v.x, v.x, v.y * v.y));
+        }
+    }
+    const uint32_t dK = d.dK;
+    uint32_t* jl = d.jlist + (size_t)r * dK;
     uint32_t* jb = d.jbits + (size_t)r * NW;
-    for (int i = threadIdx.x; i < NW; i += NT) gst(jb + i, bits[i]);
+    bool kv[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) kv[c] = valid;
+    bool done = false;
+    if constexpr (CH >= 4 && Cfg::SELCAP >= NT) {
+        if (dK <= (uint32_t)NT) {
+            // Every one of the dK largest energies is >= theta0, the dK-th largest of
+            // the per-thread maxima (at least dK threads hold a value >= theta0), so
+            // only the keys >= theta0 can be selected. Collect them (in bucket
+            // order) and select exactly among those when they are few.
+            uint32_t tmax[1] = {0};
+            const bool tv[1] = {valid};
+#pragma unroll
+            for (int c = 0; c < CH; ++c) tmax[0] = max(tmax[0], key[c]);
+            uint32_t theta0, rank0;
+            block_kth_largest<NT, 1>(tmax, tv, dK, hist, bcast, theta0, rank0);
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) cnt += (valid && key[c] >= theta0) ? 1u : 0u;
+            uint32_t total;
+            uint32_t base = block_excl_scan<NT>(cnt, scan, total);
+            if (total <= (uint32_t)Cfg::SELCAP) {   // block-uniform
+                uint32_t* ckey = bits + Cfg::NW + 64;
+                uint32_t* cidx = ckey + Cfg::SELCAP;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (valid && key[c] >= theta0) {
+                        ckey[base] = key[c];
+                        cidx[base] = threadIdx.x * CH + c;
+                        ++base;
+                    }
+                }
+                __syncthreads();
+                constexpr int CPT = Cfg::SELCAP / NT;
+                uint32_t ck[CPT];
+                bool cv[CPT];
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) {
+                    const uint32_t i = threadIdx.x * CPT + q;
+                    cv[q] = i < total;
+                    ck[q] = cv[q] ? ckey[i] : 0u;
+                }
+                uint32_t theta, rank;
+                block_kth_largest<NT, CPT>(ck, cv, dK, hist, bcast, theta, rank);
+                const uint64_t selm = select_mask<NT, CPT>(ck, cv, theta, rank, scan);
+                emit_selection<NT, CPT>(selm, [&](int q) { return cidx[threadIdx.x * CPT + q]; }, bits, NW, scan,
+                                        jl, jb, dK);
+                done = true;
+            }
+        }
+    }
+    if (!done) {   // block-uniform
+        uint32_t theta, rank;
+        block_kth_largest<NT, CH>(key, kv, dK, hist, bcast, theta, rank);
+        const uint64_t selm = select_mask<NT, CH>(key, kv, theta, rank, scan);
+        emit_selection<NT, CH>(selm, [&](int c) { return (uint32_t)(threadIdx.x * CH + c); }, bits, NW, scan, jl, jb,
+                               dK);
+    }
 }
 
 // ---------------------------------------------------------------- votes
@@ -519,38 +731,58 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
 __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged) {
     extern __shared__ uint32_t sbits[];
     __shared__ uint32_t s_sig[kMaxL];
+    __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
     const uint32_t wpl = (d.B + 31u) >> 5;
     const uint32_t L = d.L, T = d.T, M = d.M, log2M = d.log2M, maskN = d.maskN, B = d.B, dK = d.dK;
     const uint32_t* jbits = d.jbits;
-    const uint32_t* jlist = d.jlist;
-    const uint32_t* sigma_inv = d.sigma_inv;
+    // this workgroup: candidates [start, end) of enumerated loop r0, i.e. the
+    // permuted positions of selected-bucket slots slot0 .. slot0 + nslots - 1
+    const uint32_t upl = d.vote_upl;
+    const uint32_t r0 = unit / upl;
+    const uint32_t per_loop = dK * M;
+    const uint32_t start = (unit - r0 * upl) * kVoteUnit;
+    const uint32_t end = min(start + kVoteUnit, per_loop);
+    const uint32_t slot0 = start >> log2M;
+    const uint32_t nslots = ((end - 1u) >> log2M) - slot0 + 1u;
+    const uint32_t sinv0 = d.sigma_inv[r0];
+    const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
+    for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
     if (threadIdx.x < L) s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
     const uint32_t* bits = jbits;
     if (staged) {
-        const uint32_t nw = L * wpl;
-        for (uint32_t i = threadIdx.x; i < nw; i += kVoteNT) sbits[i] = gld(jbits + i);
+        // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte units)
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        const uint32_t nw4 = (L * wpl + 3u) >> 2;
+        const u4v* src = reinterpret_cast<const u4v*>(jbits);
+        u4v* dst = reinterpret_cast<u4v*>(sbits);
+        for (uint32_t i0 = threadIdx.x; i0 < nw4; i0 += 4 * kVoteNT) {
+            u4v t[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) t[e] = gld(src + min(i0 + e * kVoteNT, nw4 - 1u));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t i = i0 + e * kVoteNT;
+                if (i < nw4) dst[i] = t[e];
+            }
+        }
         bits = sbits;
     }
     __syncthreads();
-    const uint32_t per_loop = dK * M;
-    const uint32_t total = (L - T + 1u) * per_loop;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t* ctr = d.ctr;
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
     for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-        const uint32_t c = unit * kVoteUnit + qq * kVoteNT + threadIdx.x;
+        const uint32_t ci = start + qq * kVoteNT + threadIdx.x;   // candidate index within loop r0
         bool emit = false;
         uint32_t f = 0;
-        if (c < total) {
-            const uint32_t r0 = c / per_loop;
-            const uint32_t rem = c - r0 * per_loop;
-            const uint32_t h = gld(jlist + r0 * dK + (rem >> log2M));
-            const uint32_t p = ((h << log2M) - (M >> 1) + (rem & (M - 1u))) & maskN;
-            f = (gld(sigma_inv + r0) * p) & maskN;
+        if (ci < end) {
+            const uint32_t h = s_slot[(ci >> log2M) - slot0];
+            const uint32_t p = ((h << log2M) - (M >> 1) + (ci & (M - 1u))) & maskN;
+            f = (sinv0 * p) & maskN;
             uint32_t cnt = 1;
             bool dup = false;
             for (uint32_t r = 0; r < L; ++r) {
@@ -619,14 +851,42 @@ __device__ __forceinline__ float median_of(float* v, uint32_t L) {
     return (L & 1u) ? b : (a + b) * 0.5f;
 }
 
+// Copy the three FP64 phase tables (2^pc1 + 2^pc2 + 2^pc3 entries) to LDS.
+template <int NT>
+__device__ __forceinline__ void stage_phase_tables(double2* dst, const double2* src, uint32_t n) {
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {
+        double2 t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t i = i0 + e * NT;
+            if (i < n) t[e] = gld(src + i);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t i = i0 + e * NT;
+            if (i < n) dst[i] = t[e];
+        }
+    }
+}
+
+// e^{+2 pi i m/N} = T3[m >> (pc1+pc2)] T2[(m >> pc1) mod 2^pc2] T1[m mod 2^pc1], FP64
+__device__ __forceinline__ double2 phase_of(const double2* ph, uint32_t m, uint32_t pc1, uint32_t pc2, uint32_t n1,
+                                            uint32_t n2) {
+    const double2 a = ph[m & (n1 - 1u)];
+    const double2 b = ph[n1 + ((m >> pc1) & (n2 - 1u))];
+    const double2 c = ph[n1 + n2 + (m >> (pc1 + pc2))];
+    const double br = c.x * b.x - c.y * b.y, bi = c.x * b.y + c.y * b.x;
+    return make_double2(br * a.x - bi * a.y, br * a.y + bi * a.x);
+}
+
 // For each f in I': e_r = uhat_r[h_r(f)] * e^{-2 pi i (tau_r f mod N)/N} / Gtab[o_r(f)]
 // (the energy-concentration estimate of the one frequency assumed in the
 // bucket), x'_f = median_r Re e_r + i median_r Im e_r; then the K largest |x'_f|^2
 // (ties -> lower f), returned in ascending f. One workgroup per signal.
+// Dynamic LDS: phase tables, then P values and P frequencies (P = 2^ceil(log2 K)).
 template <int LMAX>
 __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
-    __shared__ uint32_t s_f[kMaxK];
-    __shared__ float2 s_v[kMaxK];
+    extern __shared__ f4v lds_raw[];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t bc[4];
     __shared__ uint32_t s_sig[kMaxL], s_tau[kMaxL];
@@ -635,11 +895,18 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
+    const uint32_t pc1 = d.pc1, pc2 = d.pc2, n1 = 1u << pc1, n2 = 1u << pc2, nph = n1 + n2 + (1u << d.pc3);
+    uint32_t P = 1;
+    while (P < d.K) P <<= 1;
+    double2* ph = reinterpret_cast<double2*>(lds_raw);
+    float2* s_v = reinterpret_cast<float2*>(ph + nph);
+    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + P);
     if (threadIdx.x == 0) bc[3] = min(gld(d.ctr), d.cap);
     if (threadIdx.x < L) {
         s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
         s_tau[threadIdx.x] = gld(d.tau + threadIdx.x);
     }
+    stage_phase_tables<kFinNT>(ph, d.ph, nph);
     __syncthreads();
     const uint32_t n = bc[3];   // block-uniform by construction
     const uint32_t* cand = d.cand;
@@ -662,10 +929,9 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
                 const float2 g = gld(invG + gi);
                 const float2 uv = gld(uhat + (size_t)r * B + h);
                 const uint32_t k = (s_tau[r] * f) & maskN;
-                double sd, cd;
-                sincospi((double)k * (2.0 / (double)N), &sd, &cd);
-                const float2 ph = make_float2((float)cd, -(float)sd);
-                const float2 e = cmul(cmul(uv, ph), g);
+                const double2 pk = phase_of(ph, k, pc1, pc2, n1, n2);   // e^{+2 pi i k/N}
+                const float2 rot = make_float2((float)pk.x, -(float)pk.y);
+                const float2 e = cmul(cmul(uv, rot), g);
                 re[r] = e.x;
                 im[r] = e.y;
             }
@@ -733,24 +999,24 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
         const uint64_t key = gld(keys + i);
         if (key <= thr) {
             const uint32_t pos = atomicAdd(&bc[2], 1u);
-            if (pos < kMaxK) {
+            if (pos < P) {
                 s_f[pos] = (uint32_t)key;
                 s_v[pos] = gld(est + i);
             }
         }
     }
     __syncthreads();
-    const uint32_t cnt = min(bc[2], min(K, (uint32_t)kMaxK));
-    uint32_t P = 1;
-    while (P < cnt) P <<= 1;
-    for (uint32_t i = cnt + threadIdx.x; i < P; i += kFinNT) {
+    const uint32_t cnt = min(bc[2], K);
+    uint32_t Q = 1;   // sort size: power of two >= cnt (<= P)
+    while (Q < cnt) Q <<= 1;
+    for (uint32_t i = cnt + threadIdx.x; i < Q; i += kFinNT) {
         s_f[i] = 0xFFFFFFFFu;
         s_v[i] = make_float2(0.f, 0.f);
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t k = 2; k <= Q; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < P; i += kFinNT) {
+            for (uint32_t i = threadIdx.x; i < Q; i += kFinNT) {
                 const uint32_t l = i ^ j;
                 if (l > i) {
                     const bool up = (i & k) == 0;
@@ -780,20 +1046,25 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
 
 // ---------------------------------------------------------------- FP64 residual
 // E_res = mean_t |x_t - sum_k v_k e^{+2 pi i (t f_k mod N)/N}|^2 and
-// E_in = mean_t |x_t|^2 over the S residual samples. The outputs are staged in
-// LDS; the phase comes from two FP64 tables split on the bits of the exact
-// integer t f mod N. Partial sums are reduced in a fixed order by the last
+// E_in = mean_t |x_t|^2 over the S residual samples. The outputs and the three
+// FP64 phase tables are staged in LDS (dynamic: tables, K values, K
+// frequencies); the phase of the exact integer t f mod N is the product of one
+// entry per table. Partial sums are reduced in a fixed order by the last
 // workgroup to finish.
 __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
-    __shared__ uint32_t s_f[kMaxK];
-    __shared__ float2 s_v[kMaxK];
+    extern __shared__ f4v lds_raw[];
     __shared__ double sh[2][kResNT / 64];
     __shared__ uint32_t is_last;
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
-    const uint32_t K = d.K, maskN = d.maskN, rsh = d.rsh;
+    const uint32_t K = d.K, maskN = d.maskN;
+    const uint32_t pc1 = d.pc1, pc2 = d.pc2, n1 = 1u << pc1, n2 = 1u << pc2, nph = n1 + n2 + (1u << d.pc3);
+    double2* ph = reinterpret_cast<double2*>(lds_raw);
+    float2* s_v = reinterpret_cast<float2*>(ph + nph);
+    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + K);
+    stage_phase_tables<kResNT>(ph, d.ph, nph);
     for (uint32_t k = threadIdx.x; k < K; k += kResNT) {
         const int64_t f = gld(io.out_idx + k);
         s_f[k] = f < 0 ? 0xFFFFFFFFu : (uint32_t)f;
@@ -801,40 +1072,19 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     }
     __syncthreads();
     const uint32_t j = unit * kResNT + threadIdx.x;
-    const double2* rt_hi = d.rt_hi;
-    const double2* rt_lo = d.rt_lo;
     double ea = 0.0, eb = 0.0;
     if (j < d.S) {
         const uint32_t t = gld(d.tpos + j);
         const float2 xv = gld(io.x + t);
         const double xr = xv.x, xi = xv.y;
         double mr = 0.0, mi = 0.0;
-        const uint32_t lomask = (1u << rsh) - 1u;
-        for (uint32_t k0 = 0; k0 < K; k0 += 4) {
-            double2 hi[4], lo[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t k = k0 + e;
-                const uint32_t f = k < K ? s_f[k] : 0xFFFFFFFFu;
-                const uint32_t m = (t * f) & maskN;
-                hi[e] = make_double2(0.0, 0.0);
-                lo[e] = make_double2(0.0, 0.0);
-                if (f != 0xFFFFFFFFu) {
-                    hi[e] = gld(rt_hi + (m >> rsh));
-                    lo[e] = gld(rt_lo + (m & lomask));
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t k = k0 + e;
-                if (k < K && s_f[k] != 0xFFFFFFFFu) {
-                    const float2 v = s_v[k];
-                    const double pr = hi[e].x * lo[e].x - hi[e].y * lo[e].y;
-                    const double pi = hi[e].x * lo[e].y + hi[e].y * lo[e].x;
-                    mr += (double)v.x * pr - (double)v.y * pi;
-                    mi += (double)v.x * pi + (double)v.y * pr;
-                }
-            }
+        for (uint32_t k = 0; k < K; ++k) {
+            const uint32_t f = s_f[k];
+            if (f == 0xFFFFFFFFu) continue;   // padding (uniform across the block)
+            const double2 p = phase_of(ph, (t * f) & maskN, pc1, pc2, n1, n2);
+            const float2 v = s_v[k];
+            mr += (double)v.x * p.x - (double)v.y * p.y;
+            mi += (double)v.x * p.y + (double)v.y * p.x;
         }
         const double er = xr - mr, ei = xi - mi;
         ea = er * er + ei * ei;
@@ -935,9 +1185,34 @@ uint32_t strip_per_thread(uint32_t lds_bytes) {
     return per;
 }
 
-hipError_t launch_fold(const Launch& a, uint32_t mode, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
-    if (mode == 1) {
-        switch (strip_per_thread(lds_bytes)) {
+uint32_t fold_variant(uint32_t mode, uint32_t strip_lds, uint32_t items, uint32_t g4) {
+    if (mode == 0) return 0;
+    const uint32_t per = strip_per_thread(strip_lds);
+    uint32_t lp = 0;
+    while ((1u << lp) < per) ++lp;
+    const uint32_t ipt = (items + kFoldNT - 1) / kFoldNT;
+    if (per >= 4 && ipt >= 1 && ipt <= 2 && g4 >= 1 && g4 <= 2) return (1u << 16) | (lp << 8) | (ipt << 4) | g4;
+    return (1u << 16) | (lp << 8);
+}
+
+// row bands of the prefetching strip kernel: LDS holds at most 32 KB of the tile
+constexpr uint32_t strip_bands(uint32_t per) { return per >= 16 ? per / 8 : 1; }
+
+#define SFFT_PF(PER, IPT, G4)                                                                              \
+    case (PER << 8) | (IPT << 4) | G4:                                                                     \
+        hipLaunchKernelGGL((fold_strip_pf_kernel<PER, IPT, G4, strip_bands(PER)>), dim3(units), dim3(kFoldNT), \
+                           lds_bytes / strip_bands(PER), s, a);                                            \
+        break;
+
+hipError_t launch_fold(const Launch& a, uint32_t variant, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
+    if (variant == 0) {
+        hipLaunchKernelGGL(fold_gather_kernel, dim3(units), dim3(kFoldNT), 0, s, a);
+        return hipGetLastError();
+    }
+    const uint32_t per = 1u << ((variant >> 8) & 255u);
+    const uint32_t ipt = (variant >> 4) & 15u, g4 = variant & 15u;
+    if (ipt == 0) {
+        switch (per) {
             case 1: hipLaunchKernelGGL(fold_strip_kernel<1>, dim3(units), dim3(kFoldNT), lds_bytes, s, a); break;
             case 2: hipLaunchKernelGGL(fold_strip_kernel<2>, dim3(units), dim3(kFoldNT), lds_bytes, s, a); break;
             case 4: hipLaunchKernelGGL(fold_strip_kernel<4>, dim3(units), dim3(kFoldNT), lds_bytes, s, a); break;
@@ -946,11 +1221,18 @@ hipError_t launch_fold(const Launch& a, uint32_t mode, uint32_t units, uint32_t 
             case 32: hipLaunchKernelGGL(fold_strip_kernel<32>, dim3(units), dim3(kFoldNT), lds_bytes, s, a); break;
             default: return hipErrorInvalidValue;
         }
-    } else {
-        hipLaunchKernelGGL(fold_gather_kernel, dim3(units), dim3(kFoldNT), 0, s, a);
+        return hipGetLastError();
+    }
+    switch ((per << 8) | (ipt << 4) | g4) {
+        SFFT_PF(4, 1, 1) SFFT_PF(4, 1, 2) SFFT_PF(4, 2, 1) SFFT_PF(4, 2, 2)
+        SFFT_PF(8, 1, 1) SFFT_PF(8, 1, 2) SFFT_PF(8, 2, 1) SFFT_PF(8, 2, 2)
+        SFFT_PF(16, 1, 1) SFFT_PF(16, 1, 2) SFFT_PF(16, 2, 1) SFFT_PF(16, 2, 2)
+        SFFT_PF(32, 1, 1) SFFT_PF(32, 1, 2) SFFT_PF(32, 2, 1) SFFT_PF(32, 2, 2)
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+#undef SFFT_PF
 
 hipError_t launch_vote(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
     const uint32_t staged = lds_bytes ? 1u : 0u;
@@ -958,19 +1240,19 @@ hipError_t launch_vote(const Launch& a, uint32_t units, uint32_t lds_bytes, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, hipStream_t s) {
+hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds, hipStream_t s) {
     switch (lmax) {
-        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(units), dim3(kFinNT), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(units), dim3(kFinNT), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(finalize_kernel<16>, dim3(units), dim3(kFinNT), 0, s, a); break;
-        case 32: hipLaunchKernelGGL(finalize_kernel<32>, dim3(units), dim3(kFinNT), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 16: hipLaunchKernelGGL(finalize_kernel<16>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 32: hipLaunchKernelGGL(finalize_kernel<32>, dim3(units), dim3(kFinNT), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const Launch& a, uint32_t units, hipStream_t s) {
-    hipLaunchKernelGGL(residual_kernel, dim3(units), dim3(kResNT), 0, s, a);
+hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(units), dim3(kResNT), lds, s, a);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "host.hpp"
+#include "kernels.hpp"
 
 namespace sfft {
 
@@ -56,6 +57,9 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.log2B = ilog2(R.B);
     R.log2M = ilog2(R.M);
     R.rsh = (R.log2N + 1) / 2;
+    R.pc1 = (R.log2N + 2) / 3;
+    R.pc2 = R.pc1;
+    R.pc3 = R.log2N - 2 * R.pc1;
     uint32_t lm = 4;
     while (lm < R.L) lm <<= 1;
     R.lmax = lm;
@@ -111,10 +115,20 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.log2C = ilog2(C);
     R.strip_lds = R.M * C * 8u;
     R.fold_units = R.mode ? R.B / C : (R.L * R.B + kFoldNT - 1) / kFoldNT;
-    R.vote_units = (R.cap + kVoteUnit - 1) / kVoteUnit;
+    // vote workgroups: chunks of kVoteUnit candidates that never straddle two loops
+    R.vote_upl = (R.dK * R.M + kVoteUnit - 1) / kVoteUnit;
+    R.vote_units = (R.L - R.T + 1) * R.vote_upl;
     const uint32_t wpl = (R.B + 31) / 32;
-    R.vote_lds = (R.L * wpl * 4u <= 65536u) ? R.L * wpl * 4u : 0u;
+    const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
+    R.vote_lds = vbytes <= 65536u ? vbytes : 0u;
     R.resid_blocks = (R.S + kResNT - 1) / kResNT;
+    const uint32_t ph_bytes = ((1u << R.pc1) + (1u << R.pc2) + (1u << R.pc3)) * 16u;
+    uint32_t P = 1;
+    while (P < R.K) P <<= 1;
+    R.resid_lds = ph_bytes + R.K * 8u + R.K * 4u;
+    R.fin_lds = ph_bytes + P * 8u + P * 4u;
+    R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;
+    R.fold_variant = fold_variant(R.mode, R.strip_lds, R.L << R.log2C, R.Mw4 / 4);
     *out = std::move(R);
     return SFFT_OK;
 }
@@ -146,6 +160,20 @@ void build_tables(const Resolved& R, HostTables* t) {
         const double a = 2.0 * pi * (double)((uint64_t)m << R.rsh) / (double)N;
         t->rt_hi[2 * m] = cos(a);
         t->rt_hi[2 * m + 1] = sin(a);
+    }
+    // device phase tables: e^{+2 pi i m/N} = T3[m >> (pc1+pc2)] T2[(m >> pc1) & .] T1[m & .]
+    {
+        const uint32_t n1 = 1u << R.pc1, n2 = 1u << R.pc2, n3 = 1u << R.pc3;
+        t->ph.resize(2 * (size_t)(n1 + n2 + n3));
+        size_t o = 0;
+        auto put = [&](uint64_t m) {
+            const double a = 2.0 * pi * (double)m / (double)N;
+            t->ph[o++] = cos(a);
+            t->ph[o++] = sin(a);
+        };
+        for (uint32_t j = 0; j < n1; ++j) put(j);
+        for (uint32_t j = 0; j < n2; ++j) put((uint64_t)j << R.pc1);
+        for (uint32_t j = 0; j < n3; ++j) put((uint64_t)j << (R.pc1 + R.pc2));
     }
     // gain table Gtab[o] = sum_n g_n e^{+2 pi i (n o mod N)/N}, exact FP64 sum
     t->gain.assign(M, std::complex<double>(0.0, 0.0));
@@ -236,8 +264,7 @@ TabLayout table_layout(const Resolved& R) {
     l.gT = take((size_t)R.B * R.Mw4 * 4);
     l.invG = take((size_t)R.M * 8);
     l.tw = take((size_t)R.B * 8);
-    l.rt_hi = take((size_t)(R.N >> R.rsh) * 16);
-    l.rt_lo = take((size_t)(1u << R.rsh) * 16);
+    l.ph = take((size_t)((1u << R.pc1) + (1u << R.pc2) + (1u << R.pc3)) * 16);
     l.total = off;
     return l;
 }
