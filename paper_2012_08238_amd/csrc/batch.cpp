@@ -87,7 +87,7 @@ sfft_status issue_steps(sfft_batch_t b, hipStream_t s, int part) {
         switch (st.kind) {
             case kFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
             case kFft: e = launch_fft_select(a, st.param, st.units, s); break;
-            case kVote: e = launch_vote(a, st.units, st.lds, s); break;
+            case kVote: e = launch_vote(a, st.param >> 8, st.units, st.lds, s); break;
             case kFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
             case kRes: e = launch_residual(a, st.units, st.lds, s); break;
         }
@@ -173,15 +173,17 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
     }
     for (uint32_t lb = 1; lb <= 14; ++lb)
         add_step(kFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
-    for (uint32_t staged = 0; staged < 2; ++staged) {
-        uint32_t lds = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            const Resolved& R = plan_resolved(plans[i]);
-            if ((R.vote_lds > 0) == (staged == 1)) lds = std::max(lds, R.vote_lds);
+    for (uint32_t staged = 0; staged < 2; ++staged)
+        for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
+            auto in_group = [&](const Resolved& R) { return (R.vote_lds > 0) == (staged == 1) && R.lmax == lm; };
+            uint32_t lds = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                const Resolved& R = plan_resolved(plans[i]);
+                if (in_group(R)) lds = std::max(lds, R.vote_lds);
+            }
+            add_step(kVote, staged | (lm << 8), staged ? lds : 0,
+                     [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
         }
-        add_step(kVote, staged, staged ? lds : 0,
-                 [&](const Resolved& R) { return ((R.vote_lds > 0) == (staged == 1)) ? R.vote_units : 0u; });
-    }
     auto max_of = [&](auto pred, auto field) {
         uint32_t v = 0;
         for (int32_t i = 0; i < n; ++i) {

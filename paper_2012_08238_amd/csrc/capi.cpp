@@ -50,7 +50,9 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.invG = reinterpret_cast<const float2*>(tab + t.invG);
     d.tw = reinterpret_cast<const float2*>(tab + t.tw);
     d.tpos = reinterpret_cast<const uint32_t*>(tab + t.tpos);
-    d.ph = reinterpret_cast<const double2*>(tab + t.ph);
+    d.rou = reinterpret_cast<const double2*>(tab + t.rou);
+    d.tb = R.tb;
+    d.step = 6.283185307179586476925286766559 / (double)R.N;
     d.uhat = reinterpret_cast<float2*>(ws + w.uhat);
     d.jbits = reinterpret_cast<uint32_t*>(ws + w.jbits);
     d.jlist = reinterpret_cast<uint32_t*>(ws + w.jlist);
@@ -76,9 +78,6 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.T = R.T;
     d.S = R.S;
     d.cap = R.cap;
-    d.pc1 = R.pc1;
-    d.pc2 = R.pc2;
-    d.pc3 = R.pc3;
     d.mode = R.mode;
     d.C = R.C;
     d.log2C = R.log2C;
@@ -102,7 +101,7 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     HIP_TRY(launch_fold(a, R.fold_variant, R.fold_units, R.strip_lds, s), "bucketization launch");
     a.xcd_order = 0;
     HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
-    HIP_TRY(launch_vote(a, R.vote_units, R.vote_lds, s), "vote launch");
+    HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, s), "vote launch");
     HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, s), "estimate launch");
     if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
     return SFFT_OK;
@@ -168,7 +167,7 @@ sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
     memcpy(&h[tl.gT], T.gT.data(), T.gT.size() * 4);
     memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
     memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
-    memcpy(&h[tl.ph], T.ph.data(), T.ph.size() * 8);
+    memcpy(&h[tl.rou], T.rou.data(), T.rou.size() * 8);
     e = hipMemcpy(pl->d_tab, h.data(), tl.total, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "table upload"));
     e = hipMemset(pl->d_ws, 0, wl.total);

@@ -9,6 +9,7 @@ namespace sfft {
 constexpr int kMaxL = 32;        // loops supported (bitmaps, median sorting network)
 constexpr int kMaxK = 4096;      // outputs supported (final sort in LDS)
 constexpr int kMaxFftLds = 16384;  // largest B transformed inside one workgroup's LDS
+constexpr int kRouMax = 256;       // entries of the FP64 root-of-unity table
 
 // Per-signal execution descriptor: plan tables (read only, shared by every
 // execution of a plan) plus one workspace. Lives in device memory; kernels
@@ -22,7 +23,7 @@ struct SigDesc {
     const float2* invG;         // [M] 1/Gtab[o], o = -M/2 .. M/2-1
     const float2* tw;           // [B] e^{-2 pi i m/B}
     const uint32_t* tpos;       // [S] residual sample positions
-    const double2* ph;          // [2^pc1 + 2^pc2 + 2^pc3] e^{+2 pi i m/N} on the three bit fields of m
+    const double2* rou;         // [2^tb] e^{2 pi i j / 2^tb}, FP64
     // workspace
     float2* uhat;               // [L][B] bucket values in column order (bucket of column col is
                                 // sigma^{-1}(col - tau) mod B), then their B-point DFT in bucket order
@@ -40,7 +41,8 @@ struct SigDesc {
     uint32_t M, log2M;          // M = N/B (bucket width in bins = rows of the strip view)
     uint32_t L, w, Mw, Mw4;     // Mw = ceil(w/B) window taps per bucket, Mw4 = Mw rounded up to 4
     uint32_t K, dK, T, S, cap;
-    uint32_t pc1, pc2, pc3;     // bit widths of the phase-table fields, pc1 + pc2 + pc3 = log2N
+    uint32_t tb;                // root-of-unity table bits, min(8, log2N)
+    double step;                // 2 pi / N
     uint32_t mode;              // 0 gather, 1 strip
     uint32_t C, log2C, strips;  // strip bucketization tile: C columns x M rows
     uint32_t vote_units;        // vote workgroups

@@ -16,8 +16,8 @@ namespace sfft {
 struct Resolved {
     uint32_t N, K, B, L, d, w, T, S;
     uint32_t dK, M, Mw, Mw4, cap, lmax;
-    uint32_t pc1, pc2, pc3;     // phase-table bit fields (device), pc1 + pc2 + pc3 = log2N
     uint32_t rsh;               // two-field split of the host gain-table phases
+    uint32_t tb;                // device root-of-unity table bits, min(8, log2N)
     uint32_t log2N, log2B, log2M;
     uint32_t mode, C, log2C;    // bucketization form (0 gather, 1 strip) and strip width
     uint64_t seed;
@@ -36,8 +36,8 @@ struct HostTables {
     std::vector<float> gT;                      // [B][Mw4]
     std::vector<float> invG;                    // [M] (re, im) pairs of 1/Gtab
     std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
-    std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N}, two bit fields (host)
-    std::vector<double> ph;                     // (re, im) pairs, three bit fields (device)
+    std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N}, two bit fields
+    std::vector<double> rou;                    // (re, im) pairs of e^{2 pi i j / 2^tb}
 };
 
 constexpr double kDefaultGaussC = 4.861870431316438;  // 516 / (2 * 16 * sqrt(11)), Fig. 1 example
@@ -84,7 +84,7 @@ WsLayout workspace_layout(const Resolved& R);
 
 // Device table layout (byte offsets into one allocation).
 struct TabLayout {
-    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, ph, total;
+    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rou, total;
 };
 TabLayout table_layout(const Resolved& R);
 

@@ -728,9 +728,9 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
 // enumerated: f = sigma_r0^{-1} p for the N/B permuted positions p of each
 // selected bucket. Each frequency is counted from the first loop that voted
 // for it (later loops skip it), so I' has no duplicates; votes are bitmap tests.
+template <int LMAX>
 __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged) {
     extern __shared__ uint32_t sbits[];
-    __shared__ uint32_t s_sig[kMaxL];
     __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
     uint32_t sig, unit;
     resolve(a, sig, unit);
@@ -750,7 +750,9 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     const uint32_t sinv0 = d.sigma_inv[r0];
     const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
     for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
-    if (threadIdx.x < L) s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
+    uint32_t sg[LMAX];   // sigma_r, uniform: scalar loads
+#pragma unroll
+    for (int r = 0; r < LMAX; ++r) sg[r] = (uint32_t)r < L ? ((CU32)d.sigma)[r] : 0u;
     const uint32_t* bits = jbits;
     if (staged) {
         // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte units)
@@ -783,24 +785,19 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
             const uint32_t h = s_slot[(ci >> log2M) - slot0];
             const uint32_t p = ((h << log2M) - (M >> 1) + (ci & (M - 1u))) & maskN;
             f = (sinv0 * p) & maskN;
-            uint32_t cnt = 1;
-            bool dup = false;
-            for (uint32_t r = 0; r < L; ++r) {
-                if (r == r0) continue;
-                const uint32_t pr = (s_sig[r] * f) & maskN;
-                const uint32_t hr = ((pr + (M >> 1)) >> log2M) & (B - 1u);
-                const uint32_t bit = (bits[r * wpl + (hr >> 5)] >> (hr & 31u)) & 1u;
-                if (r < r0) {
-                    if (bit) {
-                        dup = true;
-                        break;
-                    }
-                } else {
-                    cnt += bit;
-                    if (cnt + (L - 1u - r) < T) break;
+            // all L bitmap tests issued together (no serial chain); bit r of `votes`
+            // is set when loop r selected the bucket of f (loop r0 always did)
+            uint32_t votes = 0;
+#pragma unroll
+            for (int r = 0; r < LMAX; ++r) {
+                if ((uint32_t)r < L) {
+                    const uint32_t pr = (sg[r] * f) & maskN;
+                    const uint32_t hr = ((pr + (M >> 1)) >> log2M) & (B - 1u);
+                    votes |= ((bits[(uint32_t)r * wpl + (hr >> 5)] >> (hr & 31u)) & 1u) << r;
                 }
             }
-            emit = !dup && cnt >= T;
+            // counted once: from the first loop that voted for f
+            emit = (votes & ((1u << r0) - 1u)) == 0u && (uint32_t)__popc(votes) >= T;
         }
         const uint64_t m = __ballot(emit);
         if (m) {
@@ -851,62 +848,63 @@ __device__ __forceinline__ float median_of(float* v, uint32_t L) {
     return (L & 1u) ? b : (a + b) * 0.5f;
 }
 
-// Copy the three FP64 phase tables (2^pc1 + 2^pc2 + 2^pc3 entries) to LDS.
-template <int NT>
-__device__ __forceinline__ void stage_phase_tables(double2* dst, const double2* src, uint32_t n) {
-    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {
-        double2 t[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t i = i0 + e * NT;
-            if (i < n) t[e] = gld(src + i);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t i = i0 + e * NT;
-            if (i < n) dst[i] = t[e];
-        }
-    }
+
+constexpr double inv_fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
 }
 
-// e^{+2 pi i m/N} = T3[m >> (pc1+pc2)] T2[(m >> pc1) mod 2^pc2] T1[m mod 2^pc1], FP64
-__device__ __forceinline__ double2 phase_of(const double2* ph, uint32_t m, uint32_t pc1, uint32_t pc2, uint32_t n1,
-                                            uint32_t n2) {
-    const double2 a = ph[m & (n1 - 1u)];
-    const double2 b = ph[n1 + ((m >> pc1) & (n2 - 1u))];
-    const double2 c = ph[n1 + n2 + (m >> (pc1 + pc2))];
-    const double br = c.x * b.x - c.y * b.y, bi = c.x * b.y + c.y * b.x;
-    return make_double2(br * a.x - bi * a.y, br * a.y + bi * a.x);
+// e^{+2 pi i m/N} in FP64 for an exact integer m in [0, N): the root of unity
+// e^{2 pi i (m >> sh) / 2^tb} from the 2^tb-entry table `rou` (tb = log2 N - sh
+// <= 8) times e^{i delta}, delta = (m mod 2^sh) 2 pi / N < 2 pi / 2^tb, whose cos
+// and sin come from their Taylor series to delta^8 and delta^7 (truncation
+// below 1e-20). `step` = 2 pi / N.
+__device__ __forceinline__ double2 phase_of(const double2* rou, uint32_t m, uint32_t sh, double step) {
+    const double2 T = rou[m >> sh];
+    const double delta = (double)(m & ((1u << sh) - 1u)) * step;
+    const double z = -delta * delta;
+    const double s = fma(fma(fma(inv_fact(7), z, inv_fact(5)), z, inv_fact(3)), z, 1.0) * delta;
+    const double c = fma(fma(fma(fma(inv_fact(8), z, inv_fact(6)), z, inv_fact(4)), z, inv_fact(2)), z, 1.0);
+    return make_double2(T.x * c - T.y * s, T.x * s + T.y * c);
 }
+
+// Copy the 2^tb roots of unity (tb <= 8) to LDS.
+template <int NT>
+__device__ __forceinline__ void stage_rou(double2* dst, const double2* src, uint32_t tb) {
+    for (uint32_t i = threadIdx.x; i < (1u << tb); i += NT) dst[i] = gld(src + i);
+}
+
 
 // For each f in I': e_r = uhat_r[h_r(f)] * e^{-2 pi i (tau_r f mod N)/N} / Gtab[o_r(f)]
 // (the energy-concentration estimate of the one frequency assumed in the
 // bucket), x'_f = median_r Re e_r + i median_r Im e_r; then the K largest |x'_f|^2
 // (ties -> lower f), returned in ascending f. One workgroup per signal.
-// Dynamic LDS: phase tables, then P values and P frequencies (P = 2^ceil(log2 K)).
+// Dynamic LDS: P values and P frequencies (P = 2^ceil(log2 K)).
 template <int LMAX>
 __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t bc[4];
     __shared__ uint32_t s_sig[kMaxL], s_tau[kMaxL];
+    __shared__ double2 s_rou[kRouMax];
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
-    const uint32_t pc1 = d.pc1, pc2 = d.pc2, n1 = 1u << pc1, n2 = 1u << pc2, nph = n1 + n2 + (1u << d.pc3);
+    const uint32_t rsh = d.log2N - d.tb;
+    const double step = d.step;
     uint32_t P = 1;
     while (P < d.K) P <<= 1;
-    double2* ph = reinterpret_cast<double2*>(lds_raw);
-    float2* s_v = reinterpret_cast<float2*>(ph + nph);
+    float2* s_v = reinterpret_cast<float2*>(lds_raw);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + P);
     if (threadIdx.x == 0) bc[3] = min(gld(d.ctr), d.cap);
     if (threadIdx.x < L) {
         s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
         s_tau[threadIdx.x] = gld(d.tau + threadIdx.x);
     }
-    stage_phase_tables<kFinNT>(ph, d.ph, nph);
+    stage_rou<kFinNT>(s_rou, d.rou, d.tb);
     __syncthreads();
     const uint32_t n = bc[3];   // block-uniform by construction
     const uint32_t* cand = d.cand;
@@ -929,7 +927,7 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
                 const float2 g = gld(invG + gi);
                 const float2 uv = gld(uhat + (size_t)r * B + h);
                 const uint32_t k = (s_tau[r] * f) & maskN;
-                const double2 pk = phase_of(ph, k, pc1, pc2, n1, n2);   // e^{+2 pi i k/N}
+                const double2 pk = phase_of(s_rou, k, rsh, step);   // e^{+2 pi i k/N}
                 const float2 rot = make_float2((float)pk.x, -(float)pk.y);
                 const float2 e = cmul(cmul(uv, rot), g);
                 re[r] = e.x;
@@ -1046,25 +1044,25 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
 
 // ---------------------------------------------------------------- FP64 residual
 // E_res = mean_t |x_t - sum_k v_k e^{+2 pi i (t f_k mod N)/N}|^2 and
-// E_in = mean_t |x_t|^2 over the S residual samples. The outputs and the three
-// FP64 phase tables are staged in LDS (dynamic: tables, K values, K
-// frequencies); the phase of the exact integer t f mod N is the product of one
-// entry per table. Partial sums are reduced in a fixed order by the last
-// workgroup to finish.
+// E_in = mean_t |x_t|^2 over the S residual samples. The outputs are staged in
+// LDS (dynamic: K values, K frequencies); the phase of the exact integer
+// t f mod N is evaluated in FP64 (phase_of). Partial sums are reduced in a
+// fixed order by the last workgroup to finish.
 __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
     __shared__ double sh[2][kResNT / 64];
     __shared__ uint32_t is_last;
+    __shared__ double2 s_rou[kRouMax];
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
     const uint32_t K = d.K, maskN = d.maskN;
-    const uint32_t pc1 = d.pc1, pc2 = d.pc2, n1 = 1u << pc1, n2 = 1u << pc2, nph = n1 + n2 + (1u << d.pc3);
-    double2* ph = reinterpret_cast<double2*>(lds_raw);
-    float2* s_v = reinterpret_cast<float2*>(ph + nph);
+    const uint32_t rsh = d.log2N - d.tb;
+    const double step = d.step;
+    float2* s_v = reinterpret_cast<float2*>(lds_raw);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + K);
-    stage_phase_tables<kResNT>(ph, d.ph, nph);
+    stage_rou<kResNT>(s_rou, d.rou, d.tb);
     for (uint32_t k = threadIdx.x; k < K; k += kResNT) {
         const int64_t f = gld(io.out_idx + k);
         s_f[k] = f < 0 ? 0xFFFFFFFFu : (uint32_t)f;
@@ -1081,7 +1079,7 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
         for (uint32_t k = 0; k < K; ++k) {
             const uint32_t f = s_f[k];
             if (f == 0xFFFFFFFFu) continue;   // padding (uniform across the block)
-            const double2 p = phase_of(ph, (t * f) & maskN, pc1, pc2, n1, n2);
+            const double2 p = phase_of(s_rou, (t * f) & maskN, rsh, step);
             const float2 v = s_v[k];
             mr += (double)v.x * p.x - (double)v.y * p.y;
             mi += (double)v.x * p.y + (double)v.y * p.x;
@@ -1234,9 +1232,15 @@ hipError_t launch_fold(const Launch& a, uint32_t variant, uint32_t units, uint32
 }
 #undef SFFT_PF
 
-hipError_t launch_vote(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
+hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
     const uint32_t staged = lds_bytes ? 1u : 0u;
-    hipLaunchKernelGGL(vote_kernel, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged);
+    switch (lmax) {
+        case 4: hipLaunchKernelGGL(vote_kernel<4>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 8: hipLaunchKernelGGL(vote_kernel<8>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 16: hipLaunchKernelGGL(vote_kernel<16>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 32: hipLaunchKernelGGL(vote_kernel<32>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

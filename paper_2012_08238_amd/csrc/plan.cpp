@@ -57,9 +57,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.log2B = ilog2(R.B);
     R.log2M = ilog2(R.M);
     R.rsh = (R.log2N + 1) / 2;
-    R.pc1 = (R.log2N + 2) / 3;
-    R.pc2 = R.pc1;
-    R.pc3 = R.log2N - 2 * R.pc1;
+    R.tb = std::min<uint32_t>(8u, R.log2N);
     uint32_t lm = 4;
     while (lm < R.L) lm <<= 1;
     R.lmax = lm;
@@ -122,11 +120,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
     R.vote_lds = vbytes <= 65536u ? vbytes : 0u;
     R.resid_blocks = (R.S + kResNT - 1) / kResNT;
-    const uint32_t ph_bytes = ((1u << R.pc1) + (1u << R.pc2) + (1u << R.pc3)) * 16u;
     uint32_t P = 1;
     while (P < R.K) P <<= 1;
-    R.resid_lds = ph_bytes + R.K * 8u + R.K * 4u;
-    R.fin_lds = ph_bytes + P * 8u + P * 4u;
+    R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies
+    R.fin_lds = P * 8u + P * 4u;         // selected values, frequencies (sort size P)
     R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;
     R.fold_variant = fold_variant(R.mode, R.strip_lds, R.L << R.log2C, R.Mw4 / 4);
     *out = std::move(R);
@@ -161,19 +158,12 @@ void build_tables(const Resolved& R, HostTables* t) {
         t->rt_hi[2 * m] = cos(a);
         t->rt_hi[2 * m + 1] = sin(a);
     }
-    // device phase tables: e^{+2 pi i m/N} = T3[m >> (pc1+pc2)] T2[(m >> pc1) & .] T1[m & .]
-    {
-        const uint32_t n1 = 1u << R.pc1, n2 = 1u << R.pc2, n3 = 1u << R.pc3;
-        t->ph.resize(2 * (size_t)(n1 + n2 + n3));
-        size_t o = 0;
-        auto put = [&](uint64_t m) {
-            const double a = 2.0 * pi * (double)m / (double)N;
-            t->ph[o++] = cos(a);
-            t->ph[o++] = sin(a);
-        };
-        for (uint32_t j = 0; j < n1; ++j) put(j);
-        for (uint32_t j = 0; j < n2; ++j) put((uint64_t)j << R.pc1);
-        for (uint32_t j = 0; j < n3; ++j) put((uint64_t)j << (R.pc1 + R.pc2));
+    // roots of unity e^{2 pi i j / 2^tb} (device phases: table entry times a short series)
+    t->rou.resize(2u << R.tb);
+    for (uint32_t j = 0; j < (1u << R.tb); ++j) {
+        const double a = 2.0 * pi * (double)j / (double)(1u << R.tb);
+        t->rou[2 * j] = cos(a);
+        t->rou[2 * j + 1] = sin(a);
     }
     // gain table Gtab[o] = sum_n g_n e^{+2 pi i (n o mod N)/N}, exact FP64 sum
     t->gain.assign(M, std::complex<double>(0.0, 0.0));
@@ -264,7 +254,7 @@ TabLayout table_layout(const Resolved& R) {
     l.gT = take((size_t)R.B * R.Mw4 * 4);
     l.invG = take((size_t)R.M * 8);
     l.tw = take((size_t)R.B * 8);
-    l.ph = take((size_t)((1u << R.pc1) + (1u << R.pc2) + (1u << R.pc3)) * 16);
+    l.rou = take((size_t)16 << R.tb);
     l.total = off;
     return l;
 }
