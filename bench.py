@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 N, K, B, L, W, SNR_DB = 1 << 22, 100, 16384, 9, 131072, 20.0
 PLAN_SEED = 1
 HBM_PEAK_GBPS = 8000.0
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_strip_kernel_n22_k100_b64_counters.md")
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_strip_pf_kernel_n22_k100_b64_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_08238_amd", "csrc", "kernels.hip")
 
 
@@ -149,7 +149,7 @@ def main() -> int:
     traffic = committed_traffic(M)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "fold_strip_kernel", "alg_bytes_per_launch": alg,
+                "kernel": "fold_strip_pf_kernel (bucketization)", "alg_bytes_per_launch": alg,
                 "launch_us": round(fold_avg_s * 1e6, 2)}
     if traffic:
         roofline["effective_GBps"] = round(traffic / fold_avg_s / 1e9, 1)
