@@ -189,40 +189,59 @@ sfft_status sfft_execute_batch(const sfft_plan_t* plans, const void* const* x_de
 
 typedef struct {
     uint64_t submitted, completed, rejected, failed;
-    uint64_t batches;           /* GPU launches of batches */
-    double p50_latency_s, p99_latency_s, mean_latency_s;
-    size_t hbm_in_use, hbm_peak; /* admitted workspace + resident plan bytes */
-    uint64_t plan_cache_hits, plan_cache_misses, plan_cache_evictions;
+    uint64_t batches;           /* waves launched (one batched launch sequence each) */
+    uint64_t max_batch;         /* largest wave so far */
+    uint64_t max_waves_in_flight; /* most waves running at once (on different streams) */
+    double p50_latency_s, p99_latency_s, mean_latency_s;  /* submission -> completion observed */
+    size_t hbm_in_use, hbm_peak, hbm_budget; /* arena bytes held by workspaces + resident plan tables */
+    uint64_t plan_cache_hits, plan_cache_misses, plan_cache_evictions; /* table residency per admission */
 } sfft_server_stats;
 
-/* Serving loop: a worker thread admits submitted requests while their HBM
- * footprint (workspace, plus plan tables when not resident) fits in
- * hbm_budget_bytes and fewer than max_inflight requests are on the GPU, forms
- * batches from what is admitted (continuous batching: requests arriving while
- * others run join the next batch), and runs batches on n_streams streams so
- * that they overlap. Plans are cached by parameter set and kept resident. */
+/* Serving loop (continuous batching of sFFT requests of any N, K, B, L, w).
+ * The server reserves one device arena of hbm_budget_bytes on the current
+ * device; request workspaces and resident plan tables are placed in it. A
+ * worker thread admits queued requests in submission order while the head
+ * request's footprint (its workspace, plus its plan tables when they are not
+ * resident) fits in the arena and fewer than max_inflight requests are
+ * admitted or running; idle resident tables are evicted least recently used
+ * first when space is short. Whenever one of the n_streams streams is free,
+ * every admitted request leaves as one wave: a batched launch sequence (as
+ * sfft_batch_run) on that stream. Requests that arrive while waves run are
+ * batched into the next wave, and waves on different streams overlap on the
+ * device. Each request's result is bitwise the one sfft_execute_ex gives for
+ * its parameter set alone. Plans are cached by parameter set (host tables kept
+ * for the server's lifetime). max_inflight in [1, 1024], n_streams in [1, 16],
+ * hbm_budget_bytes >= 1 MiB. */
 sfft_status sfft_server_create(sfft_server_t* out, size_t hbm_budget_bytes, int32_t max_inflight,
                                int32_t n_streams);
 
+/* Build and cache the plan of a parameter set without queueing work (the first
+ * request of a parameter set otherwise pays for its FP64 table build). Host
+ * work only; the tables become resident with the first admitted request. */
+sfft_status sfft_server_prepare(sfft_server_t s, const sfft_params* p);
+
 /* Queue one request. x_dev, out_idx, out_val (and out_resid, may be NULL) as in
- * sfft_execute_ex; they must stay valid until the ticket completes. Returns
- * SFFT_E_INVALID for a bad parameter set (only this request is rejected) and
- * SFFT_E_NOMEM if the request alone can never fit the budget. */
+ * sfft_execute_ex; they must stay valid and x_dev unchanged until the ticket
+ * completes. Returns SFFT_E_INVALID for a bad parameter set or pointer (only
+ * this request is refused) and SFFT_E_NOMEM if the request alone can never fit
+ * the budget. Thread safe. */
 sfft_status sfft_server_submit(sfft_server_t s, const sfft_params* p, const void* x_dev,
                                int64_t* out_idx, void* out_val, double* out_resid, uint64_t* ticket);
 
-/* Non-blocking status of a ticket: *done = 1 when its outputs are complete on
- * the device; *latency_s = completion - submission time; *req_status the
- * request's own status. A completed ticket can be polled until it is released. */
+/* Non-blocking status of a ticket: *done = 1 once its outputs are complete on
+ * the device; then *latency_s = completion - submission time and *req_status
+ * the request's own status (SFFT_OK or SFFT_E_DEVICE). Unknown or released
+ * tickets give SFFT_E_NOTFOUND. */
 sfft_status sfft_server_poll(sfft_server_t s, uint64_t ticket, int32_t* done, double* latency_s,
                              int32_t* req_status);
 
-/* Block until the ticket completes, then as sfft_server_poll, and forget it. */
+/* Block until the ticket completes, report it as sfft_server_poll and release
+ * it. One waiter per ticket. */
 sfft_status sfft_server_wait(sfft_server_t s, uint64_t ticket, double* latency_s, int32_t* req_status);
 
 sfft_status sfft_server_stats_get(sfft_server_t s, sfft_server_stats* out);
 
-/* Drain all work and release everything. */
+/* Run every queued request to completion, then release the arena, streams and plans. */
 sfft_status sfft_server_destroy(sfft_server_t s);
 
 /* ---- misc ------------------------------------------------------------------------- */

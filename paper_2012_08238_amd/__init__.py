@@ -101,6 +101,12 @@ class Plan:
         del keep
         self.desc = self.describe()
 
+    @classmethod
+    def from_params(cls, params: PlanParams) -> "Plan":
+        kw = {k: getattr(params, k) for k in ("seed", "d", "vote_threshold", "n_resid", "gauss_c", "flags",
+                                               "strip_cols", "sigma", "tau")}
+        return cls(params.N, params.K, params.B, params.L, params.w, **kw)
+
     @property
     def handle(self) -> C.c_void_p:
         return self._h
@@ -223,8 +229,15 @@ class Server:
               "sfft_server_create")
         self._h = h
 
-    def submit(self, params: PlanParams, x, out_idx, out_val, out_resid=None) -> int:
+    def prepare(self, params: PlanParams):
+        """Build and cache the plan of `params`; returns a handle `submit` accepts."""
         p, keep = params.to_c()
+        check(load().sfft_server_prepare(self._h, C.byref(p)), "sfft_server_prepare")
+        return (p, keep)
+
+    def submit(self, params, x, out_idx, out_val, out_resid=None) -> int:
+        """Queue one request; `params` is a PlanParams or a handle from `prepare`."""
+        p, keep = params if isinstance(params, tuple) else params.to_c()
         t = C.c_uint64()
         check(load().sfft_server_submit(self._h, C.byref(p), _ptr(x), _ptr(out_idx), _ptr(out_val),
                                         _ptr(out_resid), C.byref(t)), "sfft_server_submit")

@@ -44,9 +44,10 @@ class Trace(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
-                ("failed", C.c_uint64), ("batches", C.c_uint64),
+                ("failed", C.c_uint64), ("batches", C.c_uint64), ("max_batch", C.c_uint64),
+                ("max_waves_in_flight", C.c_uint64),
                 ("p50_latency_s", C.c_double), ("p99_latency_s", C.c_double), ("mean_latency_s", C.c_double),
-                ("hbm_in_use", C.c_size_t), ("hbm_peak", C.c_size_t),
+                ("hbm_in_use", C.c_size_t), ("hbm_peak", C.c_size_t), ("hbm_budget", C.c_size_t),
                 ("plan_cache_hits", C.c_uint64), ("plan_cache_misses", C.c_uint64),
                 ("plan_cache_evictions", C.c_uint64)]
 
@@ -74,6 +75,7 @@ SIGNATURES = [
     ("sfft_execute_batch", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
     ("sfft_server_create", C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int32, C.c_int32]),
+    ("sfft_server_prepare", C.c_int, [C.c_void_p, C.POINTER(Params)]),
     ("sfft_server_submit", C.c_int, [C.c_void_p, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.POINTER(C.c_uint64)]),
     ("sfft_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double),

@@ -4,8 +4,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <map>
-#include <set>
 #include <mutex>
 #include <vector>
 
@@ -13,22 +11,9 @@
 #include "host.hpp"
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "steps.hpp"
 
 using namespace sfft;
-
-namespace {
-
-enum StepKind { kFold = 0, kFft = 1, kVote = 2, kFin = 3, kRes = 4 };
-
-struct Step {
-    StepKind kind;
-    uint32_t param;   // fold mode / log2B / lmax / vote staged flag
-    uint32_t units;
-    uint32_t lds;
-    size_t prefix_off;  // index into the prefix array of n+1 entries
-};
-
-}  // namespace
 
 struct sfft_batch_s {
     int device = 0;
@@ -74,26 +59,9 @@ void batch_free(sfft_batch_t b) {
 }
 
 // part 0: bucketization steps, part 1: the others
-sfft_status issue_steps(sfft_batch_t b, hipStream_t s, int part) {
-    for (const Step& st : b->steps) {
-        if ((st.kind == kFold) != (part == 0)) continue;
-        Launch a{};
-        a.descs = b->d_descs;
-        a.ios = b->d_ios;
-        a.prefix = b->d_prefix + st.prefix_off;
-        a.nsig = (uint32_t)b->n;
-        a.xcd_order = st.kind == kFold ? b->xcd_order : 0u;
-        hipError_t e = hipSuccess;
-        switch (st.kind) {
-            case kFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
-            case kFft: e = launch_fft_select(a, st.param, st.units, s); break;
-            case kVote: e = launch_vote(a, st.param >> 8, st.units, st.lds, s); break;
-            case kFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
-            case kRes: e = launch_residual(a, st.units, st.lds, s); break;
-        }
-        if (e != hipSuccess) return hip_fail(e, "batched launch");
-    }
-    return SFFT_OK;
+sfft_status issue_part(sfft_batch_t b, hipStream_t s, int part) {
+    const hipError_t e = issue_steps(b->steps, b->d_descs, b->d_ios, b->d_prefix, (uint32_t)b->n, b->xcd_order, part, s);
+    return e == hipSuccess ? SFFT_OK : hip_fail(e, "batched launch");
 }
 
 }  // namespace
@@ -147,56 +115,9 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
     }
     // one launch per stage and variant, each with its own prefix over all n signals
     std::vector<uint32_t> prefix;
-    auto add_step = [&](StepKind kind, uint32_t param, uint32_t lds, auto units_of) {
-        const size_t off = prefix.size();
-        uint32_t acc = 0;
-        prefix.push_back(0);
-        for (int32_t i = 0; i < n; ++i) {
-            acc += units_of(plan_resolved(plans[i]));
-            prefix.push_back(acc);
-        }
-        if (acc == 0) {
-            prefix.resize(off);
-            return;
-        }
-        b->steps.push_back(Step{kind, param, acc, lds, off});
-    };
-    std::set<uint32_t> variants;
-    for (int32_t i = 0; i < n; ++i) variants.insert(plan_resolved(plans[i]).fold_variant);
-    for (const uint32_t v : variants) {
-        uint32_t lds = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            const Resolved& R = plan_resolved(plans[i]);
-            if (R.fold_variant == v && R.mode == 1) lds = std::max(lds, R.strip_lds);
-        }
-        add_step(kFold, v, lds, [&](const Resolved& R) { return R.fold_variant == v ? R.fold_units : 0u; });
-    }
-    for (uint32_t lb = 1; lb <= 14; ++lb)
-        add_step(kFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
-    for (uint32_t staged = 0; staged < 2; ++staged)
-        for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
-            auto in_group = [&](const Resolved& R) { return (R.vote_lds > 0) == (staged == 1) && R.lmax == lm; };
-            uint32_t lds = 0;
-            for (int32_t i = 0; i < n; ++i) {
-                const Resolved& R = plan_resolved(plans[i]);
-                if (in_group(R)) lds = std::max(lds, R.vote_lds);
-            }
-            add_step(kVote, staged | (lm << 8), staged ? lds : 0,
-                     [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
-        }
-    auto max_of = [&](auto pred, auto field) {
-        uint32_t v = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            const Resolved& R = plan_resolved(plans[i]);
-            if (pred(R)) v = std::max(v, field(R));
-        }
-        return v;
-    };
-    for (uint32_t lm = 4; lm <= 32; lm <<= 1)
-        add_step(kFin, lm, max_of([&](const Resolved& R) { return R.lmax == lm; }, [](const Resolved& R) { return R.fin_lds; }),
-                 [&](const Resolved& R) { return R.lmax == lm ? 1u : 0u; });
-    add_step(kRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
-             [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
+    std::vector<const Resolved*> sig(n);
+    for (int32_t i = 0; i < n; ++i) sig[i] = &plan_resolved(plans[i]);
+    plan_steps(sig, &b->steps, &prefix);
     b->xcd_order = 1;
     for (int32_t i = 0; i < n; ++i) b->xcd_order &= plan_resolved(plans[i]).xcd_order;
     if (hipMalloc(&b->d_prefix, prefix.size() * 4) != hipSuccess) {
@@ -252,7 +173,7 @@ static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* 
         if (b->exec[part]) continue;
         e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        const sfft_status st = issue_steps(b, b->cap_stream, part);
+        const sfft_status st = issue_part(b, b->cap_stream, part);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (st != SFFT_OK) {

@@ -159,15 +159,7 @@ sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
     if (hipMalloc(&pl->d_tab, tl.total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device tables"));
     if (hipMalloc(&pl->d_ws, wl.total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device workspace"));
     if (hipMalloc(&pl->d_desc, sizeof(SigDesc)) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device descriptor"));
-    std::vector<char> h(tl.total, 0);
-    memcpy(&h[tl.sigma], Rr.sigma.data(), Rr.L * 4);
-    memcpy(&h[tl.sigma_inv], Rr.sigma_inv.data(), Rr.L * 4);
-    memcpy(&h[tl.tau], Rr.tau.data(), Rr.L * 4);
-    if (Rr.S) memcpy(&h[tl.tpos], Rr.tpos.data(), (size_t)Rr.S * 4);
-    memcpy(&h[tl.gT], T.gT.data(), T.gT.size() * 4);
-    memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
-    memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
-    memcpy(&h[tl.rou], T.rou.data(), T.rou.size() * 8);
+    const std::vector<char> h = pack_tables(Rr, T);
     e = hipMemcpy(pl->d_tab, h.data(), tl.total, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "table upload"));
     e = hipMemset(pl->d_ws, 0, wl.total);

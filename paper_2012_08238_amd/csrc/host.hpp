@@ -88,4 +88,7 @@ struct TabLayout {
 };
 TabLayout table_layout(const Resolved& R);
 
+// The device table image of a plan (table_layout(R).total bytes), ready to upload.
+std::vector<char> pack_tables(const Resolved& R, const HostTables& T);
+
 }  // namespace sfft

@@ -1,5 +1,6 @@
 // Host-side plan logic: validation, permutations, FP64 tables.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <thread>
@@ -257,6 +258,24 @@ TabLayout table_layout(const Resolved& R) {
     l.rou = take((size_t)16 << R.tb);
     l.total = off;
     return l;
+}
+
+}  // namespace sfft
+
+namespace sfft {
+
+std::vector<char> pack_tables(const Resolved& R, const HostTables& T) {
+    const TabLayout tl = table_layout(R);
+    std::vector<char> h(tl.total, 0);
+    memcpy(&h[tl.sigma], R.sigma.data(), (size_t)R.L * 4);
+    memcpy(&h[tl.sigma_inv], R.sigma_inv.data(), (size_t)R.L * 4);
+    memcpy(&h[tl.tau], R.tau.data(), (size_t)R.L * 4);
+    if (R.S) memcpy(&h[tl.tpos], R.tpos.data(), (size_t)R.S * 4);
+    memcpy(&h[tl.gT], T.gT.data(), T.gT.size() * 4);
+    memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
+    memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
+    memcpy(&h[tl.rou], T.rou.data(), T.rou.size() * 8);
+    return h;
 }
 
 }  // namespace sfft

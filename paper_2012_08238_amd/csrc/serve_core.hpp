@@ -1,0 +1,447 @@
+// Scheduler of the serving loop, independent of the device: admission of
+// requests by their device-memory footprint inside one arena, resident plan
+// tables with least-recently-used eviction, and continuous batching over a
+// fixed set of execution slots (one stream each). The device side is an
+// Executor; the library drives HIP through it and the tests drive a fake.
+//
+// Request life: queued (FIFO) -> admitted (arena ranges held; waits for a free
+// slot) -> running (part of a wave launched on a slot) -> done. Whenever a slot
+// is free, every admitted request (up to max_wave) leaves as one wave, so
+// requests that arrive while earlier waves run are batched together and their
+// waves overlap on the device.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <iterator>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+namespace sfft {
+namespace serve {
+
+// First-fit allocator of byte ranges of one arena. Released ranges merge with
+// free neighbours, so an empty arena is always one free range.
+class RangeAllocator {
+public:
+    explicit RangeAllocator(size_t capacity, size_t align = 256)
+        : align_(align), cap_(capacity / align * align) {
+        if (cap_) free_[0] = cap_;
+    }
+    size_t round_up(size_t n) const { return (std::max<size_t>(n, 1) + align_ - 1) / align_ * align_; }
+    bool alloc(size_t n, size_t* off) {
+        n = round_up(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, start = it->first + n;
+            free_.erase(it);
+            if (rest) free_[start] = rest;
+            used_ += n;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = round_up(n);
+        size_t start = off, len = n;
+        auto next = free_.lower_bound(off);
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        if (next != free_.end() && off + n == next->first) {
+            len += next->second;
+            free_.erase(next);
+        }
+        free_[start] = len;
+        used_ -= n;
+    }
+    size_t capacity() const { return cap_; }
+    size_t in_use() const { return used_; }
+    size_t free_ranges() const { return free_.size(); }
+    size_t largest_free() const {
+        size_t m = 0;
+        for (const auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+private:
+    size_t align_, cap_, used_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+template <class Payload>
+struct WaveItem {
+    uint64_t ticket;
+    uint32_t plan;     // plan id
+    size_t tab_off;    // arena offset of the plan's tables
+    size_t ws_off;     // arena offset of the request's workspace
+    Payload io;        // caller buffers of the request
+};
+
+// Device side of the server. All calls come from the scheduler's worker thread.
+template <class Payload>
+class Executor {
+public:
+    virtual ~Executor() = default;
+    virtual void thread_init() {}
+    // copy plan tables into the arena at `off`, complete on return; 0 = ok
+    virtual int upload(uint32_t plan, size_t off) = 0;
+    // start a wave on `slot`; 0 = ok, negative = the wave failed to launch
+    virtual int launch(int slot, const std::vector<WaveItem<Payload>>& items) = 0;
+    // 1 = the slot's wave finished, 0 = still running, negative = device error
+    virtual int query(int slot) = 0;
+};
+
+struct CoreStats {
+    uint64_t submitted = 0, completed = 0, rejected = 0, failed = 0, waves = 0;
+    uint64_t max_wave_seen = 0;
+    uint64_t max_busy_slots = 0;   // most waves in flight at once
+    double p50 = 0, p99 = 0, mean = 0;
+    size_t in_use = 0, peak = 0;
+    uint64_t hits = 0, misses = 0, evictions = 0;
+};
+
+enum : int { kCoreOk = 0, kCoreInvalid = -1, kCoreNoMem = -2, kCoreNotFound = -6 };
+
+template <class Payload>
+class ServerCore {
+public:
+    ServerCore(Executor<Payload>* ex, size_t arena_bytes, int max_inflight, int slots, int max_wave)
+        : ex_(ex), arena_(arena_bytes), max_inflight_(std::max(1, max_inflight)),
+          max_wave_(std::max(1, max_wave)), slot_(std::max(1, slots)) {
+        worker_ = std::thread([this] { run(); });
+    }
+    ~ServerCore() { stop(); }
+    ServerCore(const ServerCore&) = delete;
+    ServerCore& operator=(const ServerCore&) = delete;
+
+    size_t arena_capacity() const { return arena_.capacity(); }
+
+    // Register plan `id` with its table size (ids are the caller's).
+    void add_plan(uint32_t id, size_t tab_bytes) {
+        std::lock_guard<std::mutex> lk(mu_);
+        plans_.emplace(id, PlanState{tab_bytes});
+    }
+
+    // Queue a request; kCoreNoMem if it can never fit, kCoreNotFound for an unknown plan.
+    int submit(uint32_t plan, size_t ws_bytes, const Payload& io, uint64_t* ticket) {
+        const double t0 = now();
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = plans_.find(plan);
+        if (it == plans_.end()) {
+            ++st_.rejected;
+            return kCoreNotFound;
+        }
+        if (arena_.round_up(it->second.tab_bytes) + arena_.round_up(ws_bytes) > arena_.capacity()) {
+            ++st_.rejected;
+            return kCoreNoMem;
+        }
+        const uint64_t t = next_ticket_++;
+        Req& r = reqs_[t];
+        r.plan = plan;
+        r.ws_bytes = ws_bytes;
+        r.io = io;
+        r.t_submit = t0;
+        queue_.push_back(t);
+        ++st_.submitted;
+        *ticket = t;
+        cv_work_.notify_one();
+        return kCoreOk;
+    }
+
+    int poll(uint64_t ticket, int* done, double* latency, int* status) {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it == reqs_.end()) return kCoreNotFound;
+        fill(it->second, done, latency, status);
+        return kCoreOk;
+    }
+
+    // Block until the ticket is done, report it and forget it. One waiter per ticket.
+    int wait(uint64_t ticket, double* latency, int* status) {
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it == reqs_.end()) return kCoreNotFound;
+        Req& r = it->second;  // references survive rehashing by concurrent submits; iterators do not
+        cv_done_.wait(lk, [&] { return r.state == kDone; });
+        int done = 0;
+        fill(r, &done, latency, status);
+        reqs_.erase(ticket);
+        return kCoreOk;
+    }
+
+    CoreStats stats() {
+        std::lock_guard<std::mutex> lk(mu_);
+        CoreStats s = st_;
+        s.in_use = arena_.in_use();
+        if (!lat_.empty()) {
+            std::vector<double> v = lat_;
+            std::sort(v.begin(), v.end());
+            auto q = [&](double p) {
+                const double k = (v.size() - 1) * p;
+                const size_t lo = (size_t)k, hi = std::min(lo + 1, v.size() - 1);
+                return v[lo] + (v[hi] - v[lo]) * (k - (double)lo);
+            };
+            s.p50 = q(0.5);
+            s.p99 = q(0.99);
+            double sum = 0;
+            for (double x : v) sum += x;
+            s.mean = sum / (double)v.size();
+        }
+        return s;
+    }
+
+    // Drain every queued request, then end the worker.
+    void stop() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (stopped_) return;
+            stop_ = true;
+        }
+        cv_work_.notify_all();
+        if (worker_.joinable()) worker_.join();
+        std::lock_guard<std::mutex> lk(mu_);
+        stopped_ = true;
+    }
+
+private:
+    enum State { kQueued, kAdmitted, kRunning, kDone };
+    struct Req {
+        uint32_t plan = 0;
+        size_t ws_bytes = 0, ws_off = 0;
+        Payload io{};
+        double t_submit = 0, t_done = 0;
+        int status = 0;
+        State state = kQueued;
+    };
+    struct PlanState {
+        size_t tab_bytes = 0;
+        bool resident = false;
+        size_t off = 0;
+        uint32_t refs = 0;       // admitted + running requests
+        uint64_t last_use = 0;
+    };
+    struct Slot {
+        bool busy = false;
+        std::vector<uint64_t> tickets;
+    };
+
+    static double now() {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    }
+
+    void fill(const Req& r, int* done, double* latency, int* status) const {
+        if (done) *done = r.state == kDone;
+        if (latency) *latency = r.state == kDone ? r.t_done - r.t_submit : 0.0;
+        if (status) *status = r.state == kDone ? r.status : 0;
+    }
+
+    void note_peak() { st_.peak = std::max(st_.peak, arena_.in_use()); }
+
+    void evict(uint32_t id, PlanState& p) {
+        arena_.release(p.off, p.tab_bytes);
+        p.resident = false;
+        uploads_.erase(std::remove(uploads_.begin(), uploads_.end(), id), uploads_.end());
+        ++st_.evictions;
+    }
+
+    // Least recently used resident plan with no request, other than `keep`; false if none.
+    bool lru_idle(uint32_t keep, uint32_t* id) {
+        const PlanState* best = nullptr;
+        for (const auto& kv : plans_) {
+            const PlanState& p = kv.second;
+            if (kv.first == keep || !p.resident || p.refs) continue;
+            if (!best || p.last_use < best->last_use) {
+                best = &p;
+                *id = kv.first;
+            }
+        }
+        return best != nullptr;
+    }
+
+    bool try_place(Req& r, PlanState& p) {
+        const bool need_tab = !p.resident;
+        size_t tab_off = 0, ws_off = 0;
+        if (need_tab && !arena_.alloc(p.tab_bytes, &tab_off)) return false;
+        if (!arena_.alloc(r.ws_bytes, &ws_off)) {
+            if (need_tab) arena_.release(tab_off, p.tab_bytes);
+            return false;
+        }
+        if (need_tab) {
+            p.resident = true;
+            p.off = tab_off;
+            uploads_.push_back(r.plan);
+            ++st_.misses;
+        } else {
+            ++st_.hits;
+        }
+        r.ws_off = ws_off;
+        return true;
+    }
+
+    size_t inflight() const {
+        size_t n = admitted_.size();
+        for (const Slot& s : slot_) n += s.tickets.size();
+        return n;
+    }
+    bool any_busy() const {
+        for (const Slot& s : slot_)
+            if (s.busy) return true;
+        return false;
+    }
+
+    // FIFO admission: the head waits until it fits (no overtaking, no starvation).
+    void admit() {
+        while (!queue_.empty() && inflight() < (size_t)max_inflight_) {
+            const uint64_t t = queue_.front();
+            Req& r = reqs_[t];
+            PlanState& p = plans_[r.plan];
+            bool ok = try_place(r, p);
+            uint32_t victim = 0;
+            while (!ok && lru_idle(r.plan, &victim)) {
+                evict(victim, plans_[victim]);
+                ok = try_place(r, p);
+            }
+            if (!ok && p.resident && !p.refs && admitted_.empty() && !any_busy()) {
+                // nothing else holds the arena: re-place the head's own tables too
+                evict(r.plan, p);
+                ok = try_place(r, p);
+            }
+            if (!ok) break;
+            p.refs++;
+            p.last_use = ++tick_;
+            r.state = kAdmitted;
+            queue_.pop_front();
+            admitted_.push_back(t);
+            note_peak();
+        }
+    }
+
+    void complete(uint64_t t, int status) {
+        Req& r = reqs_[t];
+        PlanState& p = plans_[r.plan];
+        arena_.release(r.ws_off, r.ws_bytes);
+        p.refs--;
+        r.status = status;
+        r.t_done = now();
+        r.state = kDone;
+        if (status == 0) {
+            ++st_.completed;
+            lat_.push_back(r.t_done - r.t_submit);
+        } else {
+            ++st_.failed;
+        }
+    }
+
+    void finish_slot(int s, int status) {
+        for (uint64_t t : slot_[s].tickets) complete(t, status);
+        slot_[s].tickets.clear();
+        slot_[s].busy = false;
+        cv_done_.notify_all();
+    }
+
+    void run() {
+        ex_->thread_init();
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            for (int s = 0; s < (int)slot_.size(); ++s) {
+                if (!slot_[s].busy) continue;
+                const int q = ex_->query(s);
+                if (q != 0) finish_slot(s, q > 0 ? 0 : q);
+            }
+            admit();
+            int free_slot = -1;
+            for (int s = 0; s < (int)slot_.size() && free_slot < 0; ++s)
+                if (!slot_[s].busy) free_slot = s;
+            if (!admitted_.empty() && free_slot >= 0) {
+                launch_wave(lk, free_slot);
+                continue;
+            }
+            const bool busy = any_busy();
+            if (stop_ && queue_.empty() && admitted_.empty() && !busy) break;
+            if (busy) {
+                // completions are observed by polling the slots
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else if (queue_.empty()) {
+                cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
+            } else {
+                // a head that cannot be placed with nothing running does not occur
+                // (the arena then holds idle tables only); back off all the same
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(100));
+                lk.lock();
+            }
+        }
+    }
+
+    void launch_wave(std::unique_lock<std::mutex>& lk, int s) {
+        const size_t n = std::min(admitted_.size(), (size_t)max_wave_);
+        std::vector<WaveItem<Payload>> items;
+        items.reserve(n);
+        for (size_t i = 0; i < n; ++i) {
+            const uint64_t t = admitted_[i];
+            Req& r = reqs_[t];
+            r.state = kRunning;
+            items.push_back(WaveItem<Payload>{t, r.plan, plans_[r.plan].off, r.ws_off, r.io});
+            slot_[s].tickets.push_back(t);
+        }
+        admitted_.erase(admitted_.begin(), admitted_.begin() + (std::ptrdiff_t)n);
+        slot_[s].busy = true;
+        std::vector<std::pair<uint32_t, size_t>> up;
+        for (uint32_t id : uploads_) up.emplace_back(id, plans_[id].off);
+        uploads_.clear();
+        lk.unlock();
+        int rc = 0;
+        for (const auto& u : up)
+            if (rc == 0) rc = ex_->upload(u.first, u.second);
+        if (rc == 0) rc = ex_->launch(s, items);
+        lk.lock();
+        ++st_.waves;
+        st_.max_wave_seen = std::max<uint64_t>(st_.max_wave_seen, n);
+        uint64_t busy = 0;
+        for (const Slot& o : slot_) busy += o.busy;
+        if (rc == 0) st_.max_busy_slots = std::max(st_.max_busy_slots, busy);
+        if (rc != 0) {
+            // tables that may not have arrived are uploaded again before the next wave
+            for (const auto& u : up)
+                if (plans_[u.first].resident && plans_[u.first].off == u.second) uploads_.push_back(u.first);
+            finish_slot(s, rc);
+        }
+    }
+
+    Executor<Payload>* ex_;
+    RangeAllocator arena_;
+    const int max_inflight_, max_wave_;
+    std::vector<Slot> slot_;
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    std::unordered_map<uint64_t, Req> reqs_;
+    std::map<uint32_t, PlanState> plans_;
+    std::deque<uint64_t> queue_, admitted_;
+    std::vector<uint32_t> uploads_;
+    std::vector<double> lat_;
+    CoreStats st_;
+    uint64_t next_ticket_ = 1, tick_ = 0;
+    bool stop_ = false, stopped_ = false;
+    std::thread worker_;
+};
+
+}  // namespace serve
+}  // namespace sfft

@@ -1,0 +1,92 @@
+// Stage plan of a set of signals launched together (see steps.hpp).
+#include "steps.hpp"
+
+#include <algorithm>
+#include <set>
+
+#include "kernels.hpp"
+
+namespace sfft {
+
+namespace {
+constexpr uint32_t kFftLog2Max = 14;   // one-workgroup FFT sizes 2^1 .. 2^14
+constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
+}  // namespace
+
+size_t max_prefix_entries(size_t n) {
+    // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
+    // vote: 2 x kLmaxCount; finalize: kLmaxCount; residual: 1
+    const size_t launches = n + kFftLog2Max + 3 * kLmaxCount + 1;
+    return launches * (n + 1);
+}
+
+void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* steps, std::vector<uint32_t>* prefix) {
+    const size_t n = sig.size();
+    auto add_step = [&](StepKind kind, uint32_t param, uint32_t lds, auto units_of) {
+        const size_t off = prefix->size();
+        uint32_t acc = 0;
+        prefix->push_back(0);
+        for (size_t i = 0; i < n; ++i) {
+            acc += units_of(*sig[i]);
+            prefix->push_back(acc);
+        }
+        if (acc == 0) {
+            prefix->resize(off);
+            return;
+        }
+        steps->push_back(Step{kind, param, acc, lds, off});
+    };
+    auto max_of = [&](auto pred, auto field) {
+        uint32_t v = 0;
+        for (size_t i = 0; i < n; ++i)
+            if (pred(*sig[i])) v = std::max(v, field(*sig[i]));
+        return v;
+    };
+    std::set<uint32_t> variants;
+    for (size_t i = 0; i < n; ++i) variants.insert(sig[i]->fold_variant);
+    for (const uint32_t v : variants) {
+        const uint32_t lds = max_of([&](const Resolved& R) { return R.fold_variant == v && R.mode == 1; },
+                                    [](const Resolved& R) { return R.strip_lds; });
+        add_step(kStepFold, v, lds, [&](const Resolved& R) { return R.fold_variant == v ? R.fold_units : 0u; });
+    }
+    for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)
+        add_step(kStepFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
+    for (uint32_t staged = 0; staged < 2; ++staged)
+        for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
+            auto in_group = [&](const Resolved& R) { return (R.vote_lds > 0) == (staged == 1) && R.lmax == lm; };
+            const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_lds; });
+            add_step(kStepVote, staged | (lm << 8), staged ? lds : 0,
+                     [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
+        }
+    for (uint32_t lm = 4; lm <= 32; lm <<= 1)
+        add_step(kStepFin, lm,
+                 max_of([&](const Resolved& R) { return R.lmax == lm; }, [](const Resolved& R) { return R.fin_lds; }),
+                 [&](const Resolved& R) { return R.lmax == lm ? 1u : 0u; });
+    add_step(kStepRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
+             [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
+}
+
+hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, const IoDesc* d_ios,
+                       const uint32_t* d_prefix, uint32_t n, uint32_t xcd_order, int part, hipStream_t s) {
+    for (const Step& st : steps) {
+        if (part >= 0 && (st.kind == kStepFold) != (part == 0)) continue;
+        Launch a{};
+        a.descs = d_descs;
+        a.ios = d_ios;
+        a.prefix = d_prefix + st.prefix_off;
+        a.nsig = n;
+        a.xcd_order = st.kind == kStepFold ? xcd_order : 0u;
+        hipError_t e = hipSuccess;
+        switch (st.kind) {
+            case kStepFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
+            case kStepFft: e = launch_fft_select(a, st.param, st.units, s); break;
+            case kStepVote: e = launch_vote(a, st.param >> 8, st.units, st.lds, s); break;
+            case kStepFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
+            case kStepRes: e = launch_residual(a, st.units, st.lds, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace sfft
