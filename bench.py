@@ -11,8 +11,10 @@ output, residual). value = signals recovered per second.
 
 Also reported: the bucketization kernel's roofline against MI355X HBM peak
 (algorithmic bytes 8 N (1 - (1 - w/N)^L) per signal, the sampled fraction of
-Table 2 with log N -> L), p50/p99 latency of single requests, FP32-vs-FP64
-parity on a sample, and the FP64 CPU oracle timed on the host.
+Table 2 with log N -> L); p50/p99 latency through the serving loop under
+Poisson arrivals and its saturated throughput; the plain single-signal path's
+throughput; single-request latency; FP32-vs-FP64 parity on a sample; and the
+FP64 CPU oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -67,6 +69,63 @@ def percentile(v, q):
     return v[lo] + (v[hi] - v[lo]) * (k - lo)
 
 
+def serve_measure(S, torch, dev, xs, truth, args) -> dict:
+    """Serving loop on the resident signals: Poisson arrivals at --serve-rate
+    requests/s for --serve-seconds (latency = submission to completion), then a
+    saturated burst (every request queued at once) for served throughput."""
+    import numpy as np
+    M = len(xs)
+    srv = S.Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_inflight=args.serve_inflight,
+                   n_streams=args.serve_streams)
+    h = srv.prepare(S.PlanParams(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols))
+    n = max(1, int(args.serve_rate * args.serve_seconds))
+    nb = args.serve_burst
+    idx = torch.empty((max(n, nb), K), dtype=torch.int64, device=dev)
+    val = torch.empty((max(n, nb), K), dtype=torch.complex64, device=dev)
+    res = torch.empty((max(n, nb), 2), dtype=torch.float64, device=dev)
+    # warm the tables into the arena
+    srv.wait(srv.submit(h, xs[0], idx[0], val[0], res[0]))
+    rng = np.random.default_rng(2000)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, n))
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(n):
+        target = t0 + arrivals[i]
+        while True:
+            d = target - time.perf_counter()
+            if d <= 0:
+                break
+            if d > 2e-4:
+                time.sleep(d - 1.5e-4)
+        tickets.append(srv.submit(h, xs[i % M], idx[i], val[i], res[i]))
+    lats = [srv.wait(t)[0] for t in tickets]
+    t_open = time.perf_counter() - t0
+    open_stats = srv.stats()
+    ok = sum(set(idx[i].tolist()) == set(truth[i % M][0].tolist()) for i in range(min(n, 256)))
+    # saturated: queue nb requests at once, time until the last completes
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tickets = [srv.submit(h, xs[i % M], idx[i], val[i], res[i]) for i in range(nb)]
+    for t in tickets:
+        srv.wait(t)
+    t_sat = time.perf_counter() - t1
+    st = srv.stats()
+    srv.close()
+    lat_ms = sorted(x * 1e3 for x in lats)
+    return {
+        "poisson": {"rate_req_s": args.serve_rate, "requests": n, "seconds": round(t_open, 3),
+                    "p50_ms": round(percentile(lat_ms, 0.5), 4), "p99_ms": round(percentile(lat_ms, 0.99), 4),
+                    "mean_ms": round(sum(lat_ms) / len(lat_ms), 4),
+                    "waves": open_stats["batches"] - 1, "max_wave": open_stats["max_batch"],
+                    "exact_support_sampled": f"{ok}/{min(n, 256)}"},
+        "saturated": {"requests": nb, "signals_per_s": round(nb / t_sat, 1),
+                      "waves": st["batches"] - open_stats["batches"], "max_wave": st["max_batch"],
+                      "max_waves_in_flight": st["max_waves_in_flight"]},
+        "config": {"hbm_budget_gib": args.serve_budget_gib, "max_inflight": args.serve_inflight,
+                   "streams": args.serve_streams, "hbm_peak_bytes": st["hbm_peak"]},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +137,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strip-cols", type=int, default=0, help="bucketization tile width (0 = plan default)")
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
+    ap.add_argument("--single-passes", type=int, default=3, help="passes over the batch through sfft_execute alone")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="duration of the Poisson serving run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-burst", type=int, default=1024, help="requests of the saturated serving run")
+    ap.add_argument("--serve-budget-gib", type=int, default=8)
+    ap.add_argument("--serve-inflight", type=int, default=256)
+    ap.add_argument("--serve-streams", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -144,6 +210,25 @@ def main() -> int:
         if r >= 3:
             lat.append(time.perf_counter() - a)
 
+    # the plain single-signal path: one execution after another on one stream
+    single = None
+    if args.single_passes > 0:
+        outs1 = [plan.outputs(dev) for _ in range(M)]
+        for i in range(M):
+            plan.execute(xs[i], *outs1[i])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.single_passes):
+            for i in range(M):
+                plan.execute(xs[i], *outs1[i])
+        torch.cuda.synchronize()
+        single = M * args.single_passes / (time.perf_counter() - a)
+        print(f"# single-signal path {single:.0f} signals/s", file=sys.stderr, flush=True)
+
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serve_measure(S, torch, dev, xs, truth, args)
+
     alg = alg_bytes_per_signal() * M
     achieved = alg / fold_avg_s / 1e9
     traffic = committed_traffic(M)
@@ -193,9 +278,15 @@ def main() -> int:
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
                    "strip_cols": desc["strip_cols"], "parallelism": "single-gpu"},
-        "latency": ({"p50_ms": round(percentile(lat, 0.5) * 1e3, 4), "p99_ms": round(percentile(lat, 0.99) * 1e3, 4),
-                     "source": "single request, sfft_execute alone + stream sync", "runs": len(lat)}
-                    if lat else None),
+        "latency": ({"p50_ms": serving["poisson"]["p50_ms"], "p99_ms": serving["poisson"]["p99_ms"],
+                     "source": f"serving loop, Poisson arrivals at {serving['poisson']['rate_req_s']:.0f} req/s, "
+                               "submission to completion"} if serving else None),
+        "single_request_latency": ({"p50_ms": round(percentile(lat, 0.5) * 1e3, 4),
+                                    "p99_ms": round(percentile(lat, 0.99) * 1e3, 4),
+                                    "source": "sfft_execute alone + stream sync", "runs": len(lat)}
+                                   if lat else None),
+        "single_signal_path_signals_per_s": round(single, 1) if single else None,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,
