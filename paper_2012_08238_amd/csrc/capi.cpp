@@ -1,4 +1,5 @@
 // C ABI of the gfx950 sparse FFT: plans, single execution, batches, traces.
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -62,6 +63,9 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.rpart = reinterpret_cast<double*>(ws + w.rpart);
     d.resid_own = reinterpret_cast<double*>(ws + w.resid_own);
     d.ctr = reinterpret_cast<uint32_t*>(ws + w.ctr);
+    d.ubuf = reinterpret_cast<float2*>(ws + w.ubuf);
+    d.gmax = reinterpret_cast<uint32_t*>(ws + w.gmax);
+    d.fft_mode = R.fft_mode;
     d.N = R.N;
     d.maskN = R.N - 1;
     d.log2N = R.log2N;
@@ -100,7 +104,13 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     a.one_io = io;
     HIP_TRY(launch_fold(a, R.fold_variant, R.fold_units, R.strip_lds, s), "bucketization launch");
     a.xcd_order = 0;
-    HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
+    if (R.fft_mode) {
+        HIP_TRY(launch_fft_large(a, R.log2B, 0, R.fft_p1_units, s), "fft pass 1 launch");
+        HIP_TRY(launch_fft_large(a, R.log2B, 1, R.fft_p2_units, s), "fft pass 2 launch");
+        HIP_TRY(launch_fft_large(a, R.log2B, 2, R.L, s), "selection launch");
+    } else {
+        HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
+    }
     HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, s), "vote launch");
     HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, s), "estimate launch");
     if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
@@ -337,7 +347,24 @@ sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t) {
     const Resolved& R = p->R;
     const WsLayout w = workspace_layout(R);
     const size_t wpl = (R.B + 31) / 32;
-    if (t->uhat) HIP_TRY(hipMemcpy(t->uhat, p->d_ws + w.uhat, (size_t)R.L * R.B * 8, hipMemcpyDeviceToHost), "copy uhat");
+    if (t->uhat) {
+        HIP_TRY(hipMemcpy(t->uhat, p->d_ws + w.uhat, (size_t)R.L * R.B * 8, hipMemcpyDeviceToHost), "copy uhat");
+        if (R.fft_mode) {
+            // two-pass layout: bucket h's value is e^{+2 pi i (s tau h mod B)/B} V[s h mod B], s = sigma^{-1}
+            std::vector<float> v(t->uhat, t->uhat + (size_t)2 * R.L * R.B);
+            const uint32_t Bm = R.B - 1;
+            for (uint32_t r = 0; r < R.L; ++r) {
+                const uint32_t s = R.sigma_inv[r], tau = R.tau[r];
+                for (uint32_t h = 0; h < R.B; ++h) {
+                    const size_t m = (size_t)r * R.B + ((s * h) & Bm);
+                    const double a = 6.283185307179586476925286766559 * (double)((s * tau * h) & Bm) / (double)R.B;
+                    const double c = cos(a), sn = sin(a), x = v[2 * m], y = v[2 * m + 1];
+                    t->uhat[2 * ((size_t)r * R.B + h)] = (float)(x * c - y * sn);
+                    t->uhat[2 * ((size_t)r * R.B + h) + 1] = (float)(x * sn + y * c);
+                }
+            }
+        }
+    }
     if (t->jbits) HIP_TRY(hipMemcpy(t->jbits, p->d_ws + w.jbits, (size_t)R.L * wpl * 4, hipMemcpyDeviceToHost), "copy jbits");
     if (t->jlist) HIP_TRY(hipMemcpy(t->jlist, p->d_ws + w.jlist, (size_t)R.L * R.dK * 4, hipMemcpyDeviceToHost), "copy jlist");
     uint32_t ctr[4] = {0, 0, 0, 0};

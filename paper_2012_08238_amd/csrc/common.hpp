@@ -9,6 +9,7 @@ namespace sfft {
 constexpr int kMaxL = 32;        // loops supported (bitmaps, median sorting network)
 constexpr int kMaxK = 4096;      // outputs supported (final sort in LDS)
 constexpr int kMaxFftLds = 16384;  // largest B transformed inside one workgroup's LDS
+constexpr int kMaxB = 1 << 18;     // larger B: two-pass (four-step) FFT through the workspace
 constexpr int kRouMax = 256;       // entries of the FP64 root-of-unity table
 
 // Per-signal execution descriptor: plan tables (read only, shared by every
@@ -35,6 +36,8 @@ struct SigDesc {
     double* rpart;              // [2 * resid_blocks] residual partial sums
     double* resid_own;          // [2] residual when the caller gives no buffer
     uint32_t* ctr;              // [4] counters: 0 candidates, 1 residual blocks done
+    float2* ubuf;               // [L][B] two-pass FFT intermediate (B > kMaxFftLds only)
+    uint32_t* gmax;             // [L][B/16] largest energy of each 16 consecutive DFT outputs (idem)
     // sizes
     uint32_t N, maskN, log2N;
     uint32_t B, log2B;
@@ -44,6 +47,8 @@ struct SigDesc {
     uint32_t tb;                // root-of-unity table bits, min(8, log2N)
     double step;                // 2 pi / N
     uint32_t mode;              // 0 gather, 1 strip
+    uint32_t fft_mode;          // 0: one-workgroup FFT, uhat in bucket order; 1: two-pass FFT of the
+                                // column-order values, uhat[r][m] = V[m] with bucket h <-> m = sigma_r^{-1} h mod B
     uint32_t C, log2C, strips;  // strip bucketization tile: C columns x M rows
     uint32_t vote_units;        // vote workgroups
     uint32_t vote_upl;          // vote workgroups per enumerated loop (chunks of kVoteUnit candidates)

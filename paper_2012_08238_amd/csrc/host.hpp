@@ -20,6 +20,8 @@ struct Resolved {
     uint32_t tb;                // device root-of-unity table bits, min(8, log2N)
     uint32_t log2N, log2B, log2M;
     uint32_t mode, C, log2C;    // bucketization form (0 gather, 1 strip) and strip width
+    uint32_t fft_mode;          // 0 one-workgroup FFT (B <= 16384), 1 two-pass FFT
+    uint32_t fft_p1_units, fft_p2_units;   // two-pass FFT workgroups per signal
     uint64_t seed;
     double gauss_c;
     uint32_t flags;
@@ -78,7 +80,7 @@ inline uint32_t ilog2(uint64_t v) {
 
 // Device workspace layout of one execution (byte offsets, 256-aligned).
 struct WsLayout {
-    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, total;
+    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, ubuf, gmax, total;
 };
 WsLayout workspace_layout(const Resolved& R);
 

@@ -105,6 +105,10 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// |v|^2 as the bit pattern of a non-negative float (monotone as unsigned): the
+// ordering key of bucket energies, computed the same way wherever it is needed
+__device__ __forceinline__ uint32_t energy_key(float2 v) { return __float_as_uint(fmaf(v.x, v.x, v.y * v.y)); }
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const uint32_t lane = threadIdx.x & 63u;
 #pragma unroll
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
         key[c] = 0;
         if (valid) {
             const float2 v = data[padi(threadIdx.x * CH + c)];
-            key[c] = __float_as_uint(fmaf(v.x, v.x, v.y * v.y));
+            key[c] = energy_key(v);
         }
     }
     const uint32_t dK = d.dK;
@@ -719,6 +723,368 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
         const uint64_t selm = select_mask<NT, CH>(key, kv, theta, rank, scan);
         emit_selection<NT, CH>(selm, [&](int c) { return (uint32_t)(threadIdx.x * CH + c); }, bits, NW, scan, jl, jb,
                                dK);
+    }
+}
+
+
+// ---------------------------------------------------------------- two-pass FFT (B > 16384)
+// The bucketization leaves the bucket values in column order, v[col] = u[b] with
+// col = sigma b + tau mod B. Instead of moving them into bucket order first, the
+// DFT V of v is taken as it stands: with s = sigma^{-1} mod B,
+//   X[h] = sum_b u[b] e^{-2 pi i bh/B} = e^{+2 pi i (s tau h mod B)/B} V[s h mod B],
+// so bucket h's DFT value is V at m = s h mod B times a unit phase, and the
+// energies |X[h]|^2 are those of V at m (h = sigma m mod B). V is computed in four
+// steps over the B1 x B2 row-major view (col = B2 j1 + j2, B = B1 B2): DFTs of
+// length B1 down the columns, the twist W_B^{j2 k1}, DFTs of length B2 along the
+// rows, V[k1 + B1 k2] = sum_j2 W_B2^{j2 k2} W_B^{j2 k1} sum_j1 W_B1^{j1 k1} v[B2 j1 + j2].
+// Each workgroup transforms 16 sequences, so every global access moves 16
+// consecutive values. The second pass also records the largest energy of every
+// 16 consecutive V entries, which lets the selection visit few of them.
+template <int LB>
+struct LargeCfg {
+    static constexpr int B = 1 << LB;
+    static constexpr int LB1 = (LB + 1) / 2, LB2 = LB / 2;
+    static constexpr int B1 = 1 << LB1, B2 = 1 << LB2;
+    static constexpr int NT = 256;       // FFT pass workgroups: 16 sequences each
+    static constexpr int G = B / 16;     // groups of 16 consecutive V entries
+    static constexpr int SNT = 1024;     // selection workgroup
+    static constexpr int NW = B / 32;    // bitmap words
+    static constexpr int SELCAP = 8192;  // candidates of the prefiltered selection held in LDS
+};
+
+// NSEQ DFTs of length 2^LP at once in LDS (sequence q at q*SP, element j at
+// padi(j)): Stockham autosort passes as stockham_pass, twiddles tp[m] = W_P^m.
+template <int LP, int NSEQ, int NT>
+struct SeqFft {
+    static constexpr int P = 1 << LP;
+    static constexpr int SP = P + (P >> 4) + 1;
+    static constexpr size_t lds_bytes() { return (size_t)(NSEQ * SP + P) * sizeof(float2); }
+
+    template <int LOG2R, int LOG2NS>
+    __device__ __forceinline__ static void pass(float2* lds, const float2* tp) {
+        constexpr int R = 1 << LOG2R, Ns = 1 << LOG2NS, NBF = P / R, TOT = NSEQ * NBF;
+        constexpr int NPER = (TOT + NT - 1) / NT;
+        constexpr int TSHIFT = LP - LOG2NS - LOG2R;
+        float2 v[NPER][R];
+#pragma unroll
+        for (int q = 0; q < NPER; ++q) {
+            const int idx = (int)threadIdx.x + q * NT;
+            if (idx < TOT) {
+                const float2* base = lds + (idx / NBF) * SP;
+                const int j = idx % NBF;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = base[padi(j + r * NBF)];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NPER; ++q) {
+            const int idx = (int)threadIdx.x + q * NT;
+            if (idx < TOT) {
+                const int j = idx % NBF, k = j & (Ns - 1);
+                if (Ns > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tp[(r * k) << TSHIFT]);
+                }
+                SmallDft<R>::run(v[q]);
+                float2* base = lds + (idx / NBF) * SP;
+                const int o = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) base[padi(o + r * Ns)] = v[q][r];
+            }
+        }
+        __syncthreads();
+    }
+
+    template <int LOG2NS = 0>
+    __device__ __forceinline__ static void run(float2* lds, const float2* tp) {
+        constexpr int REM = LP - LOG2NS;
+        if constexpr (REM >= 4) {
+            pass<4, LOG2NS>(lds, tp);
+            run<LOG2NS + 4>(lds, tp);
+        } else if constexpr (REM > 0) {
+            pass<REM, LOG2NS>(lds, tp);
+        }
+    }
+};
+
+// First pass: 16 columns j2 of the B1 x B2 view per workgroup -> ubuf, row-major
+// [k1][j2], twisted. Units per signal: L * B2/16.
+template <int LB>
+__global__ __launch_bounds__(256) void fft_large_p1_kernel(Launch a) {
+    using C = LargeCfg<LB>;
+    using F = SeqFft<C::LB1, 16, C::NT>;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tp = data + 16 * F::SP;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    constexpr uint32_t tiles = C::B2 / 16;
+    const uint32_t r = unit / tiles, j20 = (unit % tiles) * 16u;
+    const float2* v = d.uhat + (size_t)r * C::B;
+    float2* y = d.ubuf + (size_t)r * C::B;
+    const float2* tw = d.tw;
+    constexpr int NE = 16 * C::B1 / C::NT;   // values per thread
+    constexpr int CHK = 8;
+    static_assert(NE % CHK == 0, "load chunks");
+#pragma unroll
+    for (int q0 = 0; q0 < NE; q0 += CHK) {
+        float2 t[CHK];
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            t[u] = gld(v + (size_t)(e >> 4) * C::B2 + j20 + (e & 15));
+        }
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            data[(e & 15) * F::SP + padi(e >> 4)] = t[u];
+        }
+    }
+    for (int m = threadIdx.x; m < C::B1; m += C::NT) tp[m] = gld(tw + ((size_t)m << (LB - C::LB1)));
+    __syncthreads();
+    F::run(data, tp);
+#pragma unroll 4
+    for (int q = 0; q < NE; ++q) {
+        const int e = (int)threadIdx.x + q * C::NT;
+        const uint32_t k1 = (uint32_t)e >> 4, j2 = j20 + (uint32_t)(e & 15);
+        const float2 t = gld(tw + ((j2 * k1) & (uint32_t)(C::B - 1)));   // W_B^{j2 k1}
+        gst(y + (size_t)k1 * C::B2 + j2, cmul(data[(e & 15) * F::SP + padi((int)k1)], t));
+    }
+}
+
+// Second pass: 16 rows k1 per workgroup -> V[k1 + B1 k2] into uhat, and the
+// largest energy of each 16 consecutive V entries into gmax. Units: L * B1/16.
+template <int LB>
+__global__ __launch_bounds__(256) void fft_large_p2_kernel(Launch a) {
+    using C = LargeCfg<LB>;
+    using F = SeqFft<C::LB2, 16, C::NT>;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tp = data + 16 * F::SP;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    constexpr uint32_t tiles = C::B1 / 16;
+    const uint32_t r = unit / tiles, k10 = (unit % tiles) * 16u;
+    const float2* y = d.ubuf + (size_t)r * C::B;
+    float2* V = d.uhat + (size_t)r * C::B;
+    uint32_t* gm = d.gmax + (size_t)r * C::G;
+    constexpr int NE = 16 * C::B2 / C::NT;
+    constexpr int CHK = 8;
+    static_assert(NE % CHK == 0, "load chunks");
+#pragma unroll
+    for (int q0 = 0; q0 < NE; q0 += CHK) {
+        float2 t[CHK];
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            t[u] = gld(y + (size_t)(k10 + (uint32_t)(e >> C::LB2)) * C::B2 + (e & (C::B2 - 1)));
+        }
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            data[(e >> C::LB2) * F::SP + padi(e & (C::B2 - 1))] = t[u];
+        }
+    }
+    for (int m = threadIdx.x; m < C::B2; m += C::NT) tp[m] = gld(d.tw + ((size_t)m << (LB - C::LB2)));
+    __syncthreads();
+    F::run(data, tp);
+#pragma unroll 4
+    for (int q = 0; q < NE; ++q) {
+        const int e = (int)threadIdx.x + q * C::NT;
+        const int c = e & 15, k2 = e >> 4;
+        const float2 val = data[c * F::SP + padi(k2)];
+        const uint32_t m0 = k10 + (uint32_t)C::B1 * (uint32_t)k2;   // multiple of 16
+        gst(V + m0 + c, val);
+        uint32_t mx = energy_key(val);
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+        if (c == 0) gst(gm + (m0 >> 4), mx);
+    }
+}
+
+// k-th largest (1-based, k <= number of valid keys) of n keys produced by
+// keyf(i, key) -> valid, streamed 4 times (8-bit digits from the top, LDS
+// histogram). Returns the value and how many keys equal to it are among the k largest.
+template <int NT, class KeyF>
+__device__ __forceinline__ void stream_kth_largest(uint32_t n, uint32_t k, KeyF keyf, uint32_t* hist, uint32_t* bc,
+                                                   uint32_t& theta, uint32_t& rank) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t prefix = 0, pmask = 0, kk = k;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (uint32_t i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += NT) {
+            uint32_t key;
+            if (keyf(i, key) && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int hi = 255 - 4 * (int)lane;   // lane 0 owns the largest digits
+            const uint32_t h0 = hist[hi], h1 = hist[hi - 1], h2 = hist[hi - 2], h3 = hist[hi - 3];
+            const uint32_t sum = h0 + h1 + h2 + h3;
+            const uint32_t incl = wave_incl_scan(sum);
+            const uint32_t excl = incl - sum;
+            if (excl < kk && kk <= incl) {
+                uint32_t acc = excl, dsel, rem;
+                if (acc + h0 >= kk) {
+                    dsel = hi;
+                    rem = kk - acc;
+                } else if (acc += h0, acc + h1 >= kk) {
+                    dsel = hi - 1;
+                    rem = kk - acc;
+                } else if (acc += h1, acc + h2 >= kk) {
+                    dsel = hi - 2;
+                    rem = kk - acc;
+                } else {
+                    acc += h2;
+                    dsel = hi - 3;
+                    rem = kk - acc;
+                }
+                bc[0] = dsel;
+                bc[1] = rem;
+            }
+        }
+        __syncthreads();
+        prefix |= bc[0] << shift;
+        pmask |= 255u << shift;
+        kk = bc[1];
+        __syncthreads();
+    }
+    theta = prefix;
+    rank = kk;
+}
+
+// Selection of the dK largest bucket energies (ties -> lower bucket) from V in m
+// order; bucket h = sigma m mod B. Fast path: theta0 = the dK-th largest group
+// maximum bounds the dK-th largest energy from below (at least dK groups hold an
+// energy >= theta0), so only entries >= theta0 of groups whose maximum reaches
+// theta0 are collected and selected exactly in LDS. When the bound admits too
+// many entries (flat spectra) every entry is streamed instead. One workgroup per
+// (signal, loop). Dynamic LDS: bitmap words + SELCAP (energy, bucket) pairs.
+template <int LB>
+__global__ __launch_bounds__(1024) void select_large_kernel(Launch a) {
+    using C = LargeCfg<LB>;
+    constexpr int NT = C::SNT, G = C::G, NW = C::NW, CAP = C::SELCAP;
+    constexpr uint32_t Bm = (uint32_t)C::B - 1u;
+    extern __shared__ uint32_t lds_words[];
+    uint32_t* bits = lds_words;
+    uint32_t* ckey = bits + NW;
+    uint32_t* cidx = ckey + CAP;
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t bc[4];
+    __shared__ uint32_t scan[NT / 64];
+    __shared__ uint32_t s_cnt, s_eq;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const uint32_t r = unit, dK = d.dK;
+    const uint32_t sg = ((CU32)d.sigma)[r];
+    const float2* V = d.uhat + (size_t)r * C::B;
+    const uint32_t* gm = d.gmax + (size_t)r * G;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)NW; i += NT) bits[i] = 0;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_eq = 0;
+    }
+    __syncthreads();
+    bool fast = dK <= (uint32_t)G;   // block-uniform
+    uint32_t n = 0;
+    if (fast) {
+        uint32_t theta0, rank0;
+        stream_kth_largest<NT>((uint32_t)G, dK, [&](uint32_t i, uint32_t& k) { k = gld(gm + i); return true; }, hist,
+                               bc, theta0, rank0);
+        for (uint32_t g = threadIdx.x; g < (uint32_t)G; g += NT) {
+            if (gld(gm + g) < theta0) continue;
+            const f4v* p = reinterpret_cast<const f4v*>(V + (size_t)g * 16u);
+            f4v t[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) t[c] = gld(p + c);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const f4v& q = t[c >> 1];
+                const float2 val = (c & 1) ? make_float2(q[2], q[3]) : make_float2(q[0], q[1]);
+                const uint32_t k = energy_key(val);
+                if (k >= theta0) {
+                    const uint32_t pos = atomicAdd(&s_cnt, 1u);
+                    if (pos < (uint32_t)CAP) {
+                        ckey[pos] = k;
+                        cidx[pos] = (sg * (g * 16u + (uint32_t)c)) & Bm;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        n = s_cnt;
+        fast = n <= (uint32_t)CAP;
+    }
+    // energy and bucket of entry i of the working set (candidates, or all of V)
+    auto entry = [&](uint32_t i, uint32_t& k, uint32_t& h) {
+        if (fast) {
+            k = ckey[i];
+            h = cidx[i];
+        } else {
+            k = energy_key(gld(V + i));
+            h = (sg * i) & Bm;
+        }
+    };
+    const uint32_t total = fast ? n : (uint32_t)C::B;
+    uint32_t theta, rank;
+    stream_kth_largest<NT>(total, dK, [&](uint32_t i, uint32_t& k) { uint32_t h; entry(i, k, h); return true; }, hist,
+                           bc, theta, rank);
+    // entries equal to theta: take the `rank` of lowest bucket
+    uint32_t eq = 0;
+    for (uint32_t i = threadIdx.x; i < total; i += NT) {
+        uint32_t k, h;
+        entry(i, k, h);
+        eq += k == theta;
+    }
+    if (eq) atomicAdd(&s_eq, eq);
+    __syncthreads();
+    uint32_t hcut = (uint32_t)C::B;   // ties with bucket < hcut are selected
+    if (s_eq > rank) {
+        uint32_t th, rk;
+        stream_kth_largest<NT>(total, rank, [&](uint32_t i, uint32_t& k) {
+            uint32_t e, h;
+            entry(i, e, h);
+            k = Bm - h;
+            return e == theta;
+        }, hist, bc, th, rk);
+        hcut = (uint32_t)C::B - th;
+    }
+    for (uint32_t i = threadIdx.x; i < total; i += NT) {
+        uint32_t k, h;
+        entry(i, k, h);
+        if (k > theta || (k == theta && h < hcut)) atomicOr(&bits[h >> 5], 1u << (h & 31u));
+    }
+    __syncthreads();
+    // bitmap out; buckets in ascending order into jlist
+    constexpr int WPT = NW / NT;
+    static_assert(WPT >= 1 && NW % NT == 0, "bitmap words per thread");
+    uint32_t* jb = d.jbits + (size_t)r * NW;
+    uint32_t* jl = d.jlist + (size_t)r * dK;
+    uint32_t wv[WPT], cnt = 0;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+        wv[q] = bits[threadIdx.x * WPT + q];
+        cnt += (uint32_t)__popc(wv[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) gst(jb + threadIdx.x * WPT + q, wv[q]);
+    uint32_t tot;
+    uint32_t pos = block_excl_scan<NT>(cnt, scan, tot);
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+        uint32_t w = wv[q];
+        while (w) {
+            const uint32_t b = (uint32_t)__ffs((int)w) - 1u;
+            w &= w - 1u;
+            if (pos < dK) gst(jl + pos, (threadIdx.x * WPT + q) * 32u + b);
+            ++pos;
+        }
     }
 }
 
@@ -886,12 +1252,13 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t bc[4];
-    __shared__ uint32_t s_sig[kMaxL], s_tau[kMaxL];
+    __shared__ uint32_t s_sig[kMaxL], s_tau[kMaxL], s_sinv[kMaxL];
     __shared__ double2 s_rou[kRouMax];
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
+    const uint32_t fftm = d.fft_mode;
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
     const uint32_t rsh = d.log2N - d.tb;
     const double step = d.step;
@@ -903,6 +1270,7 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     if (threadIdx.x < L) {
         s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
         s_tau[threadIdx.x] = gld(d.tau + threadIdx.x);
+        s_sinv[threadIdx.x] = gld(d.sigma_inv + threadIdx.x);
     }
     stage_rou<kFinNT>(s_rou, d.rou, d.tb);
     __syncthreads();
@@ -910,6 +1278,7 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     const uint32_t* cand = d.cand;
     const float2* invG = d.invG;
     const float2* uhat = d.uhat;
+    const float2* tw = d.tw;
     float2* est = d.est;
     uint64_t* keys = d.keys;
     for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
@@ -925,7 +1294,15 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
                 const uint32_t o = (p - (h << log2M) + (N >> 1)) & maskN;   // o + N/2
                 const uint32_t gi = o - (N >> 1) + (M >> 1);
                 const float2 g = gld(invG + gi);
-                const float2 uv = gld(uhat + (size_t)r * B + h);
+                float2 uv;
+                if (fftm) {
+                    // two-pass FFT layout: X[h] = e^{+2 pi i (s tau h mod B)/B} V[s h mod B], s = sigma^{-1}
+                    const uint32_t si = s_sinv[r];
+                    const float2 t = gld(tw + ((si * s_tau[r] * h) & (B - 1u)));   // e^{-2 pi i ./B}
+                    uv = cmul(gld(uhat + (size_t)r * B + ((si * h) & (B - 1u))), make_float2(t.x, -t.y));
+                } else {
+                    uv = gld(uhat + (size_t)r * B + h);
+                }
                 const uint32_t k = (s_tau[r] * f) & maskN;
                 const double2 pk = phase_of(s_rou, k, rsh, step);   // e^{+2 pi i k/N}
                 const float2 rot = make_float2((float)pk.x, -(float)pk.y);
@@ -1147,8 +1524,54 @@ static hipError_t set_strip_attr() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
 }
 
+template <int LB>
+constexpr size_t large_lds(uint32_t pass) {
+    using C = LargeCfg<LB>;
+    return pass == 0   ? SeqFft<C::LB1, 16, C::NT>::lds_bytes()
+           : pass == 1 ? SeqFft<C::LB2, 16, C::NT>::lds_bytes()
+                       : (size_t)(C::NW + 2 * C::SELCAP) * sizeof(uint32_t);
+}
+
+template <int LB>
+hipError_t set_large_attr() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_large_p1_kernel<LB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds<LB>(0));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_large_p2_kernel<LB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds<LB>(1));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&select_large_kernel<LB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds<LB>(2));
+    return e;
+}
+
+template <int LB>
+hipError_t launch_large_t(const Launch& a, uint32_t pass, uint32_t units, hipStream_t s) {
+    switch (pass) {
+        case 0: hipLaunchKernelGGL(fft_large_p1_kernel<LB>, dim3(units), dim3(256), large_lds<LB>(0), s, a); break;
+        case 1: hipLaunchKernelGGL(fft_large_p2_kernel<LB>, dim3(units), dim3(256), large_lds<LB>(1), s, a); break;
+        case 2: hipLaunchKernelGGL(select_large_kernel<LB>, dim3(units), dim3(1024), large_lds<LB>(2), s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint32_t units, hipStream_t s) {
+    switch (log2B) {
+        case 15: return launch_large_t<15>(a, pass, units, s);
+        case 16: return launch_large_t<16>(a, pass, units, s);
+        case 17: return launch_large_t<17>(a, pass, units, s);
+        case 18: return launch_large_t<18>(a, pass, units, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t set_kernel_attributes_impl() {
     hipError_t e;
+    if ((e = set_large_attr<15>()) != hipSuccess) return e;
+    if ((e = set_large_attr<16>()) != hipSuccess) return e;
+    if ((e = set_large_attr<17>()) != hipSuccess) return e;
+    if ((e = set_large_attr<18>()) != hipSuccess) return e;
     if ((e = set_strip_attr<16>()) != hipSuccess) return e;
     if ((e = set_strip_attr<32>()) != hipSuccess) return e;
     if ((e = set_fft_attr<13>()) != hipSuccess) return e;

@@ -35,8 +35,8 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     if ((p.sigma == nullptr) != (p.tau == nullptr)) return bad("sigma and tau must be given together");
     if ((p.flags & SFFT_FLAG_FOLD_GATHER) && (p.flags & SFFT_FLAG_FOLD_STRIP))
         return bad("FOLD_GATHER and FOLD_STRIP are exclusive");
-    if (p.B > kMaxFftLds) {
-        *err = "B > 16384 is not supported by this build";
+    if (p.B > kMaxB) {
+        *err = "B > 2^18 is not supported by this build";
         return SFFT_E_UNSUPPORTED;
     }
     R.N = (uint32_t)p.N;
@@ -120,6 +120,14 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     const uint32_t wpl = (R.B + 31) / 32;
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
     R.vote_lds = vbytes <= 65536u ? vbytes : 0u;
+    // B-point FFT: in one workgroup's LDS up to kMaxFftLds, else two passes
+    // (B = B1 * B2, tiles of 16 sequences per workgroup) and a selection workgroup per loop
+    R.fft_mode = R.B > (uint32_t)kMaxFftLds ? 1u : 0u;
+    if (R.fft_mode) {
+        const uint32_t lb1 = (R.log2B + 1) / 2, lb2 = R.log2B / 2;
+        R.fft_p1_units = R.L * ((1u << lb2) / 16u);
+        R.fft_p2_units = R.L * ((1u << lb1) / 16u);
+    }
     R.resid_blocks = (R.S + kResNT - 1) / kResNT;
     uint32_t P = 1;
     while (P < R.K) P <<= 1;
@@ -236,6 +244,8 @@ WsLayout workspace_layout(const Resolved& R) {
     l.rpart = take((size_t)std::max<uint32_t>(R.resid_blocks, 1) * 16);
     l.resid_own = take(16);
     l.ctr = take(16);
+    l.ubuf = take(R.fft_mode ? (size_t)R.L * R.B * 8 : 16);
+    l.gmax = take(R.fft_mode ? (size_t)R.L * (R.B / 16) * 4 : 16);
     l.total = off;
     return l;
 }

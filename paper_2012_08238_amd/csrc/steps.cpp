@@ -10,13 +10,14 @@ namespace sfft {
 
 namespace {
 constexpr uint32_t kFftLog2Max = 14;   // one-workgroup FFT sizes 2^1 .. 2^14
+constexpr uint32_t kLargeLog2Max = 18; // two-pass FFT sizes 2^15 .. 2^18, three launches each
 constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
 }  // namespace
 
 size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // vote: 2 x kLmaxCount; finalize: kLmaxCount; residual: 1
-    const size_t launches = n + kFftLog2Max + 3 * kLmaxCount + 1;
+    const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + 3 * kLmaxCount + 1;
     return launches * (n + 1);
 }
 
@@ -51,6 +52,12 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
     }
     for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)
         add_step(kStepFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
+    for (uint32_t pass = 0; pass < 3; ++pass)
+        for (uint32_t lb = kFftLog2Max + 1; lb <= kLargeLog2Max; ++lb)
+            add_step(kStepFftLarge, lb | (pass << 8), 0, [&](const Resolved& R) {
+                if (R.log2B != lb) return 0u;
+                return pass == 0 ? R.fft_p1_units : (pass == 1 ? R.fft_p2_units : R.L);
+            });
     for (uint32_t staged = 0; staged < 2; ++staged)
         for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
             auto in_group = [&](const Resolved& R) { return (R.vote_lds > 0) == (staged == 1) && R.lmax == lm; };
@@ -83,6 +90,7 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
             case kStepVote: e = launch_vote(a, st.param >> 8, st.units, st.lds, s); break;
             case kStepFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
             case kStepRes: e = launch_residual(a, st.units, st.lds, s); break;
+            case kStepFftLarge: e = launch_fft_large(a, st.param & 255u, st.param >> 8, st.units, s); break;
         }
         if (e != hipSuccess) return e;
     }

@@ -48,8 +48,11 @@ def test_parameter_validation(bad):
 
 def test_unsupported_large_B():
     with pytest.raises(S.SfftError) as e:
-        S.host_tables(S.PlanParams(N=1 << 22, K=200, B=1 << 15, L=9, w=1 << 18))
+        S.host_tables(S.PlanParams(N=1 << 22, K=200, B=1 << 19, L=9, w=1 << 20))
     assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+    # up to 2^18 buckets run through the two-pass FFT
+    t = S.host_tables(S.PlanParams(N=1 << 22, K=200, B=1 << 18, L=3, w=1 << 19, n_resid=8))
+    assert t["gain"].shape[0] == 16
 
 
 @pytest.mark.parametrize("N,K,B,L,w,seed", [
