@@ -126,6 +126,57 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     }
 
 
+def uneven_measure(S, torch, dev, args) -> dict:
+    """The uneven batch: --uneven signals with N = 2^16..2^22, K = 10..500, SNR
+    -10..40 dB, resident in HBM, one plan per signal (tuned table if given, else
+    the rule: B next to sqrt(N K), w = 8B, L = 9), one graph replay per step."""
+    import numpy as np
+    from paper_2012_08238_amd import autotune as A
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch, uneven_batch_specs
+    specs = uneven_batch_specs(args.uneven, seed=4)
+    table = A.Table(args.tune_table) if args.tune_table else None
+    t0 = time.perf_counter()
+    plans, xs, truth = [], [], []
+    for i, (n, k, snr) in enumerate(specs):
+        prm = table.params(n, k, seed=i, device=dev) if table else A.rule_params(n, k, seed=i)
+        plans.append(S.Plan.from_params(prm))
+        x, f, _ = make_signal_torch(n, k, snr, derive_seed(40, i), dev)
+        xs.append(x)
+        truth.append(f)
+    b = S.Batch(plans)
+    outs = [p.outputs(dev) for p in plans]
+    idx, val, res = [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs]
+    setup = time.perf_counter() - t0
+    for _ in range(2):
+        b.run(xs, idx, val, res)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.uneven_steps):
+        b.run(xs, idx, val, res)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    rec = [len(set(o[0].cpu().numpy().tolist()) & set(f.tolist())) / k
+           for (n, k, snr), o, f in zip(specs, outs, truth) if snr >= 10.0]
+    # the plain single-signal path over the same batch
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for p, x, o in zip(plans, xs, outs):
+        p.execute(x, o[0], o[1], o[2])
+    torch.cuda.synchronize()
+    single = len(plans) / (time.perf_counter() - t2)
+    nbytes = sum(n for n, _, _ in specs) * 8
+    b.close()
+    for p in plans:
+        p.close()
+    return {"signals": len(specs), "resident_bytes": nbytes, "steps": args.uneven_steps,
+            "ms_per_step": round(el / args.uneven_steps * 1e3, 4),
+            "signals_per_s": round(len(specs) * args.uneven_steps / el, 1),
+            "single_signal_path_signals_per_s": round(single, 1),
+            "mean_recall_snr_ge_10db": round(float(np.mean(rec)), 5) if rec else None,
+            "params": "autotuned table" if table else "rule: B next to sqrt(NK), w=8B, L=9",
+            "setup_s": round(setup, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +195,9 @@ def main() -> int:
     ap.add_argument("--serve-budget-gib", type=int, default=8)
     ap.add_argument("--serve-inflight", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
+    ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--tune-table", default="", help="autotuner JSON table for the uneven batch (tunes missing classes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -228,6 +282,10 @@ def main() -> int:
     serving = None
     if args.serve_seconds > 0:
         serving = serve_measure(S, torch, dev, xs, truth, args)
+    uneven = None
+    if args.uneven > 0:
+        uneven = uneven_measure(S, torch, dev, args)
+        print(f"# uneven batch {uneven['signals_per_s']:.0f} signals/s", file=sys.stderr, flush=True)
 
     alg = alg_bytes_per_signal() * M
     achieved = alg / fold_avg_s / 1e9
@@ -287,6 +345,7 @@ def main() -> int:
                                    if lat else None),
         "single_signal_path_signals_per_s": round(single, 1) if single else None,
         "serving": serving,
+        "uneven_batch": uneven,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,

@@ -90,3 +90,20 @@ def impulse(N: int, j: int) -> np.ndarray:
     x = np.zeros(N, dtype=np.complex128)
     x[j] = 1.0
     return x
+
+
+def uneven_batch_specs(n: int = 256, seed: int = 4, log2n=(16, 22), k=(10, 500), snr=(-10.0, 40.0)):
+    """(N, K, SNR dB) of an uneven batch: N = 2^e with e uniform over the integers
+    of ``log2n``, K uniform over the integers of ``k``, SNR uniform over ``snr``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        e = int(rng.integers(log2n[0], log2n[1] + 1))
+        out.append((1 << e, int(rng.integers(k[0], k[1] + 1)), float(rng.uniform(snr[0], snr[1]))))
+    return out
+
+
+def poisson_arrivals(rate: float, n: int, seed: int = 2000) -> np.ndarray:
+    """Arrival times (s) of a Poisson process: cumulative exponential gaps of mean 1/rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
