@@ -126,6 +126,81 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     }
 
 
+def serve_mix_measure(S, torch, dev, args) -> dict:
+    """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
+    N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
+    rule: B next to sqrt(N K), w = 8B, L = 9), plans prepared up front (device
+    resident after first use); requests draw pool entries at random and arrive
+    as a Poisson process at --serve-rate; then a saturated burst."""
+    import numpy as np
+    from paper_2012_08238_amd import autotune as A
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch, poisson_arrivals, uneven_batch_specs
+    specs = uneven_batch_specs(args.mix_pool, seed=5, log2n=(18, 24), k=(20, 1000), snr=(0.0, 30.0))
+    srv = S.Server(hbm_budget_bytes=args.mix_budget_gib << 30, max_inflight=args.serve_inflight,
+                   n_streams=args.serve_streams)
+    pool = []
+    for i, (n, k, snr) in enumerate(specs):
+        x, f, _ = make_signal_torch(n, k, snr, derive_seed(50, i), dev)
+        h = srv.prepare(A.rule_params(n, k, seed=i))
+        pool.append((x, f, h, k, snr))
+    nreq = max(1, int(args.serve_rate * args.serve_seconds))
+    rng = np.random.default_rng(6)
+    pick = rng.integers(0, len(pool), max(nreq, args.serve_burst))
+    kmax = max(k for _, _, _, k, _ in pool)
+    m = max(nreq, args.serve_burst)
+    idx = torch.empty((m, kmax), dtype=torch.int64, device=dev)
+    val = torch.empty((m, kmax), dtype=torch.complex64, device=dev)
+    # make every plan resident once
+    for j, (x, f, h, k, snr) in enumerate(pool):
+        srv.wait(srv.submit(h, x, idx[j, :k], val[j, :k]))
+    torch.cuda.synchronize()
+    base = srv.stats()
+    arrivals = poisson_arrivals(args.serve_rate, nreq, seed=2001)
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        target = t0 + arrivals[i]
+        while True:
+            dt = target - time.perf_counter()
+            if dt <= 0:
+                break
+            if dt > 2e-4:
+                time.sleep(dt - 1.5e-4)
+        x, f, h, k, snr = pool[pick[i]]
+        tickets.append(srv.submit(h, x, idx[i, :k], val[i, :k]))
+    lats = sorted(srv.wait(t)[0] * 1e3 for t in tickets)
+    t_open = time.perf_counter() - t0
+    mid = srv.stats()
+    rec = []
+    for i in range(min(nreq, 512)):
+        x, f, h, k, snr = pool[pick[i]]
+        if snr >= 10.0:
+            rec.append(len(set(idx[i, :k].cpu().numpy().tolist()) & set(f.tolist())) / k)
+    t1 = time.perf_counter()
+    tickets = []
+    for i in range(args.serve_burst):
+        x, f, h, k, snr = pool[pick[i]]
+        tickets.append(srv.submit(h, x, idx[i, :k], val[i, :k]))
+    for t in tickets:
+        srv.wait(t)
+    t_sat = time.perf_counter() - t1
+    st = srv.stats()
+    srv.close()
+    return {
+        "pool": {"signals": len(pool), "resident_bytes": sum(n for n, _, _ in specs) * 8,
+                 "N": "2^18..2^24", "K": "20..1000", "snr_db": "0..30", "params": "rule: B~sqrt(NK), w=8B, L=9"},
+        "poisson": {"rate_req_s": args.serve_rate, "requests": nreq, "seconds": round(t_open, 3),
+                    "p50_ms": round(percentile(lats, 0.5), 4), "p99_ms": round(percentile(lats, 0.99), 4),
+                    "mean_ms": round(sum(lats) / len(lats), 4), "waves": mid["batches"] - base["batches"],
+                    "mean_recall_snr_ge_10db": round(float(np.mean(rec)), 5) if rec else None},
+        "saturated": {"requests": args.serve_burst, "signals_per_s": round(args.serve_burst / t_sat, 1),
+                      "waves": st["batches"] - mid["batches"], "max_wave": st["max_batch"],
+                      "max_waves_in_flight": st["max_waves_in_flight"]},
+        "hbm": {"budget_bytes": st["hbm_budget"], "peak_bytes": st["hbm_peak"],
+                "plan_cache_evictions": st["plan_cache_evictions"]},
+    }
+
+
 def uneven_measure(S, torch, dev, args) -> dict:
     """The uneven batch: --uneven signals with N = 2^16..2^22, K = 10..500, SNR
     -10..40 dB, resident in HBM, one plan per signal (tuned table if given, else
@@ -143,7 +218,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
         x, f, _ = make_signal_torch(n, k, snr, derive_seed(40, i), dev)
         xs.append(x)
         truth.append(f)
-    b = S.Batch(plans)
+    b = S.Batch(plans, branches=args.branches)
     outs = [p.outputs(dev) for p in plans]
     idx, val, res = [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs]
     setup = time.perf_counter() - t0
@@ -189,12 +264,15 @@ def main() -> int:
     ap.add_argument("--strip-cols", type=int, default=0, help="bucketization tile width (0 = plan default)")
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
     ap.add_argument("--single-passes", type=int, default=3, help="passes over the batch through sfft_execute alone")
+    ap.add_argument("--branches", type=int, default=4, help="parallel stream branches of the batch graph")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="duration of the Poisson serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-burst", type=int, default=1024, help="requests of the saturated serving run")
     ap.add_argument("--serve-budget-gib", type=int, default=8)
     ap.add_argument("--serve-inflight", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--mix-pool", type=int, default=64, help="pool of mixed-size served signals (0 = skip)")
+    ap.add_argument("--mix-budget-gib", type=int, default=16)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--tune-table", default="", help="autotuner JSON table for the uneven batch (tunes missing classes)")
@@ -222,7 +300,7 @@ def main() -> int:
     plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols,
                   flags=S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0)
     desc = plan.desc
-    batch = S.Batch([plan] * M)
+    batch = S.Batch([plan] * M, branches=args.branches)
     idx = torch.empty((M, K), dtype=torch.int64, device=dev)
     val = torch.empty((M, K), dtype=torch.complex64, device=dev)
     res = torch.empty((M, 2), dtype=torch.float64, device=dev)
@@ -239,10 +317,24 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        batch.run_timed(xs, idxs, vals, ress, ev[k][0], ev[k][1])
+        if args.branches == 1:
+            batch.run_timed(xs, idxs, vals, ress, ev[k][0], ev[k][1])
+        else:
+            batch.run(xs, idxs, vals, ress)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    launch_source = "bucketization launches of the timed steps"
+    if args.branches > 1:
+        # the branched graph runs each group's bucketization beside other stages:
+        # time the kernel over the whole batch in an unbranched graph instead
+        kb = S.Batch([plan] * M)
+        kb.run(xs, idxs, vals, ress)
+        for k in range(args.steps):
+            kb.run_timed(xs, idxs, vals, ress, ev[k][0], ev[k][1])
+        torch.cuda.synchronize()
+        kb.close()
+        launch_source = "bucketization launches of an unbranched replay of the same batch, after the timed steps"
     fold_ms = [a.elapsed_ms(b) for a, b in ev]
     fold_avg_s = sum(fold_ms) / len(fold_ms) / 1e3
     print(f"# timed {args.steps} steps in {elapsed:.3f}s; bucketization {fold_avg_s * 1e6:.1f} us/launch",
@@ -282,6 +374,11 @@ def main() -> int:
     serving = None
     if args.serve_seconds > 0:
         serving = serve_measure(S, torch, dev, xs, truth, args)
+    serving_mix = None
+    if args.serve_seconds > 0 and args.mix_pool > 0:
+        serving_mix = serve_mix_measure(S, torch, dev, args)
+        print(f"# mixed serving p50 {serving_mix['poisson']['p50_ms']} ms p99 {serving_mix['poisson']['p99_ms']} ms",
+              file=sys.stderr, flush=True)
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -293,7 +390,7 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "fold_strip_pf_kernel (bucketization)", "alg_bytes_per_launch": alg,
-                "launch_us": round(fold_avg_s * 1e6, 2)}
+                "launch_us": round(fold_avg_s * 1e6, 2), "launch_timing": launch_source}
     if traffic:
         roofline["effective_GBps"] = round(traffic / fold_avg_s / 1e9, 1)
 
@@ -335,7 +432,7 @@ def main() -> int:
         "config": {"workload": "sFFT N=2^22 K=100 SNR20dB B=16384 L=9 w=131072, batch of resident signals",
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
-                   "strip_cols": desc["strip_cols"], "parallelism": "single-gpu"},
+                   "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "parallelism": "single-gpu"},
         "latency": ({"p50_ms": serving["poisson"]["p50_ms"], "p99_ms": serving["poisson"]["p99_ms"],
                      "source": f"serving loop, Poisson arrivals at {serving['poisson']['rate_req_s']:.0f} req/s, "
                                "submission to completion"} if serving else None),
@@ -345,6 +442,7 @@ def main() -> int:
                                    if lat else None),
         "single_signal_path_signals_per_s": round(single, 1) if single else None,
         "serving": serving,
+        "serving_mixed_sizes": serving_mix,
         "uneven_batch": uneven,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -165,6 +165,13 @@ sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t);
  * outlive the batch. */
 sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32_t n);
 
+/* As sfft_batch_create, with the signals split into n_branches contiguous groups
+ * of about equal bytes (n_branches in [1, 8]) whose stage sequences are captured
+ * on parallel streams of one graph: one group's FFT, vote and estimation stages
+ * overlap another group's bucketization. Results are unchanged (bitwise).
+ * sfft_batch_run_timed needs n_branches = 1 (else SFFT_E_UNSUPPORTED). */
+sfft_status sfft_batch_create_ex(sfft_batch_t* out, const sfft_plan_t* plans, int32_t n, int32_t n_branches);
+
 /* Run the batch: x_dev[i] device complex64[N_i]; out_idx[i] device int64[K_i];
  * out_val[i] device complex64[K_i]; out_resid NULL or an array of n device
  * double[2] (entries may be NULL). Asynchronous on `stream`; a batch runs one

@@ -182,11 +182,11 @@ def _ptr_array(vals):
 class Batch:
     """Uneven batch of signals run as one HIP graph of batched launches."""
 
-    def __init__(self, plans):
+    def __init__(self, plans, branches: int = 1):
         self.plans = list(plans)
         hs = _ptr_array([p.handle.value for p in self.plans])
         h = C.c_void_p()
-        check(load().sfft_batch_create(C.byref(h), hs, len(self.plans)), "sfft_batch_create")
+        check(load().sfft_batch_create_ex(C.byref(h), hs, len(self.plans), branches), "sfft_batch_create_ex")
         self._h = h
 
     def run(self, xs, idxs, vals, resids=None, stream=None) -> None:

@@ -66,6 +66,7 @@ SIGNATURES = [
     ("sfft_execute_ex", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sfft_plan_read_trace", C.c_int, [C.c_void_p, C.POINTER(Trace)]),
     ("sfft_batch_create", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32]),
+    ("sfft_batch_create_ex", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_int32]),
     ("sfft_batch_run", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
     ("sfft_batch_run_timed", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),

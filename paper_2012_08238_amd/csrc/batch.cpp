@@ -37,6 +37,17 @@ struct sfft_batch_s {
     bool launched = false;
     size_t ws_bytes = 0;
     uint32_t xcd_order = 1;
+    // parallel branches: contiguous groups of signals whose stage sequences are
+    // captured on separate streams of one graph, so one group's later stages
+    // overlap another group's bucketization
+    struct Branch {
+        int32_t g0 = 0, n = 0;
+        std::vector<Step> steps;
+    };
+    std::vector<Branch> branches;
+    std::vector<hipStream_t> bstream;
+    std::vector<hipEvent_t> bjoin;
+    hipEvent_t fork = nullptr;
     std::mutex mu;
 };
 
@@ -49,6 +60,11 @@ void batch_free(sfft_batch_t b) {
         if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
     }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (hipStream_t x : b->bstream)
+        if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : b->bjoin)
+        if (x) (void)hipEventDestroy(x);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->d_ws) (void)hipFree(b->d_ws);
     if (b->d_descs) (void)hipFree(b->d_descs);
@@ -64,12 +80,32 @@ sfft_status issue_part(sfft_batch_t b, hipStream_t s, int part) {
     return e == hipSuccess ? SFFT_OK : hip_fail(e, "batched launch");
 }
 
+// Every branch on its own stream, forked from and joined back into `s`.
+sfft_status issue_branches(sfft_batch_t b, hipStream_t s) {
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (size_t g = 0; g < b->branches.size() && e == hipSuccess; ++g) {
+        const auto& br = b->branches[g];
+        e = hipStreamWaitEvent(b->bstream[g], b->fork, 0);
+        if (e == hipSuccess)
+            e = issue_steps(br.steps, b->d_descs + br.g0, b->d_ios + br.g0, b->d_prefix, (uint32_t)br.n, b->xcd_order,
+                            -1, b->bstream[g]);
+        if (e == hipSuccess) e = hipEventRecord(b->bjoin[g], b->bstream[g]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->bjoin[g], 0);
+    }
+    return e == hipSuccess ? SFFT_OK : hip_fail(e, "batched launch (branches)");
+}
+
 }  // namespace
 
 extern "C" {
 
 sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32_t n) {
+    return sfft_batch_create_ex(out, plans, n, 1);
+}
+
+sfft_status sfft_batch_create_ex(sfft_batch_t* out, const sfft_plan_t* plans, int32_t n, int32_t n_branches) {
     if (!out || !plans || n < 1) return set_error(SFFT_E_INVALID, "need an output pointer and n >= 1 plans");
+    if (n_branches < 1 || n_branches > 8) return set_error(SFFT_E_INVALID, "n_branches must be in [1, 8]");
     *out = nullptr;
     for (int32_t i = 0; i < n; ++i)
         if (!plans[i]) return set_error(SFFT_E_INVALID, "null plan in batch");
@@ -117,7 +153,31 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
     std::vector<uint32_t> prefix;
     std::vector<const Resolved*> sig(n);
     for (int32_t i = 0; i < n; ++i) sig[i] = &plan_resolved(plans[i]);
-    plan_steps(sig, &b->steps, &prefix);
+    const int32_t nb = std::min(n_branches, n);
+    if (nb == 1) {
+        plan_steps(sig, &b->steps, &prefix);
+    } else {
+        // contiguous groups of about equal signal bytes, none empty
+        std::vector<double> pre(n + 1, 0.0);
+        for (int32_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + (double)sig[i]->N;
+        std::vector<int32_t> cut(nb + 1, 0);
+        cut[nb] = n;
+        for (int32_t g = 1; g < nb; ++g) {
+            const double target = pre[n] * g / nb;
+            int32_t c = cut[g - 1] + 1;
+            while (c < n && pre[c] + 0.5 * (double)sig[c]->N <= target) ++c;
+            cut[g] = std::min(c, n - (nb - g));
+        }
+        for (int32_t g = 0; g < nb; ++g) {
+            const int32_t start = cut[g], end = cut[g + 1];
+            sfft_batch_s::Branch br;
+            br.g0 = start;
+            br.n = end - start;
+            std::vector<const Resolved*> part(sig.begin() + start, sig.begin() + end);
+            plan_steps(part, &br.steps, &prefix);
+            b->branches.push_back(std::move(br));
+        }
+    }
     b->xcd_order = 1;
     for (int32_t i = 0; i < n; ++i) b->xcd_order &= plan_resolved(plans[i]).xcd_order;
     if (hipMalloc(&b->d_prefix, prefix.size() * 4) != hipSuccess) {
@@ -127,6 +187,15 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* plans, int32
     e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && !b->branches.empty()) {
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        b->bstream.assign(b->branches.size(), nullptr);
+        b->bjoin.assign(b->branches.size(), nullptr);
+        for (size_t g = 0; g < b->branches.size() && e == hipSuccess; ++g) {
+            e = hipStreamCreateWithFlags(&b->bstream[g], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->bjoin[g], hipEventDisableTiming);
+        }
+    }
     if (e != hipSuccess) {
         batch_free(b);
         return hip_fail(e, "batch setup");
@@ -169,11 +238,14 @@ static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* 
         b->last_io = io;
         b->io_valid = true;
     }
+    if (!b->branches.empty() && (ev_fold_begin || ev_fold_end))
+        return set_error(SFFT_E_UNSUPPORTED, "bucketization events need a batch without branches");
     for (int part = 0; part < 2; ++part) {
         if (b->exec[part]) continue;
+        if (!b->branches.empty() && part == 0) continue;   // one graph holds every branch
         e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        const sfft_status st = issue_part(b, b->cap_stream, part);
+        const sfft_status st = b->branches.empty() ? issue_part(b, b->cap_stream, part) : issue_branches(b, b->cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (st != SFFT_OK) {
@@ -192,8 +264,10 @@ static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* 
         e = hipEventRecord(reinterpret_cast<hipEvent_t>(ev_fold_begin), s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    e = hipGraphLaunch(b->exec[0], s);
-    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    if (b->exec[0]) {
+        e = hipGraphLaunch(b->exec[0], s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+    }
     if (ev_fold_end) {
         e = hipEventRecord(reinterpret_cast<hipEvent_t>(ev_fold_end), s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");

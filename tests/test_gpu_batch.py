@@ -17,7 +17,8 @@ CONFIGS = [  # (N, K, B, L, w, seed, snr)
 ]
 
 
-def test_batch_matches_single(dev):
+@pytest.mark.parametrize("branches", [1, 2, 3])
+def test_batch_matches_single(dev, branches):
     import torch
     import paper_2012_08238_amd as S
     plans, xs = [], []
@@ -34,7 +35,7 @@ def test_batch_matches_single(dev):
     for p, x in zip(bplans, bx):
         singles.append(tuple(t.clone() for t in p(x, residual=True)))
     torch.cuda.synchronize()
-    batch = S.Batch(bplans)
+    batch = S.Batch(bplans, branches=branches)
     outs = [p.outputs(dev) for p in bplans]
     for rep in range(3):
         for o in outs:
@@ -66,6 +67,29 @@ def test_batch_timed_events(dev):
     b.run_timed(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs], e0, e1)
     torch.cuda.synchronize()
     assert e0.elapsed_ms(e1) > 0
+    for x, o in zip(xs, outs):
+        ref = p(x, residual=True)
+        torch.cuda.synchronize()
+        for a, c in zip(o, ref):
+            assert torch.equal(a, c)
+    b.close()
+    p.close()
+
+
+def test_branched_batch_refuses_fold_events(dev):
+    import torch
+    import paper_2012_08238_amd as S
+    from paper_2012_08238_amd._hip import HipEvent
+    N, K, B, L, w = 1 << 16, 10, 512, 5, 4096
+    p = S.Plan(N, K, B, L, w, seed=1)
+    xs = [torch.from_numpy(make_signal(N, K, 20.0, seed=s).x.astype(np.complex64)).to(dev) for s in range(4)]
+    b = S.Batch([p] * 4, branches=2)
+    outs = [p.outputs(dev) for _ in range(4)]
+    with pytest.raises(S.SfftError) as e:
+        b.run_timed(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs], HipEvent(), HipEvent())
+    assert e.value.status == -4
+    b.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+    torch.cuda.synchronize()
     for x, o in zip(xs, outs):
         ref = p(x, residual=True)
         torch.cuda.synchronize()
