@@ -245,20 +245,37 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
     const uint32_t items = d.L << log2C;
     const uint32_t Mw = d.Mw, w = d.w, maskN = d.maskN;
     const f4v* gT = reinterpret_cast<const f4v*>(d.gT);
-    uint32_t ri[IPT], ci[IPT], si_[IPT], bi[IPT], qi[IPT];
+    uint32_t ri[IPT], ci[IPT], si_[IPT], bi[IPT], qi[IPT], sv[IPT], tv[IPT];
     f4v gi[IPT][G4];
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         const uint32_t it = threadIdx.x + e * kFoldNT;
         ri[e] = it >> log2C;
         ci[e] = it & (C - 1u);
+        si_[e] = sv[e] = tv[e] = 0u;
+    }
+    // sigma_r, sigma_r^{-1}, tau_r through the scalar cache in a uniform loop
+    // over the loops: a vector load here would complete only after the tile's
+    // loads (vector loads retire in issue order) and serialise the taps behind it
+    const uint32_t L = d.L;
+    for (uint32_t r = 0; r < L; ++r) {
+        const uint32_t s = ((CU32)d.sigma)[r], sinv = ((CU32)d.sigma_inv)[r], tu = ((CU32)d.tau)[r];
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) {
+            if (ri[e] == r) {
+                si_[e] = s;
+                sv[e] = sinv;
+                tv[e] = tu;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const uint32_t it = threadIdx.x + e * kFoldNT;
         if (it < items) {
-            const uint32_t r = ri[e];
-            const uint32_t s = gld(d.sigma + r), sinv = gld(d.sigma_inv + r), tu = gld(d.tau + r);
-            const uint32_t b = (sinv * (col0 + ci[e] - tu)) & (B - 1u);
-            si_[e] = s;
+            const uint32_t b = (sv[e] * (col0 + ci[e] - tv[e])) & (B - 1u);
             bi[e] = b;
-            qi[e] = ((s * b + tu) & maskN) >> log2B;
+            qi[e] = ((si_[e] * b + tv[e]) & maskN) >> log2B;
 #pragma unroll
             for (int k = 0; k < G4; ++k) gi[e][k] = gld(gT + (size_t)b * G4 + k);
         }
