@@ -33,7 +33,7 @@ N, K, B, L, W, SNR_DB = 1 << 22, 100, 16384, 9, 131072, 20.0
 PLAN_SEED = 1
 HBM_PEAK_GBPS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_strip_pf_kernel_n22_k100_b64_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2012_08238_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2012_08238_amd", "csrc", "fold.hip")   # the bucketization kernels
 
 
 def alg_bytes_per_signal() -> float:

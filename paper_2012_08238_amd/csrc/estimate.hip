@@ -1,0 +1,453 @@
+// Location by votes, energy-concentration estimation with the median over
+// loops, the K largest in ascending order, and the FP64 residual (formula
+// method, Eq.(2)).
+#include "device.hpp"
+
+namespace sfft {
+
+// ---------------------------------------------------------------- votes
+// A frequency with >= T votes out of L is voted by one of the loops 0..L-T
+// (pigeonhole), so only the frequencies of those loops' selected buckets are
+// enumerated: f = sigma_r0^{-1} p for the N/B permuted positions p of each
+// selected bucket. Each frequency is counted from the first loop that voted
+// for it (later loops skip it), so I' has no duplicates; votes are bitmap tests.
+template <int LMAX>
+__global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged) {
+    extern __shared__ uint32_t sbits[];
+    __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const uint32_t wpl = (d.B + 31u) >> 5;
+    const uint32_t L = d.L, T = d.T, M = d.M, log2M = d.log2M, maskN = d.maskN, B = d.B, dK = d.dK;
+    const uint32_t* jbits = d.jbits;
+    // this workgroup: candidates [start, end) of enumerated loop r0, i.e. the
+    // permuted positions of selected-bucket slots slot0 .. slot0 + nslots - 1
+    const uint32_t upl = d.vote_upl;
+    const uint32_t r0 = unit / upl;
+    const uint32_t per_loop = dK * M;
+    const uint32_t start = (unit - r0 * upl) * kVoteUnit;
+    const uint32_t end = min(start + kVoteUnit, per_loop);
+    const uint32_t slot0 = start >> log2M;
+    const uint32_t nslots = ((end - 1u) >> log2M) - slot0 + 1u;
+    const uint32_t sinv0 = d.sigma_inv[r0];
+    const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
+    for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
+    uint32_t sg[LMAX];   // sigma_r, uniform: scalar loads
+#pragma unroll
+    for (int r = 0; r < LMAX; ++r) sg[r] = (uint32_t)r < L ? ((CU32)d.sigma)[r] : 0u;
+    const uint32_t* bits = jbits;
+    if (staged) {
+        // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte units)
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        const uint32_t nw4 = (L * wpl + 3u) >> 2;
+        const u4v* src = reinterpret_cast<const u4v*>(jbits);
+        u4v* dst = reinterpret_cast<u4v*>(sbits);
+        for (uint32_t i0 = threadIdx.x; i0 < nw4; i0 += 4 * kVoteNT) {
+            u4v t[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) t[e] = gld(src + min(i0 + e * kVoteNT, nw4 - 1u));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t i = i0 + e * kVoteNT;
+                if (i < nw4) dst[i] = t[e];
+            }
+        }
+        bits = sbits;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t* ctr = d.ctr;
+    uint32_t* cand = d.cand;
+    const uint32_t cap = d.cap;
+    for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+        const uint32_t ci = start + qq * kVoteNT + threadIdx.x;   // candidate index within loop r0
+        bool emit = false;
+        uint32_t f = 0;
+        if (ci < end) {
+            const uint32_t h = s_slot[(ci >> log2M) - slot0];
+            const uint32_t p = ((h << log2M) - (M >> 1) + (ci & (M - 1u))) & maskN;
+            f = (sinv0 * p) & maskN;
+            // all L bitmap tests issued together (no serial chain); bit r of `votes`
+            // is set when loop r selected the bucket of f (loop r0 always did)
+            uint32_t votes = 0;
+#pragma unroll
+            for (int r = 0; r < LMAX; ++r) {
+                if ((uint32_t)r < L) {
+                    const uint32_t pr = (sg[r] * f) & maskN;
+                    const uint32_t hr = ((pr + (M >> 1)) >> log2M) & (B - 1u);
+                    votes |= ((bits[(uint32_t)r * wpl + (hr >> 5)] >> (hr & 31u)) & 1u) << r;
+                }
+            }
+            // counted once: from the first loop that voted for f
+            emit = (votes & ((1u << r0) - 1u)) == 0u && (uint32_t)__popc(votes) >= T;
+        }
+        const uint64_t m = __ballot(emit);
+        if (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t base = 0;
+            if ((int)lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if (emit) {
+                const uint32_t pos = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                if (pos < cap) gst(cand + pos, f);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- estimation + output
+template <int N>
+__device__ __forceinline__ void sort_net(float* v) {
+    // bitonic sorting network, ascending, fully unrolled over registers
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const float lo = fminf(v[i], v[l]), hi = fmaxf(v[i], v[l]);
+                    v[i] = up ? lo : hi;
+                    v[l] = up ? hi : lo;
+                }
+            }
+        }
+    }
+}
+
+template <int LMAX>
+__device__ __forceinline__ float median_of(float* v, uint32_t L) {
+    sort_net<LMAX>(v);
+    const uint32_t h = L >> 1;
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int r = 0; r < LMAX; ++r) {
+        if ((uint32_t)r == h) b = v[r];
+        if ((uint32_t)r + 1u == h) a = v[r];
+    }
+    return (L & 1u) ? b : (a + b) * 0.5f;
+}
+
+
+constexpr double inv_fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
+}
+
+// e^{+2 pi i m/N} in FP64 for an exact integer m in [0, N): the root of unity
+// e^{2 pi i (m >> sh) / 2^tb} from the 2^tb-entry table `rou` (tb = log2 N - sh
+// <= 8) times e^{i delta}, delta = (m mod 2^sh) 2 pi / N < 2 pi / 2^tb, whose cos
+// and sin come from their Taylor series to delta^8 and delta^7 (truncation
+// below 1e-20). `step` = 2 pi / N.
+__device__ __forceinline__ double2 phase_of(const double2* rou, uint32_t m, uint32_t sh, double step) {
+    const double2 T = rou[m >> sh];
+    const double delta = (double)(m & ((1u << sh) - 1u)) * step;
+    const double z = -delta * delta;
+    const double s = fma(fma(fma(inv_fact(7), z, inv_fact(5)), z, inv_fact(3)), z, 1.0) * delta;
+    const double c = fma(fma(fma(fma(inv_fact(8), z, inv_fact(6)), z, inv_fact(4)), z, inv_fact(2)), z, 1.0);
+    return make_double2(T.x * c - T.y * s, T.x * s + T.y * c);
+}
+
+// Copy the 2^tb roots of unity (tb <= 8) to LDS.
+template <int NT>
+__device__ __forceinline__ void stage_rou(double2* dst, const double2* src, uint32_t tb) {
+    for (uint32_t i = threadIdx.x; i < (1u << tb); i += NT) dst[i] = gld(src + i);
+}
+
+
+// For each f in I': e_r = uhat_r[h_r(f)] * e^{-2 pi i (tau_r f mod N)/N} / Gtab[o_r(f)]
+// (the energy-concentration estimate of the one frequency assumed in the
+// bucket), x'_f = median_r Re e_r + i median_r Im e_r; then the K largest |x'_f|^2
+// (ties -> lower f), returned in ascending f. One workgroup per signal.
+// Dynamic LDS: P values and P frequencies (P = 2^ceil(log2 K)).
+template <int LMAX>
+__global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
+    extern __shared__ f4v lds_raw[];
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t bc[4];
+    __shared__ uint32_t s_sig[kMaxL], s_tau[kMaxL], s_sinv[kMaxL];
+    __shared__ double2 s_rou[kRouMax];
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const IoDesc io = io_of(a, sig);
+    const uint32_t fftm = d.fft_mode;
+    const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
+    const uint32_t rsh = d.log2N - d.tb;
+    const double step = d.step;
+    uint32_t P = 1;
+    while (P < d.K) P <<= 1;
+    float2* s_v = reinterpret_cast<float2*>(lds_raw);
+    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + P);
+    if (threadIdx.x == 0) bc[3] = min(gld(d.ctr), d.cap);
+    if (threadIdx.x < L) {
+        s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
+        s_tau[threadIdx.x] = gld(d.tau + threadIdx.x);
+        s_sinv[threadIdx.x] = gld(d.sigma_inv + threadIdx.x);
+    }
+    stage_rou<kFinNT>(s_rou, d.rou, d.tb);
+    __syncthreads();
+    const uint32_t n = bc[3];   // block-uniform by construction
+    const uint32_t* cand = d.cand;
+    const float2* invG = d.invG;
+    const float2* uhat = d.uhat;
+    const float2* tw = d.tw;
+    float2* est = d.est;
+    uint64_t* keys = d.keys;
+    for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
+        const uint32_t f = gld(cand + i);
+        float re[LMAX], im[LMAX];
+#pragma unroll
+        for (int r = 0; r < LMAX; ++r) {
+            re[r] = __builtin_inff();
+            im[r] = __builtin_inff();
+            if ((uint32_t)r < L) {
+                const uint32_t p = (s_sig[r] * f) & maskN;
+                const uint32_t h = ((p + (M >> 1)) >> log2M) & (B - 1u);
+                const uint32_t o = (p - (h << log2M) + (N >> 1)) & maskN;   // o + N/2
+                const uint32_t gi = o - (N >> 1) + (M >> 1);
+                const float2 g = gld(invG + gi);
+                float2 uv;
+                if (fftm) {
+                    // two-pass FFT layout: X[h] = e^{+2 pi i (s tau h mod B)/B} V[s h mod B], s = sigma^{-1}
+                    const uint32_t si = s_sinv[r];
+                    const float2 t = gld(tw + ((si * s_tau[r] * h) & (B - 1u)));   // e^{-2 pi i ./B}
+                    uv = cmul(gld(uhat + (size_t)r * B + ((si * h) & (B - 1u))), make_float2(t.x, -t.y));
+                } else {
+                    uv = gld(uhat + (size_t)r * B + h);
+                }
+                const uint32_t k = (s_tau[r] * f) & maskN;
+                const double2 pk = phase_of(s_rou, k, rsh, step);   // e^{+2 pi i k/N}
+                const float2 rot = make_float2((float)pk.x, -(float)pk.y);
+                const float2 e = cmul(cmul(uv, rot), g);
+                re[r] = e.x;
+                im[r] = e.y;
+            }
+        }
+        const float mr = median_of<LMAX>(re, L);
+        const float mi = median_of<LMAX>(im, L);
+        const float mag = fmaf(mr, mr, mi * mi);
+        gst(est + i, make_float2(mr, mi));
+        gst(keys + i, ((uint64_t)(0xFFFFFFFFu - __float_as_uint(mag)) << 32) | (uint64_t)f);
+    }
+    __syncthreads();
+    const uint32_t K = d.K;
+    uint64_t thr = ~0ull;
+    if (n > K) {
+        // K-th smallest key (keys are unique: the low word is f)
+        uint64_t prefix = 0, pmask = 0;
+        uint32_t kk = K;
+        const uint32_t lane = threadIdx.x & 63u;
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            for (int i = threadIdx.x; i < 256; i += kFinNT) hist[i] = 0;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
+                const uint64_t key = gld(keys + i);
+                if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                const int lo = 4 * (int)lane;   // lane 0 owns the smallest digits
+                const uint32_t h0 = hist[lo], h1 = hist[lo + 1], h2 = hist[lo + 2], h3 = hist[lo + 3];
+                const uint32_t s = h0 + h1 + h2 + h3;
+                const uint32_t incl = wave_incl_scan(s);
+                const uint32_t excl = incl - s;
+                if (excl < kk && kk <= incl) {
+                    uint32_t acc = excl, dsel, rem;
+                    if (acc + h0 >= kk) {
+                        dsel = lo;
+                        rem = kk - acc;
+                    } else if (acc += h0, acc + h1 >= kk) {
+                        dsel = lo + 1;
+                        rem = kk - acc;
+                    } else if (acc += h1, acc + h2 >= kk) {
+                        dsel = lo + 2;
+                        rem = kk - acc;
+                    } else {
+                        acc += h2;
+                        dsel = lo + 3;
+                        rem = kk - acc;
+                    }
+                    bc[0] = dsel;
+                    bc[1] = rem;
+                }
+            }
+            __syncthreads();
+            prefix |= (uint64_t)bc[0] << shift;
+            pmask |= 255ull << shift;
+            kk = bc[1];
+            __syncthreads();
+        }
+        thr = prefix;
+    }
+    if (threadIdx.x == 0) bc[2] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
+        const uint64_t key = gld(keys + i);
+        if (key <= thr) {
+            const uint32_t pos = atomicAdd(&bc[2], 1u);
+            if (pos < P) {
+                s_f[pos] = (uint32_t)key;
+                s_v[pos] = gld(est + i);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = min(bc[2], K);
+    uint32_t Q = 1;   // sort size: power of two >= cnt (<= P)
+    while (Q < cnt) Q <<= 1;
+    for (uint32_t i = cnt + threadIdx.x; i < Q; i += kFinNT) {
+        s_f[i] = 0xFFFFFFFFu;
+        s_v[i] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= Q; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < Q; i += kFinNT) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint32_t fi = s_f[i], fl = s_f[l];
+                    if ((fi > fl) == up) {
+                        s_f[i] = fl;
+                        s_f[l] = fi;
+                        const float2 t = s_v[i];
+                        s_v[i] = s_v[l];
+                        s_v[l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t k = threadIdx.x; k < K; k += kFinNT) {
+        if (k < cnt) {
+            gst(io.out_idx + k, (int64_t)s_f[k]);
+            gst(io.out_val + k, s_v[k]);
+        } else {
+            gst(io.out_idx + k, (int64_t)-1);
+            gst(io.out_val + k, make_float2(0.f, 0.f));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- FP64 residual
+// E_res = mean_t |x_t - sum_k v_k e^{+2 pi i (t f_k mod N)/N}|^2 and
+// E_in = mean_t |x_t|^2 over the S residual samples. The outputs are staged in
+// LDS (dynamic: K values, K frequencies); the phase of the exact integer
+// t f mod N is evaluated in FP64 (phase_of). Partial sums are reduced in a
+// fixed order by the last workgroup to finish.
+__global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
+    extern __shared__ f4v lds_raw[];
+    __shared__ double sh[2][kResNT / 64];
+    __shared__ uint32_t is_last;
+    __shared__ double2 s_rou[kRouMax];
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const IoDesc io = io_of(a, sig);
+    const uint32_t K = d.K, maskN = d.maskN;
+    const uint32_t rsh = d.log2N - d.tb;
+    const double step = d.step;
+    float2* s_v = reinterpret_cast<float2*>(lds_raw);
+    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + K);
+    stage_rou<kResNT>(s_rou, d.rou, d.tb);
+    for (uint32_t k = threadIdx.x; k < K; k += kResNT) {
+        const int64_t f = gld(io.out_idx + k);
+        s_f[k] = f < 0 ? 0xFFFFFFFFu : (uint32_t)f;
+        s_v[k] = gld(io.out_val + k);
+    }
+    __syncthreads();
+    const uint32_t j = unit * kResNT + threadIdx.x;
+    double ea = 0.0, eb = 0.0;
+    if (j < d.S) {
+        const uint32_t t = gld(d.tpos + j);
+        const float2 xv = gld(io.x + t);
+        const double xr = xv.x, xi = xv.y;
+        double mr = 0.0, mi = 0.0;
+        for (uint32_t k = 0; k < K; ++k) {
+            const uint32_t f = s_f[k];
+            if (f == 0xFFFFFFFFu) continue;   // padding (uniform across the block)
+            const double2 p = phase_of(s_rou, (t * f) & maskN, rsh, step);
+            const float2 v = s_v[k];
+            mr += (double)v.x * p.x - (double)v.y * p.y;
+            mi += (double)v.x * p.y + (double)v.y * p.x;
+        }
+        const double er = xr - mr, ei = xi - mi;
+        ea = er * er + ei * ei;
+        eb = xr * xr + xi * xi;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ea += __shfl_down(ea, off, 64);
+        eb += __shfl_down(eb, off, 64);
+    }
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wid] = ea;
+        sh[1][wid] = eb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0.0, Bs = 0.0;
+#pragma unroll
+        for (int w = 0; w < kResNT / 64; ++w) {
+            A += sh[0][w];
+            Bs += sh[1][w];
+        }
+        gst(d.rpart + 2 * unit, A);
+        gst(d.rpart + 2 * unit + 1, Bs);
+        __threadfence();
+        const uint32_t prev = atomicAdd(d.ctr + 1, 1u);
+        is_last = (prev + 1u == d.resid_blocks) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (is_last && threadIdx.x == 0) {
+        __threadfence();
+        const volatile double* rp = d.rpart;
+        double A = 0.0, Bs = 0.0;
+        for (uint32_t u = 0; u < d.resid_blocks; ++u) {
+            A += rp[2 * u];
+            Bs += rp[2 * u + 1];
+        }
+        double* out = io.out_resid ? io.out_resid : d.resid_own;
+        gst(out + 0, A / (double)d.S);
+        gst(out + 1, Bs / (double)d.S);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
+    const uint32_t staged = lds_bytes ? 1u : 0u;
+    switch (lmax) {
+        case 4: hipLaunchKernelGGL(vote_kernel<4>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 8: hipLaunchKernelGGL(vote_kernel<8>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 16: hipLaunchKernelGGL(vote_kernel<16>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 32: hipLaunchKernelGGL(vote_kernel<32>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds, hipStream_t s) {
+    switch (lmax) {
+        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 16: hipLaunchKernelGGL(finalize_kernel<16>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 32: hipLaunchKernelGGL(finalize_kernel<32>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(units), dim3(kResNT), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sfft

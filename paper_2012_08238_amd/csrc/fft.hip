@@ -1,0 +1,835 @@
+// B-point DFT of each loop's bucket values and the selection of the d*K
+// largest buckets: one workgroup per loop in LDS up to B = 16384, two passes
+// through the workspace and a selection workgroup beyond.
+#include "device.hpp"
+
+namespace sfft {
+
+// ---------------------------------------------------------------- B-point FFT
+// In-register DFTs of size 2, 4, 8, 16 (forward, e^{-2 pi i jk/R}), natural
+// order in and out, by radix-2 decimation in time.
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // a * (-i)
+
+template <int R>
+struct SmallDft;
+
+template <>
+struct SmallDft<2> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float2 a = v[0], b = v[1];
+        v[0] = make_float2(a.x + b.x, a.y + b.y);
+        v[1] = make_float2(a.x - b.x, a.y - b.y);
+    }
+};
+
+template <>
+struct SmallDft<4> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float2 a0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const float2 a1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const float2 a2 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const float2 a3 = mul_mi(make_float2(v[1].x - v[3].x, v[1].y - v[3].y));
+        v[0] = make_float2(a0.x + a2.x, a0.y + a2.y);
+        v[2] = make_float2(a0.x - a2.x, a0.y - a2.y);
+        v[1] = make_float2(a1.x + a3.x, a1.y + a3.y);
+        v[3] = make_float2(a1.x - a3.x, a1.y - a3.y);
+    }
+};
+
+// cos / sin of 2 pi k / 16 for k = 0..7
+__device__ constexpr float kC16[8] = {1.0f, 0.92387953251128676f, 0.70710678118654752f, 0.38268343236508977f,
+                                      0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128676f};
+__device__ constexpr float kS16[8] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128676f,
+                                      1.0f, 0.92387953251128676f, 0.70710678118654752f, 0.38268343236508977f};
+
+template <int R>
+struct SmallDft {
+    // split into even / odd halves, combine with W_R^k = e^{-2 pi i k / R}
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            e[k] = v[2 * k];
+            o[k] = v[2 * k + 1];
+        }
+        SmallDft<R / 2>::run(e);
+        SmallDft<R / 2>::run(o);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            const int t = k * (16 / R);
+            const float2 w = make_float2(kC16[t], -kS16[t]);
+            const float2 ow = (k == 0) ? o[k] : cmul(o[k], w);
+            v[k] = make_float2(e[k].x + ow.x, e[k].y + ow.y);
+            v[k + R / 2] = make_float2(e[k].x - ow.x, e[k].y - ow.y);
+        }
+    }
+};
+
+template <int LOG2B>
+struct FftCfg {
+    static constexpr int B = 1 << LOG2B;
+    static constexpr int NT = B / 16 < 64 ? 64 : (B / 16 > 1024 ? 1024 : B / 16);
+    static constexpr int LOG2TL = (LOG2B + 1) / 2;   // twiddle table split: m = hi * TL + lo
+    static constexpr int TL = 1 << LOG2TL;
+    static constexpr int TH = B >> LOG2TL;
+    static constexpr int PADN = B + (B >> 4) + 1;    // one pad element per 16 (bank spread)
+    static constexpr int CH = B >= NT ? B / NT : 1;  // energies held per thread
+    static constexpr int NW = B >= 32 ? B / 32 : 1;  // bitmap words
+    // candidate capacity of the prefiltered selection: (energy, bucket) pairs
+    // placed in the data region after the bitmap words, a multiple of NT
+    static constexpr int SELCAP_RAW = (PADN * 2 - NW - 64) / 2;
+    static constexpr int SELCAP = (SELCAP_RAW > 4096 ? 4096 : SELCAP_RAW) / NT * NT;
+    static constexpr size_t lds_bytes() {
+        return (size_t)(PADN + TL + TH) * sizeof(float2) + (256 + 16 + 4) * sizeof(uint32_t);
+    }
+};
+
+__device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
+
+// One Stockham autosort pass of radix R over the B values in LDS; Ns is the
+// product of the radices of the passes before. Butterfly j reads
+// lds[j + r*B/R], is twisted by W_{Ns R}^{r (j mod Ns)}, transformed, and
+// written to lds[(j - j mod Ns) R + j mod Ns + r Ns]. Twiddles W_B^m come from
+// two LDS tables: W_B^m = hi[m / TL] * lo[m mod TL].
+template <int LOG2B, int LOG2R, int LOG2NS>
+__device__ __forceinline__ void stockham_pass(float2* lds, const float2* tlo, const float2* thi) {
+    using Cfg = FftCfg<LOG2B>;
+    constexpr int B = Cfg::B, NT = Cfg::NT, R = 1 << LOG2R, Ns = 1 << LOG2NS;
+    constexpr int NBF = B / R;
+    constexpr int NPER = NBF >= NT ? NBF / NT : 1;
+    constexpr int TSHIFT = LOG2B - LOG2NS - LOG2R;
+    float2 v[NPER][R];
+#pragma unroll
+    for (int q = 0; q < NPER; ++q) {
+        const int j = (int)threadIdx.x + q * NT;
+        if (j < NBF) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = lds[padi(j + r * NBF)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NPER; ++q) {
+        const int j = (int)threadIdx.x + q * NT;
+        if (j < NBF) {
+            const int k = j & (Ns - 1);
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const int m = (r * k) << TSHIFT;
+                    const float2 w = cmul(thi[m >> Cfg::LOG2TL], tlo[m & (Cfg::TL - 1)]);
+                    v[q][r] = cmul(v[q][r], w);
+                }
+            }
+            SmallDft<R>::run(v[q]);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[padi(base + r * Ns)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int LOG2B, int LOG2NS>
+__device__ __forceinline__ void fft_passes(float2* lds, const float2* tlo, const float2* thi) {
+    constexpr int REM = LOG2B - LOG2NS;
+    if constexpr (REM >= 4) {
+        stockham_pass<LOG2B, 4, LOG2NS>(lds, tlo, thi);
+        fft_passes<LOG2B, LOG2NS + 4>(lds, tlo, thi);
+    } else if constexpr (REM > 0) {
+        stockham_pass<LOG2B, REM, LOG2NS>(lds, tlo, thi);
+    }
+}
+
+// k-th largest (1-based; k <= number of valid keys) of the keys held by the
+// block, KPT per thread: radix select on 8-bit digits from the top through an
+// LDS histogram. The first digit (shared by most keys) is counted with one
+// atomic per distinct digit per wave. Returns the value and how many keys equal
+// to it are among the k largest.
+template <int NT, int KPT>
+__device__ __forceinline__ void block_kth_largest(const uint32_t* key, const bool* kv, uint32_t k, uint32_t* hist,
+                                                  uint32_t* bcast, uint32_t& theta, uint32_t& rank) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t prefix = 0, pmask = 0, kk = k;
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < KPT; ++c) {
+            const bool act = kv[c] && ((key[c] & pmask) == prefix);
+            const uint32_t dg = (key[c] >> shift) & 255u;
+            if (pass == 0) {
+                uint64_t pend = __ballot(act);
+                while (pend) {
+                    const int leader = __ffsll((unsigned long long)pend) - 1;
+                    const uint32_t dl = __shfl(dg, leader, 64);
+                    const uint64_t same = __ballot(act && dg == dl) & pend;
+                    if ((int)lane == leader) atomicAdd(&hist[dl], (uint32_t)__popcll(same));
+                    pend &= ~same;
+                }
+            } else if (act) {
+                atomicAdd(&hist[dg], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int top = 255 - 4 * (int)lane;   // lane 0 owns the largest digits
+            const uint32_t h0 = hist[top], h1 = hist[top - 1], h2 = hist[top - 2], h3 = hist[top - 3];
+            const uint32_t s = h0 + h1 + h2 + h3;
+            const uint32_t incl = wave_incl_scan(s);
+            const uint32_t excl = incl - s;
+            if (excl < kk && kk <= incl) {
+                uint32_t acc = excl, dsel, rem;
+                if (acc + h0 >= kk) {
+                    dsel = top;
+                    rem = kk - acc;
+                } else if (acc += h0, acc + h1 >= kk) {
+                    dsel = top - 1;
+                    rem = kk - acc;
+                } else if (acc += h1, acc + h2 >= kk) {
+                    dsel = top - 2;
+                    rem = kk - acc;
+                } else {
+                    acc += h2;
+                    dsel = top - 3;
+                    rem = kk - acc;
+                }
+                bcast[0] = dsel;
+                bcast[1] = rem;
+            }
+        }
+        __syncthreads();
+        prefix |= bcast[0] << shift;
+        pmask |= 255u << shift;
+        kk = bcast[1];
+        __syncthreads();
+    }
+    theta = prefix;
+    rank = kk;
+}
+
+// Mask of this thread's keys (KPT per thread, block order = thread-major) among
+// the k largest: every key above theta and the first `rank` keys equal to it.
+template <int NT, int KPT>
+__device__ __forceinline__ uint64_t select_mask(const uint32_t* key, const bool* kv, uint32_t theta, uint32_t rank,
+                                                uint32_t* scan) {
+    uint32_t eq = 0;
+#pragma unroll
+    for (int c = 0; c < KPT; ++c) eq += (kv[c] && key[c] == theta) ? 1u : 0u;
+    uint32_t tot;
+    uint32_t eqrank = block_excl_scan<NT>(eq, scan, tot);
+    uint64_t selm = 0;
+#pragma unroll
+    for (int c = 0; c < KPT; ++c) {
+        bool sel = false;
+        if (kv[c]) {
+            if (key[c] > theta) {
+                sel = true;
+            } else if (key[c] == theta) {
+                sel = eqrank < rank;
+                ++eqrank;
+            }
+        }
+        if (sel) selm |= 1ull << c;
+    }
+    return selm;
+}
+
+// Write the selected buckets: the bitmap (built in LDS) and the ascending list.
+template <int NT, int KPT, typename IdxF>
+__device__ __forceinline__ void emit_selection(uint64_t selm, IdxF idx_of, uint32_t* bits, int nw, uint32_t* scan,
+                                               uint32_t* jl, uint32_t* jb, uint32_t dK) {
+    for (int i = threadIdx.x; i < nw; i += NT) bits[i] = 0;
+    __syncthreads();
+    uint32_t tot;
+    uint32_t pos = block_excl_scan<NT>((uint32_t)__popcll(selm), scan, tot);
+#pragma unroll
+    for (int c = 0; c < KPT; ++c) {
+        if ((selm >> c) & 1ull) {
+            const uint32_t h = idx_of(c);
+            atomicOr(&bits[h >> 5], 1u << (h & 31));
+            if (pos < dK) gst(jl + pos, h);
+            ++pos;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nw; i += NT) gst(jb + i, bits[i]);
+}
+
+// Selection of the dK largest |uhat|^2 (ties -> lower bucket): radix select on
+// the IEEE bit patterns of the non-negative energies (monotone as unsigned),
+// four 8-bit digits from the top. Digit counts go to an LDS histogram; the
+// first digit (sign + high exponent bits, shared by most buckets) is counted
+// with one atomic per distinct digit per wave.
+template <int LOG2B>
+__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a) {
+    using Cfg = FftCfg<LOG2B>;
+    constexpr int B = Cfg::B, NT = Cfg::NT, CH = Cfg::CH, NW = Cfg::NW;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tlo = data + Cfg::PADN;
+    float2* thi = tlo + Cfg::TL;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(thi + Cfg::TH);
+    uint32_t* scan = hist + 256;   // NT/64 <= 16 words
+    uint32_t* bcast = scan + 16;   // [0] digit, [1] remaining rank
+    uint32_t* bits = reinterpret_cast<uint32_t*>(data);  // reuses the data region at the end
+
+    uint32_t sig, r;
+    resolve(a, sig, r);
+    const auto& d = desc_of(a, sig);
+    float2* u = d.uhat + (size_t)r * B;
+    const float2* tw = d.tw;
+    {
+        // the bucketization stored loop r's values in column order: column col
+        // holds bucket b = sigma_r^{-1} (col - tau_r) mod B; place them by bucket
+        const uint32_t sinv = d.sigma_inv[r], tu = d.tau[r];
+        constexpr int LPT = (B + NT - 1) / NT;
+        float2 tmp[LPT];
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int col = min((int)threadIdx.x + q * NT, B - 1);
+            tmp[q] = gld(u + col);
+        }
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const uint32_t col = threadIdx.x + q * NT;
+            if (col < (uint32_t)B) data[padi((int)((sinv * (col - tu)) & (uint32_t)(B - 1)))] = tmp[q];
+        }
+    }
+    for (int j = threadIdx.x; j < Cfg::TL; j += NT) tlo[j] = gld(tw + j);
+    for (int j = threadIdx.x; j < Cfg::TH; j += NT) thi[j] = gld(tw + (j << Cfg::LOG2TL));
+    __syncthreads();
+    fft_passes<LOG2B, 0>(data, tlo, thi);
+    for (int h = threadIdx.x; h < B; h += NT) gst(u + h, data[padi(h)]);
+
+    const bool valid = (int)threadIdx.x * CH < B;
+    uint32_t key[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        key[c] = 0;
+        if (valid) {
+            const float2 v = data[padi(threadIdx.x * CH + c)];
+            key[c] = energy_key(v);
+        }
+    }
+    const uint32_t dK = d.dK;
+    uint32_t* jl = d.jlist + (size_t)r * dK;
+    uint32_t* jb = d.jbits + (size_t)r * NW;
+    bool kv[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) kv[c] = valid;
+    bool done = false;
+    if constexpr (CH >= 4 && Cfg::SELCAP >= NT) {
+        if (dK <= (uint32_t)NT) {
+            // Every one of the dK largest energies is >= theta0, the dK-th largest of
+            // the per-thread maxima (at least dK threads hold a value >= theta0), so
+            // only the keys >= theta0 can be selected. Collect them (in bucket
+            // order) and select exactly among those when they are few.
+            uint32_t tmax[1] = {0};
+            const bool tv[1] = {valid};
+#pragma unroll
+            for (int c = 0; c < CH; ++c) tmax[0] = max(tmax[0], key[c]);
+            uint32_t theta0, rank0;
+            block_kth_largest<NT, 1>(tmax, tv, dK, hist, bcast, theta0, rank0);
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) cnt += (valid && key[c] >= theta0) ? 1u : 0u;
+            uint32_t total;
+            uint32_t base = block_excl_scan<NT>(cnt, scan, total);
+            if (total <= (uint32_t)Cfg::SELCAP) {   // block-uniform
+                uint32_t* ckey = bits + Cfg::NW + 64;
+                uint32_t* cidx = ckey + Cfg::SELCAP;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (valid && key[c] >= theta0) {
+                        ckey[base] = key[c];
+                        cidx[base] = threadIdx.x * CH + c;
+                        ++base;
+                    }
+                }
+                __syncthreads();
+                constexpr int CPT = Cfg::SELCAP / NT;
+                uint32_t ck[CPT];
+                bool cv[CPT];
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) {
+                    const uint32_t i = threadIdx.x * CPT + q;
+                    cv[q] = i < total;
+                    ck[q] = cv[q] ? ckey[i] : 0u;
+                }
+                uint32_t theta, rank;
+                block_kth_largest<NT, CPT>(ck, cv, dK, hist, bcast, theta, rank);
+                const uint64_t selm = select_mask<NT, CPT>(ck, cv, theta, rank, scan);
+                emit_selection<NT, CPT>(selm, [&](int q) { return cidx[threadIdx.x * CPT + q]; }, bits, NW, scan,
+                                        jl, jb, dK);
+                done = true;
+            }
+        }
+    }
+    if (!done) {   // block-uniform
+        uint32_t theta, rank;
+        block_kth_largest<NT, CH>(key, kv, dK, hist, bcast, theta, rank);
+        const uint64_t selm = select_mask<NT, CH>(key, kv, theta, rank, scan);
+        emit_selection<NT, CH>(selm, [&](int c) { return (uint32_t)(threadIdx.x * CH + c); }, bits, NW, scan, jl, jb,
+                               dK);
+    }
+}
+
+
+// ---------------------------------------------------------------- two-pass FFT (B > 16384)
+// The bucketization leaves the bucket values in column order, v[col] = u[b] with
+// col = sigma b + tau mod B. Instead of moving them into bucket order first, the
+// DFT V of v is taken as it stands: with s = sigma^{-1} mod B,
+//   X[h] = sum_b u[b] e^{-2 pi i bh/B} = e^{+2 pi i (s tau h mod B)/B} V[s h mod B],
+// so bucket h's DFT value is V at m = s h mod B times a unit phase, and the
+// energies |X[h]|^2 are those of V at m (h = sigma m mod B). V is computed in four
+// steps over the B1 x B2 row-major view (col = B2 j1 + j2, B = B1 B2): DFTs of
+// length B1 down the columns, the twist W_B^{j2 k1}, DFTs of length B2 along the
+// rows, V[k1 + B1 k2] = sum_j2 W_B2^{j2 k2} W_B^{j2 k1} sum_j1 W_B1^{j1 k1} v[B2 j1 + j2].
+// Each workgroup transforms 16 sequences, so every global access moves 16
+// consecutive values. The second pass also records the largest energy of every
+// 16 consecutive V entries, which lets the selection visit few of them.
+template <int LB>
+struct LargeCfg {
+    static constexpr int B = 1 << LB;
+    static constexpr int LB1 = (LB + 1) / 2, LB2 = LB / 2;
+    static constexpr int B1 = 1 << LB1, B2 = 1 << LB2;
+    static constexpr int NT = 256;       // FFT pass workgroups: 16 sequences each
+    static constexpr int G = B / 16;     // groups of 16 consecutive V entries
+    static constexpr int SNT = 1024;     // selection workgroup
+    static constexpr int NW = B / 32;    // bitmap words
+    static constexpr int SELCAP = 8192;  // candidates of the prefiltered selection held in LDS
+};
+
+// NSEQ DFTs of length 2^LP at once in LDS (sequence q at q*SP, element j at
+// padi(j)): Stockham autosort passes as stockham_pass, twiddles tp[m] = W_P^m.
+template <int LP, int NSEQ, int NT>
+struct SeqFft {
+    static constexpr int P = 1 << LP;
+    static constexpr int SP = P + (P >> 4) + 1;
+    static constexpr size_t lds_bytes() { return (size_t)(NSEQ * SP + P) * sizeof(float2); }
+
+    template <int LOG2R, int LOG2NS>
+    __device__ __forceinline__ static void pass(float2* lds, const float2* tp) {
+        constexpr int R = 1 << LOG2R, Ns = 1 << LOG2NS, NBF = P / R, TOT = NSEQ * NBF;
+        constexpr int NPER = (TOT + NT - 1) / NT;
+        constexpr int TSHIFT = LP - LOG2NS - LOG2R;
+        float2 v[NPER][R];
+#pragma unroll
+        for (int q = 0; q < NPER; ++q) {
+            const int idx = (int)threadIdx.x + q * NT;
+            if (idx < TOT) {
+                const float2* base = lds + (idx / NBF) * SP;
+                const int j = idx % NBF;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = base[padi(j + r * NBF)];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NPER; ++q) {
+            const int idx = (int)threadIdx.x + q * NT;
+            if (idx < TOT) {
+                const int j = idx % NBF, k = j & (Ns - 1);
+                if (Ns > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tp[(r * k) << TSHIFT]);
+                }
+                SmallDft<R>::run(v[q]);
+                float2* base = lds + (idx / NBF) * SP;
+                const int o = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) base[padi(o + r * Ns)] = v[q][r];
+            }
+        }
+        __syncthreads();
+    }
+
+    template <int LOG2NS = 0>
+    __device__ __forceinline__ static void run(float2* lds, const float2* tp) {
+        constexpr int REM = LP - LOG2NS;
+        if constexpr (REM >= 4) {
+            pass<4, LOG2NS>(lds, tp);
+            run<LOG2NS + 4>(lds, tp);
+        } else if constexpr (REM > 0) {
+            pass<REM, LOG2NS>(lds, tp);
+        }
+    }
+};
+
+// First pass: 16 columns j2 of the B1 x B2 view per workgroup -> ubuf, row-major
+// [k1][j2], twisted. Units per signal: L * B2/16.
+template <int LB>
+__global__ __launch_bounds__(256) void fft_large_p1_kernel(Launch a) {
+    using C = LargeCfg<LB>;
+    using F = SeqFft<C::LB1, 16, C::NT>;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tp = data + 16 * F::SP;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    constexpr uint32_t tiles = C::B2 / 16;
+    const uint32_t r = unit / tiles, j20 = (unit % tiles) * 16u;
+    const float2* v = d.uhat + (size_t)r * C::B;
+    float2* y = d.ubuf + (size_t)r * C::B;
+    const float2* tw = d.tw;
+    constexpr int NE = 16 * C::B1 / C::NT;   // values per thread
+    constexpr int CHK = 8;
+    static_assert(NE % CHK == 0, "load chunks");
+#pragma unroll
+    for (int q0 = 0; q0 < NE; q0 += CHK) {
+        float2 t[CHK];
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            t[u] = gld(v + (size_t)(e >> 4) * C::B2 + j20 + (e & 15));
+        }
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            data[(e & 15) * F::SP + padi(e >> 4)] = t[u];
+        }
+    }
+    for (int m = threadIdx.x; m < C::B1; m += C::NT) tp[m] = gld(tw + ((size_t)m << (LB - C::LB1)));
+    __syncthreads();
+    F::run(data, tp);
+#pragma unroll 4
+    for (int q = 0; q < NE; ++q) {
+        const int e = (int)threadIdx.x + q * C::NT;
+        const uint32_t k1 = (uint32_t)e >> 4, j2 = j20 + (uint32_t)(e & 15);
+        const float2 t = gld(tw + ((j2 * k1) & (uint32_t)(C::B - 1)));   // W_B^{j2 k1}
+        gst(y + (size_t)k1 * C::B2 + j2, cmul(data[(e & 15) * F::SP + padi((int)k1)], t));
+    }
+}
+
+// Second pass: 16 rows k1 per workgroup -> V[k1 + B1 k2] into uhat, and the
+// largest energy of each 16 consecutive V entries into gmax. Units: L * B1/16.
+template <int LB>
+__global__ __launch_bounds__(256) void fft_large_p2_kernel(Launch a) {
+    using C = LargeCfg<LB>;
+    using F = SeqFft<C::LB2, 16, C::NT>;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tp = data + 16 * F::SP;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    constexpr uint32_t tiles = C::B1 / 16;
+    const uint32_t r = unit / tiles, k10 = (unit % tiles) * 16u;
+    const float2* y = d.ubuf + (size_t)r * C::B;
+    float2* V = d.uhat + (size_t)r * C::B;
+    uint32_t* gm = d.gmax + (size_t)r * C::G;
+    constexpr int NE = 16 * C::B2 / C::NT;
+    constexpr int CHK = 8;
+    static_assert(NE % CHK == 0, "load chunks");
+#pragma unroll
+    for (int q0 = 0; q0 < NE; q0 += CHK) {
+        float2 t[CHK];
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            t[u] = gld(y + (size_t)(k10 + (uint32_t)(e >> C::LB2)) * C::B2 + (e & (C::B2 - 1)));
+        }
+#pragma unroll
+        for (int u = 0; u < CHK; ++u) {
+            const int e = (int)threadIdx.x + (q0 + u) * C::NT;
+            data[(e >> C::LB2) * F::SP + padi(e & (C::B2 - 1))] = t[u];
+        }
+    }
+    for (int m = threadIdx.x; m < C::B2; m += C::NT) tp[m] = gld(d.tw + ((size_t)m << (LB - C::LB2)));
+    __syncthreads();
+    F::run(data, tp);
+#pragma unroll 4
+    for (int q = 0; q < NE; ++q) {
+        const int e = (int)threadIdx.x + q * C::NT;
+        const int c = e & 15, k2 = e >> 4;
+        const float2 val = data[c * F::SP + padi(k2)];
+        const uint32_t m0 = k10 + (uint32_t)C::B1 * (uint32_t)k2;   // multiple of 16
+        gst(V + m0 + c, val);
+        uint32_t mx = energy_key(val);
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+        if (c == 0) gst(gm + (m0 >> 4), mx);
+    }
+}
+
+// k-th largest (1-based, k <= number of valid keys) of n keys produced by
+// keyf(i, key) -> valid, streamed 4 times (8-bit digits from the top, LDS
+// histogram). Returns the value and how many keys equal to it are among the k largest.
+template <int NT, class KeyF>
+__device__ __forceinline__ void stream_kth_largest(uint32_t n, uint32_t k, KeyF keyf, uint32_t* hist, uint32_t* bc,
+                                                   uint32_t& theta, uint32_t& rank) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t prefix = 0, pmask = 0, kk = k;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (uint32_t i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += NT) {
+            uint32_t key;
+            if (keyf(i, key) && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int hi = 255 - 4 * (int)lane;   // lane 0 owns the largest digits
+            const uint32_t h0 = hist[hi], h1 = hist[hi - 1], h2 = hist[hi - 2], h3 = hist[hi - 3];
+            const uint32_t sum = h0 + h1 + h2 + h3;
+            const uint32_t incl = wave_incl_scan(sum);
+            const uint32_t excl = incl - sum;
+            if (excl < kk && kk <= incl) {
+                uint32_t acc = excl, dsel, rem;
+                if (acc + h0 >= kk) {
+                    dsel = hi;
+                    rem = kk - acc;
+                } else if (acc += h0, acc + h1 >= kk) {
+                    dsel = hi - 1;
+                    rem = kk - acc;
+                } else if (acc += h1, acc + h2 >= kk) {
+                    dsel = hi - 2;
+                    rem = kk - acc;
+                } else {
+                    acc += h2;
+                    dsel = hi - 3;
+                    rem = kk - acc;
+                }
+                bc[0] = dsel;
+                bc[1] = rem;
+            }
+        }
+        __syncthreads();
+        prefix |= bc[0] << shift;
+        pmask |= 255u << shift;
+        kk = bc[1];
+        __syncthreads();
+    }
+    theta = prefix;
+    rank = kk;
+}
+
+// Selection of the dK largest bucket energies (ties -> lower bucket) from V in m
+// order; bucket h = sigma m mod B. Fast path: theta0 = the dK-th largest group
+// maximum bounds the dK-th largest energy from below (at least dK groups hold an
+// energy >= theta0), so only entries >= theta0 of groups whose maximum reaches
+// theta0 are collected and selected exactly in LDS. When the bound admits too
+// many entries (flat spectra) every entry is streamed instead. One workgroup per
+// (signal, loop). Dynamic LDS: bitmap words + SELCAP (energy, bucket) pairs.
+template <int LB>
+__global__ __launch_bounds__(1024) void select_large_kernel(Launch a) {
+    using C = LargeCfg<LB>;
+    constexpr int NT = C::SNT, G = C::G, NW = C::NW, CAP = C::SELCAP;
+    constexpr uint32_t Bm = (uint32_t)C::B - 1u;
+    extern __shared__ uint32_t lds_words[];
+    uint32_t* bits = lds_words;
+    uint32_t* ckey = bits + NW;
+    uint32_t* cidx = ckey + CAP;
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t bc[4];
+    __shared__ uint32_t scan[NT / 64];
+    __shared__ uint32_t s_cnt, s_eq;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const uint32_t r = unit, dK = d.dK;
+    const uint32_t sg = ((CU32)d.sigma)[r];
+    const float2* V = d.uhat + (size_t)r * C::B;
+    const uint32_t* gm = d.gmax + (size_t)r * G;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)NW; i += NT) bits[i] = 0;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_eq = 0;
+    }
+    __syncthreads();
+    bool fast = dK <= (uint32_t)G;   // block-uniform
+    uint32_t n = 0;
+    if (fast) {
+        uint32_t theta0, rank0;
+        stream_kth_largest<NT>((uint32_t)G, dK, [&](uint32_t i, uint32_t& k) { k = gld(gm + i); return true; }, hist,
+                               bc, theta0, rank0);
+        for (uint32_t g = threadIdx.x; g < (uint32_t)G; g += NT) {
+            if (gld(gm + g) < theta0) continue;
+            const f4v* p = reinterpret_cast<const f4v*>(V + (size_t)g * 16u);
+            f4v t[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) t[c] = gld(p + c);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const f4v& q = t[c >> 1];
+                const float2 val = (c & 1) ? make_float2(q[2], q[3]) : make_float2(q[0], q[1]);
+                const uint32_t k = energy_key(val);
+                if (k >= theta0) {
+                    const uint32_t pos = atomicAdd(&s_cnt, 1u);
+                    if (pos < (uint32_t)CAP) {
+                        ckey[pos] = k;
+                        cidx[pos] = (sg * (g * 16u + (uint32_t)c)) & Bm;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        n = s_cnt;
+        fast = n <= (uint32_t)CAP;
+    }
+    // energy and bucket of entry i of the working set (candidates, or all of V)
+    auto entry = [&](uint32_t i, uint32_t& k, uint32_t& h) {
+        if (fast) {
+            k = ckey[i];
+            h = cidx[i];
+        } else {
+            k = energy_key(gld(V + i));
+            h = (sg * i) & Bm;
+        }
+    };
+    const uint32_t total = fast ? n : (uint32_t)C::B;
+    uint32_t theta, rank;
+    stream_kth_largest<NT>(total, dK, [&](uint32_t i, uint32_t& k) { uint32_t h; entry(i, k, h); return true; }, hist,
+                           bc, theta, rank);
+    // entries equal to theta: take the `rank` of lowest bucket
+    uint32_t eq = 0;
+    for (uint32_t i = threadIdx.x; i < total; i += NT) {
+        uint32_t k, h;
+        entry(i, k, h);
+        eq += k == theta;
+    }
+    if (eq) atomicAdd(&s_eq, eq);
+    __syncthreads();
+    uint32_t hcut = (uint32_t)C::B;   // ties with bucket < hcut are selected
+    if (s_eq > rank) {
+        uint32_t th, rk;
+        stream_kth_largest<NT>(total, rank, [&](uint32_t i, uint32_t& k) {
+            uint32_t e, h;
+            entry(i, e, h);
+            k = Bm - h;
+            return e == theta;
+        }, hist, bc, th, rk);
+        hcut = (uint32_t)C::B - th;
+    }
+    for (uint32_t i = threadIdx.x; i < total; i += NT) {
+        uint32_t k, h;
+        entry(i, k, h);
+        if (k > theta || (k == theta && h < hcut)) atomicOr(&bits[h >> 5], 1u << (h & 31u));
+    }
+    __syncthreads();
+    // bitmap out; buckets in ascending order into jlist
+    constexpr int WPT = NW / NT;
+    static_assert(WPT >= 1 && NW % NT == 0, "bitmap words per thread");
+    uint32_t* jb = d.jbits + (size_t)r * NW;
+    uint32_t* jl = d.jlist + (size_t)r * dK;
+    uint32_t wv[WPT], cnt = 0;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+        wv[q] = bits[threadIdx.x * WPT + q];
+        cnt += (uint32_t)__popc(wv[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) gst(jb + threadIdx.x * WPT + q, wv[q]);
+    uint32_t tot;
+    uint32_t pos = block_excl_scan<NT>(cnt, scan, tot);
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+        uint32_t w = wv[q];
+        while (w) {
+            const uint32_t b = (uint32_t)__ffs((int)w) - 1u;
+            w &= w - 1u;
+            if (pos < dK) gst(jl + pos, (threadIdx.x * WPT + q) * 32u + b);
+            ++pos;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int LOG2B>
+static hipError_t launch_fft_t(const Launch& a, uint32_t units, hipStream_t s) {
+    using Cfg = FftCfg<LOG2B>;
+    hipLaunchKernelGGL(fft_select_kernel<LOG2B>, dim3(units), dim3(Cfg::NT), Cfg::lds_bytes(), s, a);
+    return hipGetLastError();
+}
+
+template <int LOG2B>
+static hipError_t set_fft_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_select_kernel<LOG2B>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)FftCfg<LOG2B>::lds_bytes());
+}
+
+template <int LB>
+constexpr size_t large_lds(uint32_t pass) {
+    using C = LargeCfg<LB>;
+    return pass == 0   ? SeqFft<C::LB1, 16, C::NT>::lds_bytes()
+           : pass == 1 ? SeqFft<C::LB2, 16, C::NT>::lds_bytes()
+                       : (size_t)(C::NW + 2 * C::SELCAP) * sizeof(uint32_t);
+}
+
+template <int LB>
+hipError_t set_large_attr() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_large_p1_kernel<LB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds<LB>(0));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_large_p2_kernel<LB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds<LB>(1));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&select_large_kernel<LB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds<LB>(2));
+    return e;
+}
+
+template <int LB>
+hipError_t launch_large_t(const Launch& a, uint32_t pass, uint32_t units, hipStream_t s) {
+    switch (pass) {
+        case 0: hipLaunchKernelGGL(fft_large_p1_kernel<LB>, dim3(units), dim3(256), large_lds<LB>(0), s, a); break;
+        case 1: hipLaunchKernelGGL(fft_large_p2_kernel<LB>, dim3(units), dim3(256), large_lds<LB>(1), s, a); break;
+        case 2: hipLaunchKernelGGL(select_large_kernel<LB>, dim3(units), dim3(1024), large_lds<LB>(2), s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint32_t units, hipStream_t s) {
+    switch (log2B) {
+        case 15: return launch_large_t<15>(a, pass, units, s);
+        case 16: return launch_large_t<16>(a, pass, units, s);
+        case 17: return launch_large_t<17>(a, pass, units, s);
+        case 18: return launch_large_t<18>(a, pass, units, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_fft_attributes() {
+    hipError_t e;
+    if ((e = set_large_attr<15>()) != hipSuccess) return e;
+    if ((e = set_large_attr<16>()) != hipSuccess) return e;
+    if ((e = set_large_attr<17>()) != hipSuccess) return e;
+    if ((e = set_large_attr<18>()) != hipSuccess) return e;
+    if ((e = set_fft_attr<13>()) != hipSuccess) return e;
+    if ((e = set_fft_attr<14>()) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t set_kernel_attributes_impl() {
+    hipError_t e = set_fft_attributes();
+    if (e == hipSuccess) e = set_fold_attributes();
+    return e;
+}
+
+hipError_t launch_fft_select(const Launch& a, uint32_t log2B, uint32_t units, hipStream_t s) {
+    switch (log2B) {
+        case 1: return launch_fft_t<1>(a, units, s);
+        case 2: return launch_fft_t<2>(a, units, s);
+        case 3: return launch_fft_t<3>(a, units, s);
+        case 4: return launch_fft_t<4>(a, units, s);
+        case 5: return launch_fft_t<5>(a, units, s);
+        case 6: return launch_fft_t<6>(a, units, s);
+        case 7: return launch_fft_t<7>(a, units, s);
+        case 8: return launch_fft_t<8>(a, units, s);
+        case 9: return launch_fft_t<9>(a, units, s);
+        case 10: return launch_fft_t<10>(a, units, s);
+        case 11: return launch_fft_t<11>(a, units, s);
+        case 12: return launch_fft_t<12>(a, units, s);
+        case 13: return launch_fft_t<13>(a, units, s);
+        case 14: return launch_fft_t<14>(a, units, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sfft

@@ -1,4 +1,4 @@
-// Launchers of the gfx950 kernels (defined in kernels.hip).
+// Launchers of the gfx950 kernels (defined in fold.hip, fft.hip and estimate.hip).
 #pragma once
 
 #include "common.hpp"
@@ -25,5 +25,7 @@ hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint3
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // raises the dynamic-LDS limit of the kernels that use more than 64 KB
 hipError_t set_kernel_attributes_impl();
+hipError_t set_fold_attributes();
+hipError_t set_fft_attributes();
 
 }  // namespace sfft
