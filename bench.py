@@ -29,14 +29,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-N, K, B, L, W, SNR_DB = 1 << 22, 100, 16384, 9, 131072, 20.0
+N, K, B, L, SNR_DB = 1 << 22, 100, 16384, 9, 20.0
 PLAN_SEED = 1
 HBM_PEAK_GBPS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_strip_pf_kernel_n22_k100_b64_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_08238_amd", "csrc", "fold.hip")   # the bucketization kernels
 
 
-def alg_bytes_per_signal() -> float:
+def alg_bytes_per_signal(W: int) -> float:
     return 8.0 * N * (1.0 - (1.0 - W / N) ** L)
 
 
@@ -77,7 +77,9 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     M = len(xs)
     srv = S.Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_inflight=args.serve_inflight,
                    n_streams=args.serve_streams)
-    h = srv.prepare(S.PlanParams(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols))
+    fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
+    h = srv.prepare(S.PlanParams(N, K, B, L, args.w_over_b * B, seed=PLAN_SEED, strip_cols=args.strip_cols,
+                                 flags=fflags))
     n = max(1, int(args.serve_rate * args.serve_seconds))
     nb = args.serve_burst
     idx = torch.empty((max(n, nb), K), dtype=torch.int64, device=dev)
@@ -209,7 +211,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
     from paper_2012_08238_amd import autotune as A
     from paper_2012_08238_amd.signals import derive_seed, make_signal_torch, uneven_batch_specs
     specs = uneven_batch_specs(args.uneven, seed=4)
-    table = A.Table(args.tune_table) if args.tune_table else None
+    table = A.Table(args.tune_table) if args.tune_table and os.path.exists(args.tune_table) else None
     t0 = time.perf_counter()
     plans, xs, truth = [], [], []
     for i, (n, k, snr) in enumerate(specs):
@@ -262,6 +264,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strip-cols", type=int, default=0, help="bucketization tile width (0 = plan default)")
+    ap.add_argument("--w-over-b", type=int, default=8, help="window length w as a multiple of B")
+    ap.add_argument("--fold", choices=["auto", "strip", "gather"], default="auto", help="bucketization form")
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
     ap.add_argument("--single-passes", type=int, default=3, help="passes over the batch through sfft_execute alone")
     ap.add_argument("--branches", type=int, default=4, help="parallel stream branches of the batch graph")
@@ -275,7 +279,8 @@ def main() -> int:
     ap.add_argument("--mix-budget-gib", type=int, default=16)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
-    ap.add_argument("--tune-table", default="", help="autotuner JSON table for the uneven batch (tunes missing classes)")
+    ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
+                    help="autotuner JSON table for the uneven batch ('' = the untuned rule; missing classes are tuned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -297,8 +302,10 @@ def main() -> int:
         x, f, tones = make_signal_torch(N, K, SNR_DB, derive_seed(0, i), dev)
         xs.append(x)
         truth.append((f, tones))
+    W = args.w_over_b * B
+    fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
     plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols,
-                  flags=S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0)
+                  flags=fflags | (S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0))
     desc = plan.desc
     batch = S.Batch([plan] * M, branches=args.branches)
     idx = torch.empty((M, K), dtype=torch.int64, device=dev)
@@ -384,7 +391,7 @@ def main() -> int:
         uneven = uneven_measure(S, torch, dev, args)
         print(f"# uneven batch {uneven['signals_per_s']:.0f} signals/s", file=sys.stderr, flush=True)
 
-    alg = alg_bytes_per_signal() * M
+    alg = alg_bytes_per_signal(W) * M
     achieved = alg / fold_avg_s / 1e9
     traffic = committed_traffic(M)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -429,7 +436,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sFFT N=2^22 K=100 SNR20dB B=16384 L=9 w=131072, batch of resident signals",
+        "config": {"workload": f"sFFT N=2^22 K=100 SNR20dB B=16384 L=9 w={W}, batch of resident signals",
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
                    "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "parallelism": "single-gpu"},

@@ -7,8 +7,9 @@ reference SNR:
 
 * accuracy: the recall of the planted supports, averaged over the probes; the
   configurations within ``tol`` of the best recall are kept;
-* speed: device time of one batched execution of the probes (graph replay,
-  median of a few), the fastest kept configuration wins;
+* speed: device time of one batched execution of the probes, repeated to
+  about 256 MB of signal (graph replay, median of a few), the fastest kept
+  configuration wins;
 * bucketization tile: for the winner, the gather form and strip widths around
   the default are timed. They never change results (every form sums the same
   taps in the same order), so only time decides.
@@ -70,8 +71,12 @@ def params_from(entry: dict, N: int, K: int, seed: int = 0) -> PlanParams:
                       flags=entry["flags"])
 
 
-def _time_batch(plan, xs, outs, reps: int) -> float:
+def _time_batch(plan, xs, outs, reps: int, fill: int = 1) -> float:
+    """Median device time of one batched execution of the probes, each repeated
+    `fill` times (so that small signals still fill the device as in a real batch)."""
     import torch
+    xs = list(xs) * fill
+    outs = [plan.outputs(xs[0].device) for _ in xs]
     b = Batch([plan] * len(xs))
     idx = [o[0] for o in outs]
     val = [o[1] for o in outs]
@@ -98,6 +103,8 @@ def tune_class(N: int, K: int, device, L: int = 9, snr_db: float = 10.0, probes:
     Kc = min(class_k(K), N // 16)
     sigs = [make_signal_torch(N, Kc, snr_db, derive_seed(seed, i), device) for i in range(probes)]
     xs = [s[0] for s in sigs]
+    # time batches of about 256 MB of signal (at most 64 signals), as in a full batch
+    fill = max(1, min(64, (1 << 28) // (8 * N)) // probes)
     trials = []
     for B in b_candidates(N, Kc):
         for wB in (4, 8):
@@ -112,7 +119,7 @@ def tune_class(N: int, K: int, device, L: int = 9, snr_db: float = 10.0, probes:
                 got = set(o[0].cpu().numpy().tolist())
                 recall += len(got & set(f.tolist())) / len(f)
             recall /= len(xs)
-            ms = _time_batch(p, xs, outs, reps)
+            ms = _time_batch(p, xs, outs, reps, fill)
             trials.append(dict(B=B, wB=wB, recall=recall, ms=ms, plan=p))
     if not trials:
         raise ValueError(f"no configuration fits N={N}, K={K}")
@@ -137,12 +144,11 @@ def tune_class(N: int, K: int, device, L: int = 9, snr_db: float = 10.0, probes:
             p = Plan(N, Kc, B, L, wB * B, seed=seed, n_resid=0, flags=1 | flags, strip_cols=c)
         except Exception:
             continue
-        outs = [p.outputs(device) for _ in xs]
-        forms.append((flags, c, _time_batch(p, xs, outs, reps)))
+        forms.append((flags, c, _time_batch(p, xs, None, reps, fill)))
         p.close()
     flags, c, ms = min(forms, key=lambda f: f[2])
     return dict(B=B, wB=wB, L=L, strip_cols=c, flags=flags, ms=ms, recall=win["recall"], tuned_at_k=Kc,
-                snr_db=snr_db, probes=probes)
+                snr_db=snr_db, probes=probes, timed_signals=probes * fill)
 
 
 class Table:
@@ -172,3 +178,34 @@ class Table:
             with open(tmp, "w") as f:
                 json.dump(self.entries, f, indent=1, sort_keys=True)
             os.replace(tmp, self.path)
+
+
+def main(argv=None) -> int:
+    """Tune the size classes of a workload recipe into a JSON table."""
+    import argparse
+
+    import torch
+
+    from .signals import uneven_batch_specs
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--log2n", default="16,22", help="range of log2 N (inclusive)")
+    ap.add_argument("--k", default="10,500", help="range of K (inclusive)")
+    ap.add_argument("--snr", type=float, default=10.0)
+    ap.add_argument("--probes", type=int, default=4)
+    a = ap.parse_args(argv)
+    lo, hi = (int(v) for v in a.log2n.split(","))
+    klo, khi = (int(v) for v in a.k.split(","))
+    dev = torch.device("cuda:0")
+    t = Table(a.out)
+    specs = uneven_batch_specs(4096, seed=4, log2n=(lo, hi), k=(klo, khi))
+    keys = sorted({(n, class_k(k)) for n, k, _ in specs})
+    for n, k in keys:
+        e = t.get(n, k, dev, snr_db=a.snr, probes=a.probes)
+        print(f"{class_key(n, k)}: B={e['B']} w=B*{e['wB']} strip_cols={e['strip_cols']} flags={e['flags']} "
+              f"recall={e['recall']:.4f} {e['ms']:.3f} ms", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
