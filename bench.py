@@ -128,6 +128,43 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     }
 
 
+def snr_sweep(S, torch, dev, args) -> dict:
+    """L0/L1/L2 error against the best K-term approximation (the dense FP64
+    spectrum of each signal) versus SNR, median and mean of the loop estimates
+    (the robustness experiment): N=2^20, K=50, B=1024, L=7, w=8B, signals per point."""
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    n, k, b, l = 1 << 20, 50, 1024, 7
+    plans = {c: S.Plan(n, k, b, l, 8 * b, seed=11, flags=S.SFFT_FLAG_MEAN_ESTIMATE if c == "mean" else 0)
+             for c in ("median", "mean")}
+    out = {"N": n, "K": k, "B": b, "L": l, "w": 8 * b, "signals": args.sweep_signals, "points": []}
+    for snr in (-10.0, 0.0, 10.0, 20.0, 30.0, 40.0):
+        row = {"snr_db": snr}
+        errs = {c: [0.0, 0.0, 0.0] for c in plans}
+        for i in range(args.sweep_signals):
+            x, _, _ = make_signal_torch(n, k, snr, derive_seed(60 + int(snr), i), dev)
+            xh = torch.fft.fft(x.to(torch.complex128)) / n
+            mag = xh.abs()
+            best = torch.topk(mag, k).indices
+            for c, p in plans.items():
+                idx, val = p(x)
+                got = idx[idx >= 0]
+                est = torch.zeros(n, dtype=torch.complex128, device=dev)
+                est[got] = val[idx >= 0].to(torch.complex128)
+                ref = torch.zeros(n, dtype=torch.complex128, device=dev)
+                ref[best] = xh[best]
+                union = torch.unique(torch.cat([got, best]))
+                d = (est - ref)[union]
+                errs[c][0] += float(k - torch.isin(best, got).sum())
+                errs[c][1] += float(d.abs().sum()) / k
+                errs[c][2] += float((d.abs() ** 2).sum().sqrt())
+        for c in plans:
+            row[c] = {m: round(v / args.sweep_signals, 6) for m, v in zip(("L0", "L1", "L2"), errs[c])}
+        out["points"].append(row)
+    for p in plans.values():
+        p.close()
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -276,6 +313,7 @@ def main() -> int:
     ap.add_argument("--serve-inflight", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--mix-pool", type=int, default=64, help="pool of mixed-size served signals (0 = skip)")
+    ap.add_argument("--sweep-signals", type=int, default=8, help="signals per SNR point of the error sweep (0 = skip)")
     ap.add_argument("--mix-budget-gib", type=int, default=16)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
@@ -386,6 +424,7 @@ def main() -> int:
         serving_mix = serve_mix_measure(S, torch, dev, args)
         print(f"# mixed serving p50 {serving_mix['poisson']['p50_ms']} ms p99 {serving_mix['poisson']['p99_ms']} ms",
               file=sys.stderr, flush=True)
+    sweep = snr_sweep(S, torch, dev, args) if args.sweep_signals > 0 else None
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -451,6 +490,7 @@ def main() -> int:
         "serving": serving,
         "serving_mixed_sizes": serving_mix,
         "uneven_batch": uneven,
+        "error_vs_snr": sweep,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,

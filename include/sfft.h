@@ -65,6 +65,8 @@ typedef enum {
 #define SFFT_FLAG_FOLD_GATHER 0x2u  /* force the gather form of the bucketization */
 #define SFFT_FLAG_FOLD_STRIP  0x4u  /* force the streamed column-strip form */
 #define SFFT_FLAG_XCD_ORDER   0x8u  /* bucketization: give each XCD a contiguous range of column strips */
+#define SFFT_FLAG_MEAN_ESTIMATE 0x10u /* combine the L loop estimates by their mean (the averaging of the
+                                         energy-concentration method) instead of the coordinate-wise median */
 
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {

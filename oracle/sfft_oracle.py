@@ -263,6 +263,12 @@ def median_combine(e: np.ndarray) -> np.ndarray:
     return np.median(e.real, axis=0) + 1j * np.median(e.imag, axis=0)
 
 
+def mean_combine(e: np.ndarray) -> np.ndarray:
+    """Average of the estimates over bucketizations (the averaging the
+    energy-concentration method describes)."""
+    return e.mean(axis=0)
+
+
 def finalize(I, v, K: int):
     """K candidates of largest |v|^2 (ties -> lower frequency), ascending by
     frequency, padded with (-1, 0) when fewer than K candidates exist.
@@ -340,8 +346,9 @@ def check_params(N, K, B, L, w, d=2):
 
 def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
          T: int | None = None, c_g: float = C_G, sigma=None, tau=None,
-         n_resid: int = 4096, tpos=None) -> OracleResult:
-    """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout."""
+         n_resid: int = 4096, tpos=None, combine: str = "median") -> OracleResult:
+    """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout.
+    combine: "median" (coordinate-wise, default) or "mean" of the loop estimates."""
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     check_params(N, K, B, L, w, d)
@@ -365,7 +372,8 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     counts = vote_counts(J, sigma, N, B)
     I = np.nonzero(counts >= T)[0].astype(np.int64)
     e = loop_estimates(I, uhat, sigma, tau, G, N, B)
-    v = median_combine(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
+    comb = {"median": median_combine, "mean": mean_combine}[combine]
+    v = comb(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
     idx, val, fmargin = finalize(I, v, K)
     e_res, e_in = residual_energy(x, idx, val, tpos) if len(tpos) else (0.0, 0.0)
     trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,

@@ -18,6 +18,7 @@ SFFT_FLAG_NO_RESIDUAL = 0x1
 SFFT_FLAG_FOLD_GATHER = 0x2
 SFFT_FLAG_FOLD_STRIP = 0x4
 SFFT_FLAG_XCD_ORDER = 0x8
+SFFT_FLAG_MEAN_ESTIMATE = 0x10
 
 
 class Params(C.Structure):

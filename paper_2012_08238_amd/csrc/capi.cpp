@@ -90,6 +90,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.vote_upl = R.vote_upl;
     d.resid_blocks = R.resid_blocks;
     d.lmax = R.lmax;
+    d.combine = (R.flags & SFFT_FLAG_MEAN_ESTIMATE) ? 1u : 0u;
     return d;
 }
 

@@ -176,6 +176,7 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
     const uint32_t fftm = d.fft_mode;
+    const uint32_t mean = d.combine;
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
     const uint32_t rsh = d.log2N - d.tb;
     const double step = d.step;
@@ -228,8 +229,23 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
                 im[r] = e.y;
             }
         }
-        const float mr = median_of<LMAX>(re, L);
-        const float mi = median_of<LMAX>(im, L);
+        float mr, mi;
+        if (mean) {
+            // the average of the loop estimates, summed in loop order
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int r = 0; r < LMAX; ++r) {
+                if ((uint32_t)r < L) {
+                    sr += re[r];
+                    si += im[r];
+                }
+            }
+            mr = sr / (float)L;
+            mi = si / (float)L;
+        } else {
+            mr = median_of<LMAX>(re, L);
+            mi = median_of<LMAX>(im, L);
+        }
         const float mag = fmaf(mr, mr, mi * mi);
         gst(est + i, make_float2(mr, mi));
         gst(keys + i, ((uint64_t)(0xFFFFFFFFu - __float_as_uint(mag)) << 32) | (uint64_t)f);

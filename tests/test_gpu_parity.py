@@ -34,10 +34,10 @@ def _run(dev, x64, **plan_kw):
     return out
 
 
-def _oracle(x64, K, B, L, w, seed, d=2, vote_threshold=0, n_resid=4096):
+def _oracle(x64, K, B, L, w, seed, d=2, vote_threshold=0, n_resid=4096, combine="median"):
     T = vote_threshold or None
     return O.sfft(x64.astype(np.complex64).astype(np.complex128), K, B, L, w, seed=seed, d=d, T=T,
-                  n_resid=n_resid)
+                  n_resid=n_resid, combine=combine)
 
 
 def compare(g, r, K, B, L, w, seed, check_values=True):
@@ -246,3 +246,27 @@ def test_c3_other_k(dev, K, B):
     g = _run(dev, sig.x, K=K, B=B, L=9, w=8 * B, seed=2)
     r = _oracle(sig.x, K, B, 9, 8 * B, 2)
     compare(g, r, K, B, 9, 8 * B, 2)
+
+
+# ------------------------------------------------------------------ estimator variants
+@pytest.mark.parametrize("cfg", [
+    dict(N=1 << 16, K=20, B=512, L=7, w=4096, seed=21, d=1),
+    dict(N=1 << 16, K=20, B=512, L=7, w=4096, seed=22, d=3),
+    dict(N=1 << 18, K=16, B=1024, L=9, w=8192, seed=23, d=4),
+    dict(N=1 << 16, K=20, B=512, L=7, w=4096, seed=24, mean=True),
+    dict(N=1 << 20, K=50, B=1024, L=8, w=8192, seed=25, mean=True),
+    dict(N=1 << 14, K=10, B=128, L=5, w=512, seed=26, mean=True, d=3),
+])
+def test_estimator_variants(dev, cfg):
+    """d != 2 buckets per loop, and the mean of the loop estimates in place of the median."""
+    import paper_2012_08238_amd as S
+    cfg = dict(cfg)
+    N = cfg.pop("N")
+    mean = cfg.pop("mean", False)
+    d = cfg.get("d", 2)
+    sig = make_signal(N, cfg["K"], 20.0, seed=cfg["seed"] + 70)
+    g = _run(dev, sig.x, flags=S.SFFT_FLAG_MEAN_ESTIMATE if mean else 0, **cfg)
+    r = _oracle(sig.x, cfg["K"], cfg["B"], cfg["L"], cfg["w"], cfg["seed"], d=d,
+                combine="mean" if mean else "median")
+    compare(g, r, cfg["K"], cfg["B"], cfg["L"], cfg["w"], cfg["seed"])
+    check_residual(g, sig.x, r.trace["tpos"])

@@ -262,6 +262,20 @@ def check_median():
             assert m[k].imag == statistics.median(e[:, k].imag.tolist())
 
 
+def check_mean():
+    rng = np.random.default_rng(12)
+    for L in (1, 3, 8):
+        e = rng.standard_normal((L, 5)) + 1j * rng.standard_normal((L, 5))
+        m = O.mean_combine(e)
+        for k in range(5):
+            assert abs(m[k].real - statistics.fmean(e[:, k].real.tolist())) < 1e-15
+            assert abs(m[k].imag - statistics.fmean(e[:, k].imag.tolist())) < 1e-15
+    # one noiseless tone: every loop's estimate is the tone, so is their mean
+    sig = make_signal(1 << 12, 1, None, seed=7)
+    r = O.sfft(sig.x, 1, 64, 5, 512, seed=1, combine="mean")
+    assert list(r.idx) == list(sig.freqs) and abs(r.val[0] - sig.tones[0]) < 1e-12
+
+
 def check_finalize():
     rng = np.random.default_rng(10)
     I = rng.choice(1000, 40, replace=False)
