@@ -73,6 +73,14 @@ def draw_permutations(N: int, L: int, seed: int, n_resid: int = 0):
     return sigma, tau, tpos
 
 
+def draw_comb_shifts(N: int, L: int, seed: int, n_resid: int, n_comb: int) -> np.ndarray:
+    """Time shifts of the comb (spike-train) prefilter loops: the next ``n_comb``
+    outputs of the same SplitMix64 stream, after the 2L permutation draws and
+    the residual positions."""
+    draws = splitmix64(seed, 2 * L + n_resid + n_comb)
+    return np.array([draws[2 * L + n_resid + c] & (N - 1) for c in range(n_comb)], dtype=np.int64)
+
+
 def modinv(sigma: int, N: int) -> int:
     """sigma^{-1} mod N (sigma odd, N a power of two)."""
     return pow(int(sigma), -1, int(N))
@@ -223,6 +231,33 @@ def select_buckets(uhat: np.ndarray, dK: int):
 
 
 # ---------------------------------------------------------------------------
+# Spike-train (comb) bucketization: the sFFT2.0 prefilter (Table 1, spike train
+# + flat filters). Eq.(15) reads garbled: its example (N=2048, B=128, buckets =
+# residues mod 128) needs the spikes every N/B samples, i.e. B samples at stride
+# N/B; with that reading Eq.(16) holds exactly.
+# ---------------------------------------------------------------------------
+def comb_buckets(x: np.ndarray, Bc: int, tau: int) -> np.ndarray:
+    """Bc-point DFT of the Bc samples x[tau + j N/Bc]: bucket i holds
+    Bc * sum over f = i (mod Bc) of xhat_f e^{+2 pi i tau f / N} (Eq.(16))."""
+    N = x.shape[0]
+    j = np.arange(Bc, dtype=np.int64)
+    return np.fft.fft(x[(tau + j * (N // Bc)) % N])
+
+
+def comb_mask(x: np.ndarray, Bc: int, taus, keep: int):
+    """Residues mod Bc that may hold large coefficients: the union over the comb
+    shifts of the ``keep`` largest |comb bucket|^2 (ties -> lower residue).
+    Returns the mask and the selection margin of each shift."""
+    mask = np.zeros(Bc, dtype=bool)
+    margins = []
+    for t in taus:
+        J, m = select_buckets(comb_buckets(x, Bc, int(t)), keep)
+        mask[J] = True
+        margins.append(m)
+    return mask, margins
+
+
+# ---------------------------------------------------------------------------
 # Stage 2a: location by probability and statistics (voting).
 # ---------------------------------------------------------------------------
 def vote_counts(J_list, sigma, N: int, B: int) -> np.ndarray:
@@ -346,9 +381,13 @@ def check_params(N, K, B, L, w, d=2):
 
 def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
          T: int | None = None, c_g: float = C_G, sigma=None, tau=None,
-         n_resid: int = 4096, tpos=None, combine: str = "median") -> OracleResult:
+         n_resid: int = 4096, tpos=None, combine: str = "median",
+         comb_b: int = 0, comb_loops: int = 0, comb_keep: int = 0) -> OracleResult:
     """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout.
-    combine: "median" (coordinate-wise, default) or "mean" of the loop estimates."""
+    combine: "median" (coordinate-wise, default) or "mean" of the loop estimates.
+    comb_loops > 0 adds the comb prefilter: a frequency is a candidate only if
+    its residue mod comb_b is among the comb_keep (default d*K) largest comb
+    buckets of some comb shift."""
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     check_params(N, K, B, L, w, d)
@@ -370,7 +409,13 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     sel = [select_buckets(u, d * K) for u in uhat]
     J = [s[0] for s in sel]
     counts = vote_counts(J, sigma, N, B)
-    I = np.nonzero(counts >= T)[0].astype(np.int64)
+    voted = counts >= T
+    cmask, cmargins, ctaus = None, [], np.zeros(0, dtype=np.int64)
+    if comb_loops:
+        ctaus = draw_comb_shifts(N, L, seed, n_resid, comb_loops)
+        cmask, cmargins = comb_mask(x, comb_b, ctaus, comb_keep or d * K)
+        voted &= cmask[np.arange(N, dtype=np.int64) % comb_b]
+    I = np.nonzero(voted)[0].astype(np.int64)
     e = loop_estimates(I, uhat, sigma, tau, G, N, B)
     comb = {"median": median_combine, "mean": mean_combine}[combine]
     v = comb(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
@@ -378,7 +423,8 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     e_res, e_in = residual_energy(x, idx, val, tpos) if len(tpos) else (0.0, 0.0)
     trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,
                  J=J, select_margin=[s[1] for s in sel], counts=counts, I=I,
-                 e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos))
+                 e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos),
+                 comb_mask=cmask, comb_margin=cmargins, comb_tau=ctaus)
     return OracleResult(idx=idx, val=val, e_res=e_res, e_in=e_in, trace=trace)
 
 

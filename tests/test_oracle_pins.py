@@ -276,6 +276,43 @@ def check_mean():
     assert list(r.idx) == list(sig.freqs) and abs(r.val[0] - sig.tones[0]) < 1e-12
 
 
+def check_comb_buckets():
+    # Eq.(16) against the library FFT of the whole signal: bucket i collects the
+    # coefficients at f = i (mod Bc), each with the shift phase e^{+2 pi i tau f/N}
+    rng = np.random.default_rng(13)
+    N = 1 << 10
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    xh = np.fft.fft(x) / N
+    f = np.arange(N)
+    for Bc, tau in ((16, 0), (64, 5), (128, 1000)):
+        got = O.comb_buckets(x, Bc, tau)
+        want = np.array([Bc * np.sum(xh[f % Bc == i] * np.exp(2j * np.pi * ((tau * f[f % Bc == i]) % N) / N))
+                         for i in range(Bc)])
+        assert np.max(np.abs(got - want)) < 1e-9 * np.max(np.abs(want))
+    # the printed spike-train example: 64, 304, 610, 1660 fall in buckets 64, 48, 98, 124 of B=128
+    ex = GOLD["spike_train_example"]
+    sig = make_signal(ex["N"], 4, None, freqs=ex["freqs"], tones=ex["values"])
+    mask, _ = O.comb_mask(sig.x, ex["B"], [0, 17], 4)
+    assert sorted(np.nonzero(mask)[0].tolist()) == sorted(ex["buckets"])
+    # and in the aliasing example 98 and 610 share residue 98 mod 128
+    al = GOLD["aliasing_example"]
+    assert 98 % 128 == 610 % 128 and al["freqs"][1] % 128 == al["freqs"][2] % 128
+
+
+def check_comb_keeps_support():
+    # exactly sparse with distinct residues: the prefilter keeps every true residue,
+    # and the filtered run returns the same support as the unfiltered one
+    for s in range(3):
+        sig = make_signal(1 << 14, 10, None, seed=300 + s)
+        if len(set((sig.freqs % 256).tolist())) < 10:
+            continue
+        a = O.sfft(sig.x, 10, 128, 9, 1024, seed=s, n_resid=0)
+        b = O.sfft(sig.x, 10, 128, 9, 1024, seed=s, n_resid=0, comb_b=256, comb_loops=2)
+        assert np.all(b.trace["comb_mask"][sig.freqs % 256])
+        assert list(a.idx) == list(b.idx) == list(sig.freqs)
+        assert set(b.trace["I"].tolist()) <= set(a.trace["I"].tolist())
+
+
 def check_finalize():
     rng = np.random.default_rng(10)
     I = rng.choice(1000, 40, replace=False)
