@@ -84,6 +84,15 @@ typedef struct {
     int32_t strip_cols;     /* tile width of the strip bucketization (power of two); 0 = automatic */
     const uint32_t* sigma;  /* optional host uint32[L]: explicit odd scalings (NULL = draw from seed) */
     const uint32_t* tau;    /* optional host uint32[L]: explicit shifts; required iff sigma is given */
+    /* Comb prefilter (the spike-train bucketization of the sFFT2.0 row, Eq.(15)-(16)):
+     * comb_loops in [0, 8] (0 = off) shifts tau_c drawn after the residual samples,
+     * each taking the comb_b samples x[tau_c + j N/comb_b]; the comb_keep (0 = d*K)
+     * largest of their comb_b-point DFT mark residues mod comb_b, and only
+     * frequencies whose residue is marked by some shift can be located.
+     * comb_b: power of two in [2, min(N/2, 16384)]; comb_keep <= comb_b. */
+    int32_t comb_b;
+    int32_t comb_loops;
+    int32_t comb_keep;
 } sfft_params;
 
 /* Resolved plan description (what the plan actually runs). */
@@ -106,6 +115,7 @@ typedef struct {
     uint32_t* jlist;        /* uint32[L*d*K]: selected buckets per loop, ascending */
     uint32_t* cand;         /* uint32[cand_cap]: frequencies with >= T votes, unordered */
     int64_t cand_count;     /* out: number of valid entries written to cand */
+    uint32_t* cbits;        /* uint32[comb_loops * max(1, comb_b/32)]: residues kept per comb loop */
 } sfft_trace;
 
 /* ---- parameters and plans --------------------------------------------------------- */

@@ -37,6 +37,9 @@ class PlanParams:
     strip_cols: int = 0
     sigma: np.ndarray | None = None
     tau: np.ndarray | None = None
+    comb_b: int = 0
+    comb_loops: int = 0
+    comb_keep: int = 0
 
     def to_c(self):
         """Return (Params struct, keep-alive list)."""
@@ -50,6 +53,9 @@ class PlanParams:
         p.gauss_c = self.gauss_c
         p.flags = self.flags
         p.strip_cols = self.strip_cols
+        p.comb_b = self.comb_b
+        p.comb_loops = self.comb_loops
+        p.comb_keep = self.comb_keep
         keep = []
         if self.sigma is not None:
             s = np.ascontiguousarray(self.sigma, dtype=np.uint32)
@@ -105,7 +111,7 @@ class Plan:
     @classmethod
     def from_params(cls, params: PlanParams) -> "Plan":
         kw = {k: getattr(params, k) for k in ("seed", "d", "vote_threshold", "n_resid", "gauss_c", "flags",
-                                               "strip_cols", "sigma", "tau")}
+                                               "strip_cols", "sigma", "tau", "comb_b", "comb_loops", "comb_keep")}
         return cls(params.N, params.K, params.B, params.L, params.w, **kw)
 
     @property
@@ -154,12 +160,20 @@ class Plan:
         jb = np.zeros(L * wpl, np.uint32)
         jl = np.zeros(L * dK, np.uint32)
         cd = np.zeros(max(cap, 1), np.uint32)
+        nc, cb = self.params.comb_loops, self.params.comb_b
+        cw = max(1, cb // 32) if nc else 1
+        cbits = np.zeros(max(nc, 1) * cw, np.uint32)
         t = _capi.Trace(uh.ctypes.data_as(C.POINTER(C.c_float)), jb.ctypes.data_as(C.POINTER(C.c_uint32)),
-                        jl.ctypes.data_as(C.POINTER(C.c_uint32)), cd.ctypes.data_as(C.POINTER(C.c_uint32)), 0)
+                        jl.ctypes.data_as(C.POINTER(C.c_uint32)), cd.ctypes.data_as(C.POINTER(C.c_uint32)), 0,
+                        cbits.ctypes.data_as(C.POINTER(C.c_uint32)))
         check(load().sfft_plan_read_trace(self._h, C.byref(t)), "sfft_plan_read_trace")
         uhat = (uh[0::2] + 1j * uh[1::2]).reshape(L, B)
-        return dict(uhat=uhat, jbits=jb.reshape(L, wpl), jlist=jl.reshape(L, dK),
-                    cand=cd[:t.cand_count].copy())
+        out = dict(uhat=uhat, jbits=jb.reshape(L, wpl), jlist=jl.reshape(L, dK), cand=cd[:t.cand_count].copy())
+        if nc:
+            rows = cbits.reshape(nc, cw)
+            out["comb_rows"] = np.array([[(rows[c, i >> 5] >> (i & 31)) & 1 for i in range(cb)] for c in range(nc)],
+                                        dtype=bool)
+        return out
 
     def close(self) -> None:
         if getattr(self, "_h", None):

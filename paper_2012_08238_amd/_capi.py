@@ -26,7 +26,8 @@ class Params(C.Structure):
                 ("d", C.c_int32), ("w", C.c_int64), ("seed", C.c_uint64),
                 ("vote_threshold", C.c_int32), ("n_resid", C.c_int32), ("gauss_c", C.c_double),
                 ("flags", C.c_uint32), ("strip_cols", C.c_int32),
-                ("sigma", C.POINTER(C.c_uint32)), ("tau", C.POINTER(C.c_uint32))]
+                ("sigma", C.POINTER(C.c_uint32)), ("tau", C.POINTER(C.c_uint32)),
+                ("comb_b", C.c_int32), ("comb_loops", C.c_int32), ("comb_keep", C.c_int32)]
 
 
 class PlanDesc(C.Structure):
@@ -40,7 +41,7 @@ class PlanDesc(C.Structure):
 class Trace(C.Structure):
     _fields_ = [("uhat", C.POINTER(C.c_float)), ("jbits", C.POINTER(C.c_uint32)),
                 ("jlist", C.POINTER(C.c_uint32)), ("cand", C.POINTER(C.c_uint32)),
-                ("cand_count", C.c_int64)]
+                ("cand_count", C.c_int64), ("cbits", C.POINTER(C.c_uint32))]
 
 
 class ServerStats(C.Structure):

@@ -52,6 +52,8 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.tw = reinterpret_cast<const float2*>(tab + t.tw);
     d.tpos = reinterpret_cast<const uint32_t*>(tab + t.tpos);
     d.rou = reinterpret_cast<const double2*>(tab + t.rou);
+    d.comb_tau = reinterpret_cast<const uint32_t*>(tab + t.ctau);
+    d.ctw = reinterpret_cast<const float2*>(tab + t.ctw);
     d.tb = R.tb;
     d.step = 6.283185307179586476925286766559 / (double)R.N;
     d.uhat = reinterpret_cast<float2*>(ws + w.uhat);
@@ -65,6 +67,10 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.ctr = reinterpret_cast<uint32_t*>(ws + w.ctr);
     d.ubuf = reinterpret_cast<float2*>(ws + w.ubuf);
     d.gmax = reinterpret_cast<uint32_t*>(ws + w.gmax);
+    d.cbits = reinterpret_cast<uint32_t*>(ws + w.cbits);
+    d.comb_loops = R.comb_loops;
+    d.comb_log2b = R.comb_log2b;
+    d.comb_keep = R.comb_keep;
     d.fft_mode = R.fft_mode;
     d.N = R.N;
     d.maskN = R.N - 1;
@@ -112,6 +118,7 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     } else {
         HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
     }
+    if (R.comb_loops) HIP_TRY(launch_comb(a, R.comb_log2b, R.comb_loops, s), "comb prefilter launch");
     HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, s), "vote launch");
     HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, s), "estimate launch");
     if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
@@ -368,6 +375,9 @@ sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t) {
     }
     if (t->jbits) HIP_TRY(hipMemcpy(t->jbits, p->d_ws + w.jbits, (size_t)R.L * wpl * 4, hipMemcpyDeviceToHost), "copy jbits");
     if (t->jlist) HIP_TRY(hipMemcpy(t->jlist, p->d_ws + w.jlist, (size_t)R.L * R.dK * 4, hipMemcpyDeviceToHost), "copy jlist");
+    if (t->cbits && R.comb_loops)
+        HIP_TRY(hipMemcpy(t->cbits, p->d_ws + w.cbits, (size_t)R.comb_loops * R.comb_words * 4, hipMemcpyDeviceToHost),
+                "copy comb bitmaps");
     uint32_t ctr[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpy(ctr, p->d_ws + w.ctr, 16, hipMemcpyDeviceToHost), "copy counters");
     const uint32_t n = std::min(ctr[0], R.cap);

@@ -11,6 +11,8 @@ constexpr int kMaxK = 4096;      // outputs supported (final sort in LDS)
 constexpr int kMaxFftLds = 16384;  // largest B transformed inside one workgroup's LDS
 constexpr int kMaxB = 1 << 18;     // larger B: two-pass (four-step) FFT through the workspace
 constexpr int kRouMax = 256;       // entries of the FP64 root-of-unity table
+constexpr int kMaxCombLoops = 8;   // comb prefilter loops
+constexpr int kMaxCombB = 16384;   // comb size (one workgroup's LDS FFT)
 
 // Per-signal execution descriptor: plan tables (read only, shared by every
 // execution of a plan) plus one workspace. Lives in device memory; kernels
@@ -25,6 +27,8 @@ struct SigDesc {
     const float2* tw;           // [B] e^{-2 pi i m/B}
     const uint32_t* tpos;       // [S] residual sample positions
     const double2* rou;         // [2^tb] e^{2 pi i j / 2^tb}, FP64
+    const uint32_t* comb_tau;   // [comb_loops] time shifts of the comb prefilter
+    const float2* ctw;          // [Bc] e^{-2 pi i m/Bc}
     // workspace
     float2* uhat;               // [L][B] bucket values in column order (bucket of column col is
                                 // sigma^{-1}(col - tau) mod B), then their B-point DFT in bucket order
@@ -37,6 +41,7 @@ struct SigDesc {
     double* resid_own;          // [2] residual when the caller gives no buffer
     uint32_t* ctr;              // [4] counters: 0 candidates, 1 residual blocks done
     float2* ubuf;               // [L][B] two-pass FFT intermediate (B > kMaxFftLds only)
+    uint32_t* cbits;            // [comb_loops][max(1, Bc/32)] residues kept by each comb loop
     uint32_t* gmax;             // [L][B/16] largest energy of each 16 consecutive DFT outputs (idem)
     // sizes
     uint32_t N, maskN, log2N;
@@ -55,6 +60,9 @@ struct SigDesc {
     uint32_t resid_blocks;      // residual workgroups
     uint32_t lmax;              // power of two >= L used by the median network
     uint32_t combine;           // 0: coordinate-wise median over the loops, 1: mean
+    uint32_t comb_loops;        // comb prefilter loops (0 = off)
+    uint32_t comb_log2b;        // log2 Bc
+    uint32_t comb_keep;         // residues kept per comb loop
 };
 
 // Per-signal caller buffers of one execution.

@@ -15,6 +15,7 @@ template <int LMAX>
 __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged) {
     extern __shared__ uint32_t sbits[];
     __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
+    __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
@@ -36,6 +37,15 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     uint32_t sg[LMAX];   // sigma_r, uniform: scalar loads
 #pragma unroll
     for (int r = 0; r < LMAX; ++r) sg[r] = (uint32_t)r < L ? ((CU32)d.sigma)[r] : 0u;
+    const uint32_t ncomb = d.comb_loops, cmask = (1u << d.comb_log2b) - 1u;
+    if (ncomb) {
+        const uint32_t cw = max(1u, (cmask + 1u) >> 5);
+        for (uint32_t i = threadIdx.x; i < cw; i += kVoteNT) {
+            uint32_t v = 0;
+            for (uint32_t c = 0; c < ncomb; ++c) v |= gld(d.cbits + c * cw + i);
+            s_comb[i] = v;
+        }
+    }
     const uint32_t* bits = jbits;
     if (staged) {
         // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte units)
@@ -81,6 +91,10 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
             }
             // counted once: from the first loop that voted for f
             emit = (votes & ((1u << r0) - 1u)) == 0u && (uint32_t)__popc(votes) >= T;
+            if (ncomb) {
+                const uint32_t res = f & cmask;
+                emit = emit && ((s_comb[res >> 5] >> (res & 31u)) & 1u);
+            }
         }
         const uint64_t m = __ballot(emit);
         if (m) {

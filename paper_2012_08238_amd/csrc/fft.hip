@@ -258,52 +258,14 @@ __device__ __forceinline__ void emit_selection(uint64_t selm, IdxF idx_of, uint3
     for (int i = threadIdx.x; i < nw; i += NT) gst(jb + i, bits[i]);
 }
 
-// Selection of the dK largest |uhat|^2 (ties -> lower bucket): radix select on
-// the IEEE bit patterns of the non-negative energies (monotone as unsigned),
-// four 8-bit digits from the top. Digit counts go to an LDS histogram; the
-// first digit (sign + high exponent bits, shared by most buckets) is counted
-// with one atomic per distinct digit per wave.
+// The dK largest |data[h]|^2 of the B values in LDS (ties -> lower h): bitmap
+// jb[B/32] and, when jl is not null, the ascending list jl[dK]. LDS scratch as
+// laid out by fft_select_kernel; the data region is reused for the bitmap.
 template <int LOG2B>
-__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a) {
+__device__ __forceinline__ void select_top(const float2* data, uint32_t dK, uint32_t* hist, uint32_t* scan,
+                                           uint32_t* bcast, uint32_t* bits, uint32_t* jl, uint32_t* jb) {
     using Cfg = FftCfg<LOG2B>;
     constexpr int B = Cfg::B, NT = Cfg::NT, CH = Cfg::CH, NW = Cfg::NW;
-    extern __shared__ f4v lds_raw[];
-    float2* data = reinterpret_cast<float2*>(lds_raw);
-    float2* tlo = data + Cfg::PADN;
-    float2* thi = tlo + Cfg::TL;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(thi + Cfg::TH);
-    uint32_t* scan = hist + 256;   // NT/64 <= 16 words
-    uint32_t* bcast = scan + 16;   // [0] digit, [1] remaining rank
-    uint32_t* bits = reinterpret_cast<uint32_t*>(data);  // reuses the data region at the end
-
-    uint32_t sig, r;
-    resolve(a, sig, r);
-    const auto& d = desc_of(a, sig);
-    float2* u = d.uhat + (size_t)r * B;
-    const float2* tw = d.tw;
-    {
-        // the bucketization stored loop r's values in column order: column col
-        // holds bucket b = sigma_r^{-1} (col - tau_r) mod B; place them by bucket
-        const uint32_t sinv = d.sigma_inv[r], tu = d.tau[r];
-        constexpr int LPT = (B + NT - 1) / NT;
-        float2 tmp[LPT];
-#pragma unroll
-        for (int q = 0; q < LPT; ++q) {
-            const int col = min((int)threadIdx.x + q * NT, B - 1);
-            tmp[q] = gld(u + col);
-        }
-#pragma unroll
-        for (int q = 0; q < LPT; ++q) {
-            const uint32_t col = threadIdx.x + q * NT;
-            if (col < (uint32_t)B) data[padi((int)((sinv * (col - tu)) & (uint32_t)(B - 1)))] = tmp[q];
-        }
-    }
-    for (int j = threadIdx.x; j < Cfg::TL; j += NT) tlo[j] = gld(tw + j);
-    for (int j = threadIdx.x; j < Cfg::TH; j += NT) thi[j] = gld(tw + (j << Cfg::LOG2TL));
-    __syncthreads();
-    fft_passes<LOG2B, 0>(data, tlo, thi);
-    for (int h = threadIdx.x; h < B; h += NT) gst(u + h, data[padi(h)]);
-
     const bool valid = (int)threadIdx.x * CH < B;
     uint32_t key[CH];
 #pragma unroll
@@ -314,9 +276,7 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
             key[c] = energy_key(v);
         }
     }
-    const uint32_t dK = d.dK;
-    uint32_t* jl = d.jlist + (size_t)r * dK;
-    uint32_t* jb = d.jbits + (size_t)r * NW;
+    const uint32_t nl = jl ? dK : 0u;   // list entries written (none without a list)
     bool kv[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) kv[c] = valid;
@@ -363,7 +323,7 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
                 block_kth_largest<NT, CPT>(ck, cv, dK, hist, bcast, theta, rank);
                 const uint64_t selm = select_mask<NT, CPT>(ck, cv, theta, rank, scan);
                 emit_selection<NT, CPT>(selm, [&](int q) { return cidx[threadIdx.x * CPT + q]; }, bits, NW, scan,
-                                        jl, jb, dK);
+                                        jl, jb, nl);
                 done = true;
             }
         }
@@ -373,10 +333,102 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
         block_kth_largest<NT, CH>(key, kv, dK, hist, bcast, theta, rank);
         const uint64_t selm = select_mask<NT, CH>(key, kv, theta, rank, scan);
         emit_selection<NT, CH>(selm, [&](int c) { return (uint32_t)(threadIdx.x * CH + c); }, bits, NW, scan, jl, jb,
-                               dK);
+                               nl);
     }
 }
 
+// Selection of the dK largest |uhat|^2 (ties -> lower bucket): radix select on
+// the IEEE bit patterns of the non-negative energies (monotone as unsigned),
+// four 8-bit digits from the top. Digit counts go to an LDS histogram; the
+// first digit (sign + high exponent bits, shared by most buckets) is counted
+// with one atomic per distinct digit per wave.
+template <int LOG2B>
+__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a) {
+    using Cfg = FftCfg<LOG2B>;
+    constexpr int B = Cfg::B, NT = Cfg::NT, NW = Cfg::NW;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tlo = data + Cfg::PADN;
+    float2* thi = tlo + Cfg::TL;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(thi + Cfg::TH);
+    uint32_t* scan = hist + 256;   // NT/64 <= 16 words
+    uint32_t* bcast = scan + 16;   // [0] digit, [1] remaining rank
+    uint32_t* bits = reinterpret_cast<uint32_t*>(data);  // reuses the data region at the end
+
+    uint32_t sig, r;
+    resolve(a, sig, r);
+    const auto& d = desc_of(a, sig);
+    float2* u = d.uhat + (size_t)r * B;
+    const float2* tw = d.tw;
+    {
+        // the bucketization stored loop r's values in column order: column col
+        // holds bucket b = sigma_r^{-1} (col - tau_r) mod B; place them by bucket
+        const uint32_t sinv = d.sigma_inv[r], tu = d.tau[r];
+        constexpr int LPT = (B + NT - 1) / NT;
+        float2 tmp[LPT];
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int col = min((int)threadIdx.x + q * NT, B - 1);
+            tmp[q] = gld(u + col);
+        }
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const uint32_t col = threadIdx.x + q * NT;
+            if (col < (uint32_t)B) data[padi((int)((sinv * (col - tu)) & (uint32_t)(B - 1)))] = tmp[q];
+        }
+    }
+    for (int j = threadIdx.x; j < Cfg::TL; j += NT) tlo[j] = gld(tw + j);
+    for (int j = threadIdx.x; j < Cfg::TH; j += NT) thi[j] = gld(tw + (j << Cfg::LOG2TL));
+    __syncthreads();
+    fft_passes<LOG2B, 0>(data, tlo, thi);
+    for (int h = threadIdx.x; h < B; h += NT) gst(u + h, data[padi(h)]);
+
+    select_top<LOG2B>(data, d.dK, hist, scan, bcast, bits, d.jlist + (size_t)r * d.dK, d.jbits + (size_t)r * NW);
+}
+
+// ---------------------------------------------------------------- comb prefilter
+// Spike-train bucketization of the sFFT2.0 row (Eq.(15)-(16)): comb loop c takes
+// the Bc samples x[tau_c + j N/Bc]; their Bc-point DFT holds in bucket i the
+// coefficients at f = i (mod Bc), so the comb_keep largest buckets mark the
+// residues that may hold large coefficients (bitmap row c, ties -> lower
+// residue). One workgroup per (signal, comb loop); same LDS layout as
+// fft_select_kernel.
+template <int LOG2B>
+__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void comb_kernel(Launch a) {
+    using Cfg = FftCfg<LOG2B>;
+    constexpr int B = Cfg::B, NT = Cfg::NT, NW = Cfg::NW;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    float2* tlo = data + Cfg::PADN;
+    float2* thi = tlo + Cfg::TL;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(thi + Cfg::TH);
+    uint32_t* scan = hist + 256;
+    uint32_t* bcast = scan + 16;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(data);
+    uint32_t sig, c;
+    resolve(a, sig, c);
+    const auto& d = desc_of(a, sig);
+    const float2* x = io_of(a, sig).x;
+    const uint32_t tc = ((CU32)d.comb_tau)[c], sh = d.log2N - (uint32_t)LOG2B, maskN = d.maskN;
+    constexpr int LPT = (B + NT - 1) / NT;
+    float2 tmp[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        const uint32_t j = min((uint32_t)threadIdx.x + (uint32_t)(q * NT), (uint32_t)B - 1u);
+        tmp[q] = gld(x + ((tc + (j << sh)) & maskN));
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        const int j = (int)threadIdx.x + q * NT;
+        if (j < B) data[padi(j)] = tmp[q];
+    }
+    const float2* tw = d.ctw;
+    for (int j = threadIdx.x; j < Cfg::TL; j += NT) tlo[j] = gld(tw + j);
+    for (int j = threadIdx.x; j < Cfg::TH; j += NT) thi[j] = gld(tw + (j << Cfg::LOG2TL));
+    __syncthreads();
+    fft_passes<LOG2B, 0>(data, tlo, thi);
+    select_top<LOG2B>(data, d.comb_keep, hist, scan, bcast, bits, nullptr, d.cbits + (size_t)c * NW);
+}
 
 // ---------------------------------------------------------------- two-pass FFT (B > 16384)
 // The bucketization leaves the bucket values in column order, v[col] = u[b] with
@@ -749,8 +801,39 @@ static hipError_t launch_fft_t(const Launch& a, uint32_t units, hipStream_t s) {
 
 template <int LOG2B>
 static hipError_t set_fft_attr() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_select_kernel<LOG2B>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)FftCfg<LOG2B>::lds_bytes());
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_select_kernel<LOG2B>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)FftCfg<LOG2B>::lds_bytes());
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&comb_kernel<LOG2B>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)FftCfg<LOG2B>::lds_bytes());
+    return e;
+}
+
+template <int LOG2B>
+static hipError_t launch_comb_t(const Launch& a, uint32_t units, hipStream_t s) {
+    using Cfg = FftCfg<LOG2B>;
+    hipLaunchKernelGGL(comb_kernel<LOG2B>, dim3(units), dim3(Cfg::NT), Cfg::lds_bytes(), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_comb(const Launch& a, uint32_t log2b, uint32_t units, hipStream_t s) {
+    switch (log2b) {
+        case 1: return launch_comb_t<1>(a, units, s);
+        case 2: return launch_comb_t<2>(a, units, s);
+        case 3: return launch_comb_t<3>(a, units, s);
+        case 4: return launch_comb_t<4>(a, units, s);
+        case 5: return launch_comb_t<5>(a, units, s);
+        case 6: return launch_comb_t<6>(a, units, s);
+        case 7: return launch_comb_t<7>(a, units, s);
+        case 8: return launch_comb_t<8>(a, units, s);
+        case 9: return launch_comb_t<9>(a, units, s);
+        case 10: return launch_comb_t<10>(a, units, s);
+        case 11: return launch_comb_t<11>(a, units, s);
+        case 12: return launch_comb_t<12>(a, units, s);
+        case 13: return launch_comb_t<13>(a, units, s);
+        case 14: return launch_comb_t<14>(a, units, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int LB>

@@ -21,6 +21,8 @@ struct Resolved {
     uint32_t log2N, log2B, log2M;
     uint32_t mode, C, log2C;    // bucketization form (0 gather, 1 strip) and strip width
     uint32_t fft_mode;          // 0 one-workgroup FFT (B <= 16384), 1 two-pass FFT
+    uint32_t comb_b, comb_log2b, comb_loops, comb_keep, comb_words;  // comb prefilter
+    std::vector<uint32_t> comb_tau;
     uint32_t fft_p1_units, fft_p2_units;   // two-pass FFT workgroups per signal
     uint64_t seed;
     double gauss_c;
@@ -40,6 +42,7 @@ struct HostTables {
     std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
     std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N}, two bit fields
     std::vector<double> rou;                    // (re, im) pairs of e^{2 pi i j / 2^tb}
+    std::vector<float> ctw;                     // [comb_b] (re, im) pairs of e^{-2 pi i m/comb_b}
 };
 
 constexpr double kDefaultGaussC = 4.861870431316438;  // 516 / (2 * 16 * sqrt(11)), Fig. 1 example
@@ -80,13 +83,13 @@ inline uint32_t ilog2(uint64_t v) {
 
 // Device workspace layout of one execution (byte offsets, 256-aligned).
 struct WsLayout {
-    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, ubuf, gmax, total;
+    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, ubuf, gmax, cbits, total;
 };
 WsLayout workspace_layout(const Resolved& R);
 
 // Device table layout (byte offsets into one allocation).
 struct TabLayout {
-    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rou, total;
+    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rou, ctau, ctw, total;
 };
 TabLayout table_layout(const Resolved& R);
 

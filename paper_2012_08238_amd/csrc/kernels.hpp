@@ -13,6 +13,8 @@ uint32_t fold_variant(uint32_t mode, uint32_t strip_lds, uint32_t items, uint32_
 hipError_t launch_fold(const Launch& a, uint32_t variant, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // one workgroup per (signal, loop); every signal of the launch has B = 2^log2B <= 16384
 hipError_t launch_fft_select(const Launch& a, uint32_t log2B, uint32_t units, hipStream_t s);
+// comb prefilter: one workgroup per (signal, comb loop); every signal of the launch has Bc = 2^log2b <= 16384
+hipError_t launch_comb(const Launch& a, uint32_t log2b, uint32_t units, hipStream_t s);
 // B = 2^log2B > 16384: pass 0 = first FFT pass (units = L * B2/16 per signal),
 // 1 = second pass (L * B1/16), 2 = selection (L); every signal of the launch has this B
 hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint32_t units, hipStream_t s);

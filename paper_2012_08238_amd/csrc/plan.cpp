@@ -35,6 +35,13 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     if ((p.sigma == nullptr) != (p.tau == nullptr)) return bad("sigma and tau must be given together");
     if ((p.flags & SFFT_FLAG_FOLD_GATHER) && (p.flags & SFFT_FLAG_FOLD_STRIP))
         return bad("FOLD_GATHER and FOLD_STRIP are exclusive");
+    if (p.comb_loops < 0 || p.comb_loops > kMaxCombLoops) return bad("comb_loops must be in [0, 8]");
+    if (p.comb_loops > 0) {
+        if (p.comb_b < 2 || !is_pow2((uint64_t)p.comb_b) || (int64_t)p.comb_b > p.N / 2 || p.comb_b > kMaxCombB)
+            return bad("comb_b must be a power of two in [2, min(N/2, 16384)]");
+        const int64_t keep = p.comb_keep ? p.comb_keep : (int64_t)p.d * p.K;
+        if (keep < 1 || keep > p.comb_b) return bad("comb_keep must be in [1, comb_b]");
+    }
     if (p.B > kMaxB) {
         *err = "B > 2^18 is not supported by this build";
         return SFFT_E_UNSUPPORTED;
@@ -80,6 +87,14 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     }
     R.tpos.resize(R.S);
     for (uint32_t j = 0; j < R.S; ++j) R.tpos[j] = (uint32_t)(rng.next() & (R.N - 1));
+    // comb prefilter shifts: the next draws of the same stream
+    R.comb_loops = (uint32_t)p.comb_loops;
+    R.comb_b = R.comb_loops ? (uint32_t)p.comb_b : 0u;
+    R.comb_log2b = R.comb_loops ? ilog2(R.comb_b) : 0u;
+    R.comb_keep = R.comb_loops ? (uint32_t)(p.comb_keep ? p.comb_keep : p.d * p.K) : 0u;
+    R.comb_words = R.comb_loops ? std::max<uint32_t>(1u, R.comb_b / 32) : 0u;
+    R.comb_tau.resize(R.comb_loops);
+    for (uint32_t c = 0; c < R.comb_loops; ++c) R.comb_tau[c] = (uint32_t)(rng.next() & (R.N - 1));
     if (p.sigma) {
         for (uint32_t r = 0; r < R.L; ++r) {
             if (!(p.sigma[r] & 1u) || p.sigma[r] >= R.N || p.tau[r] >= R.N)
@@ -224,6 +239,12 @@ void build_tables(const Resolved& R, HostTables* t) {
         t->tw[2 * m] = (float)cos(a);
         t->tw[2 * m + 1] = (float)sin(a);
     }
+    t->ctw.resize(2 * (size_t)R.comb_b);
+    for (uint32_t m = 0; m < R.comb_b; ++m) {
+        const double a = -2.0 * pi * (double)m / (double)R.comb_b;
+        t->ctw[2 * m] = (float)cos(a);
+        t->ctw[2 * m + 1] = (float)sin(a);
+    }
 }
 
 WsLayout workspace_layout(const Resolved& R) {
@@ -246,6 +267,7 @@ WsLayout workspace_layout(const Resolved& R) {
     l.ctr = take(16);
     l.ubuf = take(R.fft_mode ? (size_t)R.L * R.B * 8 : 16);
     l.gmax = take(R.fft_mode ? (size_t)R.L * (R.B / 16) * 4 : 16);
+    l.cbits = take((size_t)R.comb_loops * R.comb_words * 4);
     l.total = off;
     return l;
 }
@@ -266,6 +288,8 @@ TabLayout table_layout(const Resolved& R) {
     l.invG = take((size_t)R.M * 8);
     l.tw = take((size_t)R.B * 8);
     l.rou = take((size_t)16 << R.tb);
+    l.ctau = take((size_t)R.comb_loops * 4);
+    l.ctw = take((size_t)R.comb_b * 8);
     l.total = off;
     return l;
 }
@@ -285,6 +309,10 @@ std::vector<char> pack_tables(const Resolved& R, const HostTables& T) {
     memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
     memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
     memcpy(&h[tl.rou], T.rou.data(), T.rou.size() * 8);
+    if (R.comb_loops) {
+        memcpy(&h[tl.ctau], R.comb_tau.data(), (size_t)R.comb_loops * 4);
+        memcpy(&h[tl.ctw], T.ctw.data(), T.ctw.size() * 4);
+    }
     return h;
 }
 

@@ -154,6 +154,9 @@ std::string plan_key(const sfft_params& p) {
     put(&p.gauss_c, 8);
     put(&p.flags, 4);
     put(&p.strip_cols, 4);
+    put(&p.comb_b, 4);
+    put(&p.comb_loops, 4);
+    put(&p.comb_keep, 4);
     const int32_t has = p.sigma != nullptr;
     put(&has, 4);
     if (p.sigma && p.tau && p.L > 0 && p.L <= kMaxL) {

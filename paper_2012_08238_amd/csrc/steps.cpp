@@ -17,7 +17,8 @@ constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
 size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // vote: 2 x kLmaxCount; finalize: kLmaxCount; residual: 1
-    const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + 3 * kLmaxCount + 1;
+    // + comb prefilter: one launch per comb size (2^1 .. 2^14)
+    const size_t launches = n + 2 * kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + 3 * kLmaxCount + 1;
     return launches * (n + 1);
 }
 
@@ -58,6 +59,8 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
                 if (R.log2B != lb) return 0u;
                 return pass == 0 ? R.fft_p1_units : (pass == 1 ? R.fft_p2_units : R.L);
             });
+    for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)
+        add_step(kStepComb, lb, 0, [&](const Resolved& R) { return R.comb_loops && R.comb_log2b == lb ? R.comb_loops : 0u; });
     for (uint32_t staged = 0; staged < 2; ++staged)
         for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
             auto in_group = [&](const Resolved& R) { return (R.vote_lds > 0) == (staged == 1) && R.lmax == lm; };
@@ -91,6 +94,7 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
             case kStepFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
             case kStepRes: e = launch_residual(a, st.units, st.lds, s); break;
             case kStepFftLarge: e = launch_fft_large(a, st.param & 255u, st.param >> 8, st.units, s); break;
+            case kStepComb: e = launch_comb(a, st.param, st.units, s); break;
         }
         if (e != hipSuccess) return e;
     }

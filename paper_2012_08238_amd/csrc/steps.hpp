@@ -12,7 +12,9 @@
 
 namespace sfft {
 
-enum StepKind : uint32_t { kStepFold = 0, kStepFft = 1, kStepVote = 2, kStepFin = 3, kStepRes = 4, kStepFftLarge = 5 };
+enum StepKind : uint32_t {
+    kStepFold = 0, kStepFft = 1, kStepVote = 2, kStepFin = 3, kStepRes = 4, kStepFftLarge = 5, kStepComb = 6
+};
 
 struct Step {
     StepKind kind;

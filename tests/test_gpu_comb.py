@@ -1,0 +1,119 @@
+"""Comb prefilter (spike-train bucketization of the sFFT2.0 row) on the GPU
+against the oracle: each comb shift's kept residues equal the oracle's where
+its selection margin is not a near-tie, and the candidates and outputs obey
+the same parity bar as the plain path."""
+import numpy as np
+import pytest
+
+import oracle.sfft_oracle as O
+from paper_2012_08238_amd.signals import make_signal
+from test_gpu_parity import SEL_MARGIN, check_residual, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(dev, x64, **kw):
+    import torch
+    import paper_2012_08238_amd as S
+    N = x64.shape[0]
+    p = S.Plan(N, **kw)
+    idx, val, res = p(torch.from_numpy(x64.astype(np.complex64)).to(dev), residual=True)
+    torch.cuda.synchronize()
+    out = dict(idx=idx.cpu().numpy(), val=val.cpu().numpy().astype(np.complex128), resid=res.cpu().numpy(),
+               trace=p.trace(), perms=p.perms(), desc=p.desc)
+    p.close()
+    return out
+
+
+def _check_comb(g, r, x64, Bc, keep):
+    """Per comb shift: the kept residues equal the oracle's when the keep-th
+    largest energy is resolved (margin above SEL_MARGIN and above the rounding
+    floor of FP32 arithmetic, 1e-9 of the largest energy); otherwise (an exactly
+    sparse signal leaves most comb buckets at rounding level) every residue above
+    the floor must be kept and the rest are ties at rounding level."""
+    x = x64.astype(np.complex64).astype(np.complex128)
+    rows = g["trace"]["comb_rows"]
+    exact = True
+    for c, t in enumerate(r.trace["comb_tau"]):
+        u = O.comb_buckets(x, Bc, int(t))
+        E = u.real ** 2 + u.imag ** 2
+        J, margin = O.select_buckets(u, keep)
+        got = np.nonzero(rows[c])[0]
+        assert got.shape[0] == keep
+        floor = 1e-9 * E.max()
+        kth = np.sort(E)[::-1][keep - 1]
+        if margin > SEL_MARGIN and kth > floor:
+            assert np.array_equal(got, J), f"comb shift {c}"
+        else:
+            exact = exact and np.array_equal(got, J)
+        if kth <= floor:
+            strong = np.nonzero(E > floor)[0]
+            assert set(strong.tolist()) <= set(got.tolist()), f"comb shift {c}: a resolved residue was dropped"
+    return exact
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(N=1 << 20, K=50, B=1024, L=7, w=8192, seed=31, comb_b=1024, comb_loops=2, snr=20.0),
+    dict(N=1 << 14, K=10, B=128, L=5, w=512, seed=32, comb_b=256, comb_loops=1, snr=None),
+    dict(N=1 << 16, K=20, B=512, L=7, w=4096, seed=33, comb_b=2, comb_loops=3, comb_keep=1, snr=10.0),
+    dict(N=1 << 16, K=20, B=512, L=7, w=4096, seed=34, comb_b=16384, comb_loops=2, snr=10.0),
+    dict(N=1 << 16, K=20, B=512, L=7, w=4096, seed=35, comb_b=64, comb_loops=1, comb_keep=64, snr=10.0),
+    dict(N=1 << 22, K=200, B=1 << 15, L=9, w=1 << 18, seed=36, comb_b=4096, comb_loops=2, snr=20.0),
+])
+def test_comb_parity(dev, cfg):
+    cfg = dict(cfg)
+    N = cfg.pop("N")
+    snr = cfg.pop("snr")
+    sig = make_signal(N, cfg["K"], snr, seed=cfg["seed"] + 90)
+    g = _run(dev, sig.x, **cfg)
+    keep = cfg.get("comb_keep", 0) or 2 * cfg["K"]
+    r = O.sfft(sig.x.astype(np.complex64).astype(np.complex128), cfg["K"], cfg["B"], cfg["L"], cfg["w"],
+               seed=cfg["seed"], comb_b=cfg["comb_b"], comb_loops=cfg["comb_loops"], comb_keep=keep)
+    exact = _check_comb(g, r, sig.x, cfg["comb_b"], keep)
+    compare(g, r, cfg["K"], cfg["B"], cfg["L"], cfg["w"], cfg["seed"], cand_exact=exact)
+    check_residual(g, sig.x, r.trace["tpos"])
+
+
+def test_comb_reduces_candidates(dev):
+    """With 10% of the buckets kept per loop (C2 shape) many false frequencies pass
+    the vote; the comb keeps only those whose residue holds a large comb bucket."""
+    sig = make_signal(1 << 20, 50, 20.0, seed=40)
+    a = _run(dev, sig.x, K=50, B=1024, L=7, w=8192, seed=3)
+    b = _run(dev, sig.x, K=50, B=1024, L=7, w=8192, seed=3, comb_b=4096, comb_loops=2)
+    na, nb = a["trace"]["cand"].shape[0], b["trace"]["cand"].shape[0]
+    assert nb < na / 5
+    assert set(b["trace"]["cand"].tolist()) <= set(a["trace"]["cand"].tolist())
+    assert set(b["idx"].tolist()) == set(sig.freqs.tolist()) == set(a["idx"].tolist())
+
+
+def test_comb_zero_signal(dev):
+    N, K, B, L, w = 1 << 12, 4, 64, 5, 512
+    x = np.zeros(N, dtype=np.complex128)
+    g = _run(dev, x, K=K, B=B, L=L, w=w, seed=3, comb_b=128, comb_loops=2)
+    r = O.sfft(x, K, B, L, w, seed=3, comb_b=128, comb_loops=2)
+    assert np.array_equal(g["idx"], r.idx)
+    for c in range(2):
+        assert np.array_equal(np.nonzero(g["trace"]["comb_rows"][c])[0], np.arange(2 * K))
+
+
+def test_comb_in_batch(dev):
+    import torch
+    import paper_2012_08238_amd as S
+    plans = [S.Plan(1 << 20, 50, 1024, 7, 8192, seed=3, comb_b=4096, comb_loops=2),
+             S.Plan(1 << 18, 30, 2048, 9, 16384, seed=4),
+             S.Plan(1 << 20, 50, 1024, 7, 8192, seed=5, comb_b=1024, comb_loops=1)]
+    xs = [torch.from_numpy(make_signal(p.params.N, p.params.K, 20.0, seed=41 + i).x.astype(np.complex64)).to(dev)
+          for i, p in enumerate(plans)]
+    singles = [tuple(t.clone() for t in p(x, residual=True)) for p, x in zip(plans, xs)]
+    torch.cuda.synchronize()
+    b = S.Batch(plans, branches=2)
+    outs = [p.outputs(dev) for p in plans]
+    for _ in range(2):
+        b.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        for o, s1 in zip(outs, singles):
+            for u, v in zip(o, s1):
+                assert torch.equal(u, v)
+    b.close()
+    for p in plans:
+        p.close()

@@ -40,7 +40,9 @@ def _oracle(x64, K, B, L, w, seed, d=2, vote_threshold=0, n_resid=4096, combine=
                   n_resid=n_resid, combine=combine)
 
 
-def compare(g, r, K, B, L, w, seed, check_values=True):
+def compare(g, r, K, B, L, w, seed, check_values=True, cand_exact=True):
+    """cand_exact=False when a prefilter's selection was a rounding-level tie (the
+    candidate sets may then differ by frequencies whose estimates are ~0)."""
     N = r.trace["counts"].shape[0]
     sigma, sigma_inv, tau = g["perms"]
     assert np.array_equal(sigma, r.trace["sigma"].astype(np.uint32))
@@ -63,7 +65,7 @@ def compare(g, r, K, B, L, w, seed, check_values=True):
             all_sel_equal = all_sel_equal and np.array_equal(jl, r.trace["J"][rr])
     cand = np.sort(g["trace"]["cand"].astype(np.int64))
     assert len(np.unique(cand)) == cand.shape[0], "duplicate candidates"
-    if all_sel_equal:
+    if all_sel_equal and cand_exact:
         assert np.array_equal(cand, np.sort(r.trace["I"])), "candidate set"
     idx = g["idx"]
     if all_sel_equal and r.trace["final_margin"] > FINAL_MARGIN:

@@ -36,6 +36,8 @@ def test_version_and_status_strings():
 
 
 @pytest.mark.parametrize("bad", [
+    dict(comb_loops=1, comb_b=3), dict(comb_loops=1, comb_b=1 << 14), dict(comb_loops=9, comb_b=64),
+    dict(comb_loops=1, comb_b=16), dict(comb_loops=1, comb_b=64, comb_keep=65), dict(comb_loops=-1),
     dict(N=1000), dict(N=8), dict(B=3), dict(B=1 << 14), dict(B=16), dict(K=0), dict(K=600), dict(L=0), dict(L=33),
     dict(w=511), dict(w=0), dict(w=1 << 15), dict(vote_threshold=9), dict(n_resid=-1)])
 def test_parameter_validation(bad):
