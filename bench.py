@@ -165,6 +165,46 @@ def snr_sweep(S, torch, dev, args) -> dict:
     return out
 
 
+def comb_measure(S, torch, dev, args) -> dict:
+    """The comb prefilter (sFFT2.0 row) on batches of 64 resident signals: the
+    C2 shape (N=2^20, K=50, B=1024, L=7, w=8B; 10% of the buckets kept per loop,
+    so thousands of false frequencies pass the vote) and the benchmark shape with
+    fewer buckets (N=2^22, K=100, B=4096, the comb disambiguating), each without
+    and with the comb: signals/s, candidates per signal, exact supports."""
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    shapes = [("c2", 1 << 20, 50, 1024, 7, 0, 0), ("c2+comb", 1 << 20, 50, 1024, 7, 4096, 2),
+              ("n22_b4096", 1 << 22, 100, 4096, 9, 0, 0), ("n22_b4096+comb", 1 << 22, 100, 4096, 9, 16384, 2)]
+    out = {}
+    m = args.comb_batch
+    cache = {}
+    for name, n, k, b, l, cb, cl in shapes:
+        if (n, k) not in cache:
+            cache[(n, k)] = [make_signal_torch(n, k, 20.0, derive_seed(70, i), dev) for i in range(m)]
+        sigs = cache[(n, k)]
+        plan = S.Plan(n, k, b, l, 8 * b, seed=13, comb_b=cb, comb_loops=cl)
+        bt = S.Batch([plan] * m, branches=args.branches)
+        outs = [plan.outputs(dev) for _ in range(m)]
+        xs = [q[0] for q in sigs]
+        for _ in range(2):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.comb_steps):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        exact = sum(set(o[0].cpu().numpy().tolist()) == set(q[1].tolist()) for o, q in zip(outs, sigs))
+        plan.execute(xs[0], *outs[0])
+        ncand = int(plan.trace()["cand"].shape[0])
+        bt.close()
+        plan.close()
+        out[name] = {"N": n, "K": k, "B": b, "L": l, "w": 8 * b, "comb_b": cb, "comb_loops": cl,
+                     "signals_per_s": round(m * args.comb_steps / el, 1), "candidates_signal0": ncand,
+                     "exact_support": f"{exact}/{m}"}
+    cache.clear()
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -314,6 +354,8 @@ def main() -> int:
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--mix-pool", type=int, default=64, help="pool of mixed-size served signals (0 = skip)")
     ap.add_argument("--sweep-signals", type=int, default=8, help="signals per SNR point of the error sweep (0 = skip)")
+    ap.add_argument("--comb-batch", type=int, default=64, help="signals per batch of the comb prefilter runs (0 = skip)")
+    ap.add_argument("--comb-steps", type=int, default=10)
     ap.add_argument("--mix-budget-gib", type=int, default=16)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
@@ -425,6 +467,7 @@ def main() -> int:
         print(f"# mixed serving p50 {serving_mix['poisson']['p50_ms']} ms p99 {serving_mix['poisson']['p99_ms']} ms",
               file=sys.stderr, flush=True)
     sweep = snr_sweep(S, torch, dev, args) if args.sweep_signals > 0 else None
+    comb = comb_measure(S, torch, dev, args) if args.comb_batch > 0 else None
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -491,6 +534,7 @@ def main() -> int:
         "serving_mixed_sizes": serving_mix,
         "uneven_batch": uneven,
         "error_vs_snr": sweep,
+        "comb_prefilter": comb,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,
