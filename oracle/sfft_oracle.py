@@ -180,6 +180,17 @@ def gain_table(g: np.ndarray, N: int, B: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Bucket hash (flat-filter example: bucket = round(f / (N/B)), 64/128 -> 1).
 # ---------------------------------------------------------------------------
+def gain_wide(g: np.ndarray, N: int, B: int) -> np.ndarray:
+    """Gain at the offsets of a bucket and its two neighbours: Gw[o + 3N/2B] =
+    sum_n g_n e^{+2 pi i n o / N} for o in [-3N/2B, 3N/2B) (exact FP64 sum)."""
+    M = N // B
+    n = np.arange(g.shape[0], dtype=np.int64)
+    out = np.empty(3 * M, dtype=np.complex128)
+    for k, o in enumerate(range(-3 * M // 2, 3 * M // 2)):
+        out[k] = np.sum(g * np.exp(2j * np.pi * ((o * n) % N) / N))
+    return out
+
+
 def bucket_of(p, N: int, B: int):
     """Bucket of permuted frequency p: round-half-up of p/(N/B), taken mod B
     (the top half-bucket wraps to bucket 0)."""
@@ -292,6 +303,28 @@ def loop_estimates(I, uhat_list, sigma, tau, G, N: int, B: int) -> np.ndarray:
     return e
 
 
+# ---------------------------------------------------------------------------
+# Iterative framework: subtract the recovered coefficients before recovering
+# again (frameworks section, iterative framework).
+# ---------------------------------------------------------------------------
+def subtract_recovered(uhat_r: np.ndarray, f_list, v_list, sigma_r: int, tau_r: int, Gw: np.ndarray,
+                       N: int, B: int) -> np.ndarray:
+    """Loop r's bucket values with the recovered coefficients removed: each (f, v)
+    contributes v e^{+2 pi i tau f/N} Gw(sigma f - h N/B) to bucket h; its own bucket
+    and the two neighbours are corrected (further out the flat window's response
+    is below 1e-6 for w >= 8B and is dropped)."""
+    M = N // B
+    u = np.array(uhat_r, dtype=np.complex128, copy=True)
+    for f, v in zip(np.asarray(f_list, dtype=np.int64), np.asarray(v_list, dtype=np.complex128)):
+        p = (int(sigma_r) * int(f)) % N
+        h0 = int(bucket_of(p, N, B))
+        o = int(offset_in_bucket(p, N, B))
+        ph = np.exp(2j * np.pi * ((int(tau_r) * int(f)) % N) / N)
+        for j in (-1, 0, 1):
+            u[(h0 + j) % B] -= v * ph * Gw[o - j * M + 3 * M // 2]
+    return u
+
+
 def median_combine(e: np.ndarray) -> np.ndarray:
     """Coordinate-wise median over bucketizations (mean of the two middle values
     when the count is even)."""
@@ -382,12 +415,17 @@ def check_params(N, K, B, L, w, d=2):
 def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
          T: int | None = None, c_g: float = C_G, sigma=None, tau=None,
          n_resid: int = 4096, tpos=None, combine: str = "median",
-         comb_b: int = 0, comb_loops: int = 0, comb_keep: int = 0) -> OracleResult:
+         comb_b: int = 0, comb_loops: int = 0, comb_keep: int = 0, iterate: bool = False) -> OracleResult:
     """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout.
     combine: "median" (coordinate-wise, default) or "mean" of the loop estimates.
     comb_loops > 0 adds the comb prefilter: a frequency is a candidate only if
     its residue mod comb_b is among the comb_keep (default d*K) largest comb
-    buckets of some comb shift."""
+    buckets of some comb shift.
+    iterate=True adds one round of the iterative framework: the K recovered
+    coefficients are subtracted from every loop's buckets, the residual buckets
+    are selected and voted again (frequencies already recovered excluded),
+    new candidates are estimated from the residual, the recovered ones are
+    corrected by the median residual estimate, and the K largest are returned."""
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     check_params(N, K, B, L, w, d)
@@ -420,11 +458,31 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     comb = {"median": median_combine, "mean": mean_combine}[combine]
     v = comb(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
     idx, val, fmargin = finalize(I, v, K)
+    it = {}
+    if iterate:
+        keep1 = idx >= 0
+        K1, V1 = idx[keep1], val[keep1]
+        Gw = gain_wide(g, N, B)
+        ures = [subtract_recovered(uhat[r], K1, V1, int(sigma[r]), int(tau[r]), Gw, N, B) for r in range(L)]
+        sel2 = [select_buckets(u, d * K) for u in ures]
+        J2 = [s[0] for s in sel2]
+        voted2 = vote_counts(J2, sigma, N, B) >= T
+        if cmask is not None:
+            voted2 &= cmask[np.arange(N, dtype=np.int64) % comb_b]
+        voted2[K1] = False
+        I2 = np.nonzero(voted2)[0].astype(np.int64)
+        e2 = loop_estimates(I2, ures, sigma, tau, G, N, B)
+        v2 = comb(e2) if I2.shape[0] else np.zeros(0, dtype=np.complex128)
+        eK = loop_estimates(K1, ures, sigma, tau, G, N, B)
+        vK = V1 + (comb(eK) if K1.shape[0] else 0)
+        it = dict(idx1=idx, val1=val, final_margin1=fmargin, ures=ures, J2=J2,
+                  select_margin2=[s[1] for s in sel2], I2=I2, e2=e2, eK=eK)
+        idx, val, fmargin = finalize(np.concatenate([I2, K1]), np.concatenate([v2, vK]), K)
     e_res, e_in = residual_energy(x, idx, val, tpos) if len(tpos) else (0.0, 0.0)
     trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,
                  J=J, select_margin=[s[1] for s in sel], counts=counts, I=I,
                  e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos),
-                 comb_mask=cmask, comb_margin=cmargins, comb_tau=ctaus)
+                 comb_mask=cmask, comb_margin=cmargins, comb_tau=ctaus, **it)
     return OracleResult(idx=idx, val=val, e_res=e_res, e_in=e_in, trace=trace)
 
 
