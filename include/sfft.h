@@ -67,6 +67,15 @@ typedef enum {
 #define SFFT_FLAG_XCD_ORDER   0x8u  /* bucketization: give each XCD a contiguous range of column strips */
 #define SFFT_FLAG_MEAN_ESTIMATE 0x10u /* combine the L loop estimates by their mean (the averaging of the
                                          energy-concentration method) instead of the coordinate-wise median */
+#define SFFT_FLAG_ITERATE 0x20u       /* one round of the iterative framework (frameworks section): the K
+                                         recovered coefficients (f, v) are subtracted from every loop's
+                                         buckets, v e^{+2 pi i tau f/N} Gw(sigma f - h N/B) from the bucket h
+                                         of sigma f and its two neighbours (Gw = sum_n g_n e^{+2 pi i n o/N});
+                                         the residual buckets are selected and voted again (frequencies
+                                         already recovered excluded), new candidates are estimated from the
+                                         residual buckets, each recovered value is corrected by the combined
+                                         residual estimate, and the K largest of both are returned.
+                                         Requires B <= 16384 (else SFFT_E_UNSUPPORTED). */
 
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {
@@ -116,6 +125,11 @@ typedef struct {
     uint32_t* cand;         /* uint32[cand_cap]: frequencies with >= T votes, unordered */
     int64_t cand_count;     /* out: number of valid entries written to cand */
     uint32_t* cbits;        /* uint32[comb_loops * max(1, comb_b/32)]: residues kept per comb loop */
+    /* With SFFT_FLAG_ITERATE, uhat, jbits, jlist and cand above are those of the second round (residual
+     * buckets, their selection, the new candidates) and the first round's outputs are: */
+    uint32_t* rec_idx;      /* uint32[K]: first-round frequencies, ascending, 0xFFFFFFFF padded */
+    float* rec_val;         /* float[2*K]: their values (re, im) */
+    int64_t rec_count;      /* out: number of valid first-round entries (0 without SFFT_FLAG_ITERATE) */
 } sfft_trace;
 
 /* ---- parameters and plans --------------------------------------------------------- */

@@ -14,11 +14,11 @@ import numpy as np
 
 from . import _capi
 from ._capi import (SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, SFFT_FLAG_XCD_ORDER, SFFT_FLAG_NO_RESIDUAL,  # noqa: F401,E501
-                    SFFT_FLAG_MEAN_ESTIMATE, SfftError, check, load)
+                    SFFT_FLAG_MEAN_ESTIMATE, SFFT_FLAG_ITERATE, SfftError, check, load)
 
 __all__ = ["PlanParams", "Plan", "Batch", "Server", "host_tables", "load", "SfftError",
            "SFFT_FLAG_FOLD_GATHER", "SFFT_FLAG_FOLD_STRIP", "SFFT_FLAG_XCD_ORDER", "SFFT_FLAG_NO_RESIDUAL",
-           "SFFT_FLAG_MEAN_ESTIMATE"]
+           "SFFT_FLAG_MEAN_ESTIMATE", "SFFT_FLAG_ITERATE"]
 
 
 @dataclass
@@ -163,12 +163,21 @@ class Plan:
         nc, cb = self.params.comb_loops, self.params.comb_b
         cw = max(1, cb // 32) if nc else 1
         cbits = np.zeros(max(nc, 1) * cw, np.uint32)
+        K = d["K"]
+        ri = np.zeros(K, np.uint32)
+        rv = np.zeros(2 * K, np.float32)
         t = _capi.Trace(uh.ctypes.data_as(C.POINTER(C.c_float)), jb.ctypes.data_as(C.POINTER(C.c_uint32)),
                         jl.ctypes.data_as(C.POINTER(C.c_uint32)), cd.ctypes.data_as(C.POINTER(C.c_uint32)), 0,
-                        cbits.ctypes.data_as(C.POINTER(C.c_uint32)))
+                        cbits.ctypes.data_as(C.POINTER(C.c_uint32)), ri.ctypes.data_as(C.POINTER(C.c_uint32)),
+                        rv.ctypes.data_as(C.POINTER(C.c_float)), 0)
         check(load().sfft_plan_read_trace(self._h, C.byref(t)), "sfft_plan_read_trace")
         uhat = (uh[0::2] + 1j * uh[1::2]).reshape(L, B)
         out = dict(uhat=uhat, jbits=jb.reshape(L, wpl), jlist=jl.reshape(L, dK), cand=cd[:t.cand_count].copy())
+        if self.params.flags & SFFT_FLAG_ITERATE:
+            # first-round outputs (the trace arrays above are the second round's)
+            n1 = int(t.rec_count)
+            out["rec_idx"] = ri[:n1].astype(np.int64)
+            out["rec_val"] = (rv[0::2] + 1j * rv[1::2])[:n1]
         if nc:
             rows = cbits.reshape(nc, cw)
             out["comb_rows"] = np.array([[(rows[c, i >> 5] >> (i & 31)) & 1 for i in range(cb)] for c in range(nc)],

@@ -19,6 +19,7 @@ SFFT_FLAG_FOLD_GATHER = 0x2
 SFFT_FLAG_FOLD_STRIP = 0x4
 SFFT_FLAG_XCD_ORDER = 0x8
 SFFT_FLAG_MEAN_ESTIMATE = 0x10
+SFFT_FLAG_ITERATE = 0x20
 
 
 class Params(C.Structure):
@@ -41,7 +42,8 @@ class PlanDesc(C.Structure):
 class Trace(C.Structure):
     _fields_ = [("uhat", C.POINTER(C.c_float)), ("jbits", C.POINTER(C.c_uint32)),
                 ("jlist", C.POINTER(C.c_uint32)), ("cand", C.POINTER(C.c_uint32)),
-                ("cand_count", C.c_int64), ("cbits", C.POINTER(C.c_uint32))]
+                ("cand_count", C.c_int64), ("cbits", C.POINTER(C.c_uint32)),
+                ("rec_idx", C.POINTER(C.c_uint32)), ("rec_val", C.POINTER(C.c_float)), ("rec_count", C.c_int64)]
 
 
 class ServerStats(C.Structure):

@@ -54,6 +54,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.rou = reinterpret_cast<const double2*>(tab + t.rou);
     d.comb_tau = reinterpret_cast<const uint32_t*>(tab + t.ctau);
     d.ctw = reinterpret_cast<const float2*>(tab + t.ctw);
+    d.gw = reinterpret_cast<const float2*>(tab + t.gw);
     d.tb = R.tb;
     d.step = 6.283185307179586476925286766559 / (double)R.N;
     d.uhat = reinterpret_cast<float2*>(ws + w.uhat);
@@ -68,6 +69,9 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.ubuf = reinterpret_cast<float2*>(ws + w.ubuf);
     d.gmax = reinterpret_cast<uint32_t*>(ws + w.gmax);
     d.cbits = reinterpret_cast<uint32_t*>(ws + w.cbits);
+    d.rec_f = reinterpret_cast<uint32_t*>(ws + w.rec_f);
+    d.rec_v = reinterpret_cast<float2*>(ws + w.rec_v);
+    d.iterate = R.iterate;
     d.comb_loops = R.comb_loops;
     d.comb_log2b = R.comb_log2b;
     d.comb_keep = R.comb_keep;
@@ -119,8 +123,14 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
         HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
     }
     if (R.comb_loops) HIP_TRY(launch_comb(a, R.comb_log2b, R.comb_loops, s), "comb prefilter launch");
-    HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, s), "vote launch");
-    HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, s), "estimate launch");
+    HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 0, s), "vote launch");
+    HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, 0, s), "estimate launch");
+    if (R.iterate) {
+        HIP_TRY(launch_subtract(a, R.L, R.sub_lds, s), "subtraction launch");
+        HIP_TRY(launch_reselect(a, R.log2B, R.L, s), "reselection launch");
+        HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 1, s), "second vote launch");
+        HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, 1, s), "second estimate launch");
+    }
     if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
     return SFFT_OK;
 }
@@ -382,6 +392,11 @@ sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t) {
     HIP_TRY(hipMemcpy(ctr, p->d_ws + w.ctr, 16, hipMemcpyDeviceToHost), "copy counters");
     const uint32_t n = std::min(ctr[0], R.cap);
     t->cand_count = n;
+    t->rec_count = R.iterate ? std::min(ctr[2], R.K) : 0;
+    if (R.iterate && t->rec_idx)
+        HIP_TRY(hipMemcpy(t->rec_idx, p->d_ws + w.rec_f, (size_t)R.K * 4, hipMemcpyDeviceToHost), "copy first-round frequencies");
+    if (R.iterate && t->rec_val)
+        HIP_TRY(hipMemcpy(t->rec_val, p->d_ws + w.rec_v, (size_t)R.K * 8, hipMemcpyDeviceToHost), "copy first-round values");
     if (t->cand && n) HIP_TRY(hipMemcpy(t->cand, p->d_ws + w.cand, (size_t)n * 4, hipMemcpyDeviceToHost), "copy candidates");
     return SFFT_OK;
 }

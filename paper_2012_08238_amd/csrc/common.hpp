@@ -29,20 +29,23 @@ struct SigDesc {
     const double2* rou;         // [2^tb] e^{2 pi i j / 2^tb}, FP64
     const uint32_t* comb_tau;   // [comb_loops] time shifts of the comb prefilter
     const float2* ctw;          // [Bc] e^{-2 pi i m/Bc}
+    const float2* gw;           // [3M] gain at offsets o in [-3M/2, 3M/2): gw[o + 3M/2] (iteration only)
     // workspace
     float2* uhat;               // [L][B] bucket values in column order (bucket of column col is
                                 // sigma^{-1}(col - tau) mod B), then their B-point DFT in bucket order
     uint32_t* jbits;            // [L][B/32] selected buckets
     uint32_t* jlist;            // [L][dK] selected buckets, ascending
     uint32_t* cand;             // [cap] frequencies with >= T votes
-    float2* est;                // [cap] median estimates
-    uint64_t* keys;             // [cap] ordering keys of the estimates
+    float2* est;                // [cap (+ K with iteration)] median estimates
+    uint64_t* keys;             // [cap (+ K with iteration)] ordering keys of the estimates
     double* rpart;              // [2 * resid_blocks] residual partial sums
     double* resid_own;          // [2] residual when the caller gives no buffer
-    uint32_t* ctr;              // [4] counters: 0 candidates, 1 residual blocks done
+    uint32_t* ctr;              // [4] counters: 0 candidates, 1 residual blocks done, 2 first-round outputs
     float2* ubuf;               // [L][B] two-pass FFT intermediate (B > kMaxFftLds only)
     uint32_t* cbits;            // [comb_loops][max(1, Bc/32)] residues kept by each comb loop
     uint32_t* gmax;             // [L][B/16] largest energy of each 16 consecutive DFT outputs (idem)
+    uint32_t* rec_f;            // [K] first-round frequencies, ascending, 0xFFFFFFFF padded (iteration only)
+    float2* rec_v;              // [K] first-round values
     // sizes
     uint32_t N, maskN, log2N;
     uint32_t B, log2B;
@@ -63,6 +66,7 @@ struct SigDesc {
     uint32_t comb_loops;        // comb prefilter loops (0 = off)
     uint32_t comb_log2b;        // log2 Bc
     uint32_t comb_keep;         // residues kept per comb loop
+    uint32_t iterate;           // 1: one subtraction round after the first recovery
 };
 
 // Per-signal caller buffers of one execution.
@@ -93,6 +97,7 @@ constexpr uint32_t kFoldNT = 256;
 constexpr uint32_t kFftNT = 256;
 constexpr uint32_t kFinNT = 256;
 constexpr uint32_t kResNT = 256;
+constexpr uint32_t kSubNT = 256;
 constexpr uint32_t kStripLdsBytes = 65536;  // strip tile budget
 
 }  // namespace sfft

@@ -5,14 +5,26 @@
 
 namespace sfft {
 
+// Whether f is among the n ascending entries of a (binary search in global memory).
+__device__ __forceinline__ bool in_sorted(const uint32_t* a, uint32_t n, uint32_t f) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (gld(a + mid) < f) lo = mid + 1u; else hi = mid;
+    }
+    return lo < n && gld(a + lo) == f;
+}
+
 // ---------------------------------------------------------------- votes
 // A frequency with >= T votes out of L is voted by one of the loops 0..L-T
 // (pigeonhole), so only the frequencies of those loops' selected buckets are
 // enumerated: f = sigma_r0^{-1} p for the N/B permuted positions p of each
 // selected bucket. Each frequency is counted from the first loop that voted
 // for it (later loops skip it), so I' has no duplicates; votes are bitmap tests.
+// In the subtraction round (round 1) the frequencies recovered by the first
+// round are not candidates again.
 template <int LMAX>
-__global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged) {
+__global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged, uint32_t round) {
     extern __shared__ uint32_t sbits[];
     __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
     __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
@@ -70,6 +82,7 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     uint32_t* ctr = d.ctr;
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
+    const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;   // first-round frequencies (ascending)
     for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
         const uint32_t ci = start + qq * kVoteNT + threadIdx.x;   // candidate index within loop r0
         bool emit = false;
@@ -95,6 +108,7 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
                 const uint32_t res = f & cmask;
                 emit = emit && ((s_comb[res >> 5] >> (res & 31u)) & 1u);
             }
+            if (emit && n1) emit = !in_sorted(d.rec_f, n1, f);
         }
         const uint64_t m = __ballot(emit);
         if (m) {
@@ -178,8 +192,13 @@ __device__ __forceinline__ void stage_rou(double2* dst, const double2* src, uint
 // bucket), x'_f = median_r Re e_r + i median_r Im e_r; then the K largest |x'_f|^2
 // (ties -> lower f), returned in ascending f. One workgroup per signal.
 // Dynamic LDS: P values and P frequencies (P = 2^ceil(log2 K)).
+// With the subtraction round, round 0 keeps its K largest in the workspace
+// (rec_f, rec_v, count in ctr[2]) instead of the outputs; round 1 estimates the
+// new candidates from the residual buckets, adds the first round's
+// frequencies as candidates valued v + (combined residual estimate), and
+// writes the K largest of both to the outputs.
 template <int LMAX>
-__global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
+__global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t round) {
     extern __shared__ f4v lds_raw[];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t bc[4];
@@ -206,7 +225,8 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     }
     stage_rou<kFinNT>(s_rou, d.rou, d.tb);
     __syncthreads();
-    const uint32_t n = bc[3];   // block-uniform by construction
+    const uint32_t nc = bc[3];   // block-uniform by construction
+    const uint32_t n = nc + (round ? min(gld(d.ctr + 2), d.K) : 0u);
     const uint32_t* cand = d.cand;
     const float2* invG = d.invG;
     const float2* uhat = d.uhat;
@@ -214,7 +234,8 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
     float2* est = d.est;
     uint64_t* keys = d.keys;
     for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
-        const uint32_t f = gld(cand + i);
+        const bool rec = i >= nc;   // a first-round frequency (round 1)
+        const uint32_t f = rec ? gld(d.rec_f + (i - nc)) : gld(cand + i);
         float re[LMAX], im[LMAX];
 #pragma unroll
         for (int r = 0; r < LMAX; ++r) {
@@ -259,6 +280,11 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
         } else {
             mr = median_of<LMAX>(re, L);
             mi = median_of<LMAX>(im, L);
+        }
+        if (rec) {
+            const float2 v0 = gld(d.rec_v + (i - nc));
+            mr = v0.x + mr;
+            mi = v0.y + mi;
         }
         const float mag = fmaf(mr, mr, mi * mi);
         gst(est + i, make_float2(mr, mi));
@@ -355,6 +381,14 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
             __syncthreads();
         }
     }
+    if (d.iterate && round == 0) {
+        for (uint32_t k = threadIdx.x; k < K; k += kFinNT) {
+            gst(d.rec_f + k, k < cnt ? s_f[k] : 0xFFFFFFFFu);
+            gst(d.rec_v + k, k < cnt ? s_v[k] : make_float2(0.f, 0.f));
+        }
+        if (threadIdx.x == 0) gst(d.ctr + 2, cnt);
+        return;
+    }
     for (uint32_t k = threadIdx.x; k < K; k += kFinNT) {
         if (k < cnt) {
             gst(io.out_idx + k, (int64_t)s_f[k]);
@@ -363,6 +397,98 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a) {
             gst(io.out_idx + k, (int64_t)-1);
             gst(io.out_val + k, make_float2(0.f, 0.f));
         }
+    }
+}
+
+// ---------------------------------------------------------------- subtraction round
+// Iterative framework (frameworks section), subtraction step for loop r: a
+// recovered coefficient (f, v) with p = sigma_r f mod N in bucket h0 at offset
+// o = p - h0 N/B contributes v e^{+2 pi i (tau_r f mod N)/N} Gw(o - j N/B) to bucket
+// h0 + j (Eq.(9) with the flat window's gain); j = -1, 0, 1 are removed, further
+// buckets lie in the window's stopband. Each touched bucket is rewritten by one
+// thread that subtracts its contributions in a fixed order (coefficients sorted
+// by (h0, index)), so the result is independent of scheduling. Unit 0 also
+// clears the candidate counter for the second vote. One workgroup per
+// (signal, loop). Dynamic LDS: phased values [K], sort keys [P], offsets [K],
+// first sorted position of each bucket's run [B] (16 bit).
+__global__ __launch_bounds__(kSubNT) void subtract_kernel(Launch a) {
+    extern __shared__ f4v lds_raw[];
+    __shared__ double2 s_rou[kRouMax];
+    uint32_t sig, r;
+    resolve(a, sig, r);
+    const auto& d = desc_of(a, sig);
+    const uint32_t K = d.K, B = d.B, M = d.M, log2M = d.log2M, maskN = d.maskN, N = d.N;
+    uint32_t P = 1;
+    while (P < K) P <<= 1;
+    float2* s_vph = reinterpret_cast<float2*>(lds_raw);
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(s_vph + K);
+    int32_t* s_off = reinterpret_cast<int32_t*>(s_key + P);
+    uint16_t* s_first = reinterpret_cast<uint16_t*>(s_off + K);
+    const uint32_t n1 = min(gld(d.ctr + 2), K);
+    if (r == 0 && threadIdx.x == 0) gst(d.ctr, 0u);
+    if (n1 == 0) return;   // block-uniform: nothing was recovered
+    uint32_t Q = 1;        // sort size: power of two >= n1
+    while (Q < n1) Q <<= 1;
+    const uint32_t sg = gld(d.sigma + r), tu = gld(d.tau + r);
+    const uint32_t rsh = d.log2N - d.tb;
+    stage_rou<kSubNT>(s_rou, d.rou, d.tb);
+    for (uint32_t b = threadIdx.x; b < B; b += kSubNT) s_first[b] = 0xFFFFu;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < Q; k += kSubNT) {
+        uint32_t key = 0xFFFFFFFFu;
+        if (k < n1) {
+            const uint32_t f = gld(d.rec_f + k);
+            const float2 v = gld(d.rec_v + k);
+            const uint32_t p = (sg * f) & maskN;
+            const uint32_t h0 = ((p + (M >> 1)) >> log2M) & (B - 1u);
+            s_off[k] = (int32_t)((p - (h0 << log2M) + (N >> 1)) & maskN) - (int32_t)(N >> 1);
+            const double2 ph = phase_of(s_rou, (tu * f) & maskN, rsh, d.step);   // e^{+2 pi i tau f/N}
+            s_vph[k] = make_float2((float)((double)v.x * ph.x - (double)v.y * ph.y),
+                                   (float)((double)v.x * ph.y + (double)v.y * ph.x));
+            key = (h0 << 12) | k;   // h0 < 2^14, k < 2^12
+        }
+        s_key[k] = key;
+    }
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= Q; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < Q; i += kSubNT) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t x = s_key[i], y = s_key[l];
+                    if ((x > y) == ((i & kk) == 0)) {
+                        s_key[i] = y;
+                        s_key[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n1; i += kSubNT) {
+        const uint32_t h = s_key[i] >> 12;
+        if (i == 0 || (s_key[i - 1] >> 12) != h) s_first[h] = (uint16_t)i;
+    }
+    __syncthreads();
+    float2* u = d.uhat + (size_t)r * B;
+    const float2* gw = d.gw;
+    const int32_t c0 = (int32_t)(3u * M / 2u);
+    for (uint32_t b = threadIdx.x; b < B; b += kSubNT) {
+        // runs of the buckets b-1 (contributing with j = +1), b (j = 0), b+1 (j = -1)
+        const uint32_t hs[3] = {(b - 1u) & (B - 1u), b, (b + 1u) & (B - 1u)};
+        if (s_first[hs[0]] == 0xFFFFu && s_first[hs[1]] == 0xFFFFu && s_first[hs[2]] == 0xFFFFu) continue;
+        float2 acc = gld(u + b);
+        for (int q = 0; q < 3; ++q) {
+            const uint32_t hh = hs[q];
+            const int32_t sh = (q - 1) * (int32_t)M + c0;   // gw index = o - j M + 3M/2, j = 1 - q
+            for (uint32_t i = s_first[hh]; i < n1 && (s_key[i] >> 12) == hh; ++i) {
+                const uint32_t k = s_key[i] & 4095u;
+                const float2 c = cmul(s_vph[k], gld(gw + (s_off[k] + sh)));
+                acc.x -= c.x;
+                acc.y -= c.y;
+            }
+        }
+        gst(u + b, acc);
     }
 }
 
@@ -452,27 +578,42 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
+hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
+                       hipStream_t s) {
     const uint32_t staged = lds_bytes ? 1u : 0u;
     switch (lmax) {
-        case 4: hipLaunchKernelGGL(vote_kernel<4>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
-        case 8: hipLaunchKernelGGL(vote_kernel<8>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
-        case 16: hipLaunchKernelGGL(vote_kernel<16>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
-        case 32: hipLaunchKernelGGL(vote_kernel<32>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged); break;
+        case 4: hipLaunchKernelGGL(vote_kernel<4>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
+        case 8: hipLaunchKernelGGL(vote_kernel<8>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
+        case 16: hipLaunchKernelGGL(vote_kernel<16>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
+        case 32: hipLaunchKernelGGL(vote_kernel<32>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds, hipStream_t s) {
+hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds, uint32_t round,
+                           hipStream_t s) {
     switch (lmax) {
-        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(units), dim3(kFinNT), lds, s, a); break;
-        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(units), dim3(kFinNT), lds, s, a); break;
-        case 16: hipLaunchKernelGGL(finalize_kernel<16>, dim3(units), dim3(kFinNT), lds, s, a); break;
-        case 32: hipLaunchKernelGGL(finalize_kernel<32>, dim3(units), dim3(kFinNT), lds, s, a); break;
+        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
+        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
+        case 16: hipLaunchKernelGGL(finalize_kernel<16>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
+        case 32: hipLaunchKernelGGL(finalize_kernel<32>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(subtract_kernel, dim3(units), dim3(kSubNT), lds, s, a);
+    return hipGetLastError();
+}
+
+// largest subtraction LDS: K = 4096 (P = 4096), B = 16384
+constexpr int kSubLdsMax = kMaxK * 8 + kMaxK * 4 + kMaxK * 4 + kMaxFftLds * 2;
+
+hipError_t set_estimate_attributes() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&subtract_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kSubLdsMax);
 }
 
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {

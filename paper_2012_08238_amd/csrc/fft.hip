@@ -386,6 +386,29 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
     select_top<LOG2B>(data, d.dK, hist, scan, bcast, bits, d.jlist + (size_t)r * d.dK, d.jbits + (size_t)r * NW);
 }
 
+// Selection of the residual buckets of the subtraction round: loop r's B bucket
+// values (bucket order, as fft_select_kernel left them, then corrected by the
+// subtraction) are staged in LDS and the dK largest energies selected as in the
+// first round. Same LDS layout as fft_select_kernel.
+template <int LOG2B>
+__global__ __launch_bounds__(FftCfg<LOG2B>::NT) void reselect_kernel(Launch a) {
+    using Cfg = FftCfg<LOG2B>;
+    constexpr int B = Cfg::B, NT = Cfg::NT, NW = Cfg::NW;
+    extern __shared__ f4v lds_raw[];
+    float2* data = reinterpret_cast<float2*>(lds_raw);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(data + Cfg::PADN + Cfg::TL + Cfg::TH);
+    uint32_t* scan = hist + 256;
+    uint32_t* bcast = scan + 16;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(data);
+    uint32_t sig, r;
+    resolve(a, sig, r);
+    const auto& d = desc_of(a, sig);
+    const float2* u = d.uhat + (size_t)r * B;
+    for (int h = threadIdx.x; h < B; h += NT) data[padi(h)] = gld(u + h);
+    __syncthreads();
+    select_top<LOG2B>(data, d.dK, hist, scan, bcast, bits, d.jlist + (size_t)r * d.dK, d.jbits + (size_t)r * NW);
+}
+
 // ---------------------------------------------------------------- comb prefilter
 // Spike-train bucketization of the sFFT2.0 row (Eq.(15)-(16)): comb loop c takes
 // the Bc samples x[tau_c + j N/Bc]; their Bc-point DFT holds in bucket i the
@@ -806,7 +829,37 @@ static hipError_t set_fft_attr() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&comb_kernel<LOG2B>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)FftCfg<LOG2B>::lds_bytes());
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&reselect_kernel<LOG2B>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)FftCfg<LOG2B>::lds_bytes());
     return e;
+}
+
+template <int LOG2B>
+static hipError_t launch_reselect_t(const Launch& a, uint32_t units, hipStream_t s) {
+    using Cfg = FftCfg<LOG2B>;
+    hipLaunchKernelGGL(reselect_kernel<LOG2B>, dim3(units), dim3(Cfg::NT), Cfg::lds_bytes(), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reselect(const Launch& a, uint32_t log2B, uint32_t units, hipStream_t s) {
+    switch (log2B) {
+        case 1: return launch_reselect_t<1>(a, units, s);
+        case 2: return launch_reselect_t<2>(a, units, s);
+        case 3: return launch_reselect_t<3>(a, units, s);
+        case 4: return launch_reselect_t<4>(a, units, s);
+        case 5: return launch_reselect_t<5>(a, units, s);
+        case 6: return launch_reselect_t<6>(a, units, s);
+        case 7: return launch_reselect_t<7>(a, units, s);
+        case 8: return launch_reselect_t<8>(a, units, s);
+        case 9: return launch_reselect_t<9>(a, units, s);
+        case 10: return launch_reselect_t<10>(a, units, s);
+        case 11: return launch_reselect_t<11>(a, units, s);
+        case 12: return launch_reselect_t<12>(a, units, s);
+        case 13: return launch_reselect_t<13>(a, units, s);
+        case 14: return launch_reselect_t<14>(a, units, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int LOG2B>
@@ -892,6 +945,7 @@ hipError_t set_fft_attributes() {
 hipError_t set_kernel_attributes_impl() {
     hipError_t e = set_fft_attributes();
     if (e == hipSuccess) e = set_fold_attributes();
+    if (e == hipSuccess) e = set_estimate_attributes();
     return e;
 }
 

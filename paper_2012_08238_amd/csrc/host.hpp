@@ -22,6 +22,7 @@ struct Resolved {
     uint32_t mode, C, log2C;    // bucketization form (0 gather, 1 strip) and strip width
     uint32_t fft_mode;          // 0 one-workgroup FFT (B <= 16384), 1 two-pass FFT
     uint32_t comb_b, comb_log2b, comb_loops, comb_keep, comb_words;  // comb prefilter
+    uint32_t iterate, sub_lds;  // one subtraction round (iterative framework); its LDS bytes
     std::vector<uint32_t> comb_tau;
     uint32_t fft_p1_units, fft_p2_units;   // two-pass FFT workgroups per signal
     uint64_t seed;
@@ -37,12 +38,14 @@ struct Resolved {
 struct HostTables {
     std::vector<double> window;                 // g_n, n < w
     std::vector<std::complex<double>> gain;     // Gtab[o], o = -M/2 .. M/2-1
+    std::vector<std::complex<double>> gain_wide;  // [3M] gain at o = -3M/2 .. 3M/2-1 (iteration only)
     std::vector<float> gT;                      // [B][Mw4]
     std::vector<float> invG;                    // [M] (re, im) pairs of 1/Gtab
     std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
     std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N}, two bit fields
     std::vector<double> rou;                    // (re, im) pairs of e^{2 pi i j / 2^tb}
     std::vector<float> ctw;                     // [comb_b] (re, im) pairs of e^{-2 pi i m/comb_b}
+    std::vector<float> gw;                      // [3M] (re, im) pairs of gain_wide (iteration only)
 };
 
 constexpr double kDefaultGaussC = 4.861870431316438;  // 516 / (2 * 16 * sqrt(11)), Fig. 1 example
@@ -83,13 +86,13 @@ inline uint32_t ilog2(uint64_t v) {
 
 // Device workspace layout of one execution (byte offsets, 256-aligned).
 struct WsLayout {
-    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, ubuf, gmax, cbits, total;
+    size_t uhat, jbits, jlist, cand, est, keys, rpart, resid_own, ctr, ubuf, gmax, cbits, rec_f, rec_v, total;
 };
 WsLayout workspace_layout(const Resolved& R);
 
 // Device table layout (byte offsets into one allocation).
 struct TabLayout {
-    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rou, ctau, ctw, total;
+    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rou, ctau, ctw, gw, total;
 };
 TabLayout table_layout(const Resolved& R);
 

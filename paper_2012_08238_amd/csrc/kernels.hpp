@@ -20,14 +20,24 @@ hipError_t launch_comb(const Launch& a, uint32_t log2b, uint32_t units, hipStrea
 hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint32_t units, hipStream_t s);
 // lds_bytes = L * ceil(B/32) * 4 when the selected-bucket bitmaps are staged in LDS, else 0
 // lmax in {4, 8, 16, 32} >= L of every signal of the launch
-hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, hipStream_t s);
+// round 1: the vote of the subtraction round (the first round's frequencies are excluded)
+hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
+                       hipStream_t s);
 // one workgroup per signal; lmax in {4, 8, 16, 32} >= L of every signal of the launch
 // lds_bytes: K-sized output staging (Resolved::fin_lds / resid_lds)
-hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, hipStream_t s);
+// round 0 of an iterating signal keeps its K largest in the workspace; round 1
+// adds the first round's coefficients to the candidates and writes the outputs
+hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
+                           hipStream_t s);
+// subtraction round: one workgroup per (signal, loop); lds_bytes = Resolved::sub_lds (max over the launch)
+hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
+// selection of the residual buckets: one workgroup per (signal, loop); every signal has B = 2^log2B <= 16384
+hipError_t launch_reselect(const Launch& a, uint32_t log2B, uint32_t units, hipStream_t s);
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // raises the dynamic-LDS limit of the kernels that use more than 64 KB
 hipError_t set_kernel_attributes_impl();
 hipError_t set_fold_attributes();
 hipError_t set_fft_attributes();
+hipError_t set_estimate_attributes();
 
 }  // namespace sfft

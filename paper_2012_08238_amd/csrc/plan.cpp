@@ -46,6 +46,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         *err = "B > 2^18 is not supported by this build";
         return SFFT_E_UNSUPPORTED;
     }
+    if ((p.flags & SFFT_FLAG_ITERATE) && p.B > kMaxFftLds) {
+        *err = "the subtraction round needs B <= 16384";
+        return SFFT_E_UNSUPPORTED;
+    }
     R.N = (uint32_t)p.N;
     R.K = (uint32_t)p.K;
     R.B = (uint32_t)p.B;
@@ -148,6 +152,9 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     while (P < R.K) P <<= 1;
     R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies
     R.fin_lds = P * 8u + P * 4u;         // selected values, frequencies (sort size P)
+    R.iterate = (p.flags & SFFT_FLAG_ITERATE) ? 1u : 0u;
+    // subtraction round: phased values [K], sort keys [P], offsets [K], run starts [B] (16 bit)
+    R.sub_lds = R.iterate ? ((R.K * 8u + P * 4u + R.K * 4u + R.B * 2u + 15u) & ~15u) : 0u;
     R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;
     R.fold_variant = fold_variant(R.mode, R.strip_lds, R.L << R.log2C, R.Mw4 / 4);
     *out = std::move(R);
@@ -189,12 +196,16 @@ void build_tables(const Resolved& R, HostTables* t) {
         t->rou[2 * j] = cos(a);
         t->rou[2 * j + 1] = sin(a);
     }
-    // gain table Gtab[o] = sum_n g_n e^{+2 pi i (n o mod N)/N}, exact FP64 sum
-    t->gain.assign(M, std::complex<double>(0.0, 0.0));
+    // gain table Gtab[o] = sum_n g_n e^{+2 pi i (n o mod N)/N}, exact FP64 sum, at
+    // o = -M/2 .. M/2-1; with the subtraction round at o = -3M/2 .. 3M/2-1 (the
+    // offsets of a bucket's two neighbours too), whose middle M entries are Gtab
+    const uint32_t G = R.iterate ? 3 * M : M;
+    std::vector<std::complex<double>>& gout = R.iterate ? t->gain_wide : t->gain;
+    gout.assign(G, std::complex<double>(0.0, 0.0));
     const uint32_t lomask = nlo - 1;
     auto work = [&](uint32_t k0, uint32_t k1) {
         for (uint32_t k = k0; k < k1; ++k) {
-            const int64_t o = (int64_t)k - (int64_t)(M / 2);
+            const int64_t o = (int64_t)k - (int64_t)(G / 2);
             const uint32_t step = (uint32_t)((o % (int64_t)N + (int64_t)N) % (int64_t)N);
             double re = 0.0, im = 0.0;
             uint32_t m = 0;  // n * o mod N, advanced by step
@@ -207,19 +218,27 @@ void build_tables(const Resolved& R, HostTables* t) {
                 im += t->window[n] * sn;
                 m = (m + step) & (N - 1);
             }
-            t->gain[k] = std::complex<double>(re, im);
+            gout[k] = std::complex<double>(re, im);
         }
     };
-    const uint64_t work_total = (uint64_t)M * w;
+    const uint64_t work_total = (uint64_t)G * w;
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     if (work_total < (1u << 20)) nth = 1;
-    nth = std::min<unsigned>(nth, M);
+    nth = std::min<unsigned>(nth, G);
     std::vector<std::thread> th;
     for (unsigned i = 0; i < nth; ++i) {
-        const uint32_t k0 = (uint32_t)((uint64_t)M * i / nth), k1 = (uint32_t)((uint64_t)M * (i + 1) / nth);
+        const uint32_t k0 = (uint32_t)((uint64_t)G * i / nth), k1 = (uint32_t)((uint64_t)G * (i + 1) / nth);
         th.emplace_back(work, k0, k1);
     }
     for (auto& x : th) x.join();
+    if (R.iterate) {
+        t->gain.assign(t->gain_wide.begin() + M, t->gain_wide.begin() + 2 * M);
+        t->gw.resize(6 * (size_t)M);
+        for (uint32_t k = 0; k < 3 * M; ++k) {
+            t->gw[2 * k] = (float)t->gain_wide[k].real();
+            t->gw[2 * k + 1] = (float)t->gain_wide[k].imag();
+        }
+    }
     // device tables
     t->gT.assign((size_t)B * R.Mw4, 0.0f);
     for (uint32_t b = 0; b < B; ++b)
@@ -260,14 +279,17 @@ WsLayout workspace_layout(const Resolved& R) {
     l.jbits = take((size_t)R.L * wpl * 4);
     l.jlist = take((size_t)R.L * R.dK * 4);
     l.cand = take((size_t)R.cap * 4);
-    l.est = take((size_t)R.cap * 8);
-    l.keys = take((size_t)R.cap * 8);
+    const size_t nest = (size_t)R.cap + (R.iterate ? R.K : 0u);   // + the recovered coefficients
+    l.est = take(nest * 8);
+    l.keys = take(nest * 8);
     l.rpart = take((size_t)std::max<uint32_t>(R.resid_blocks, 1) * 16);
     l.resid_own = take(16);
     l.ctr = take(16);
     l.ubuf = take(R.fft_mode ? (size_t)R.L * R.B * 8 : 16);
     l.gmax = take(R.fft_mode ? (size_t)R.L * (R.B / 16) * 4 : 16);
     l.cbits = take((size_t)R.comb_loops * R.comb_words * 4);
+    l.rec_f = take(R.iterate ? (size_t)R.K * 4 : 16);
+    l.rec_v = take(R.iterate ? (size_t)R.K * 8 : 16);
     l.total = off;
     return l;
 }
@@ -290,6 +312,7 @@ TabLayout table_layout(const Resolved& R) {
     l.rou = take((size_t)16 << R.tb);
     l.ctau = take((size_t)R.comb_loops * 4);
     l.ctw = take((size_t)R.comb_b * 8);
+    l.gw = take(R.iterate ? (size_t)3 * R.M * 8 : 16);
     l.total = off;
     return l;
 }
@@ -313,6 +336,7 @@ std::vector<char> pack_tables(const Resolved& R, const HostTables& T) {
         memcpy(&h[tl.ctau], R.comb_tau.data(), (size_t)R.comb_loops * 4);
         memcpy(&h[tl.ctw], T.ctw.data(), T.ctw.size() * 4);
     }
+    if (R.iterate) memcpy(&h[tl.gw], T.gw.data(), T.gw.size() * 4);
     return h;
 }
 

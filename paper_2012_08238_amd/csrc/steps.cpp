@@ -18,7 +18,8 @@ size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // vote: 2 x kLmaxCount; finalize: kLmaxCount; residual: 1
     // + comb prefilter: one launch per comb size (2^1 .. 2^14)
-    const size_t launches = n + 2 * kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + 3 * kLmaxCount + 1;
+    // + subtraction round: subtraction 1, reselection kFftLog2Max, vote and finalize again
+    const size_t launches = n + 3 * kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + 6 * kLmaxCount + 2;
     return launches * (n + 1);
 }
 
@@ -61,17 +62,30 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
             });
     for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)
         add_step(kStepComb, lb, 0, [&](const Resolved& R) { return R.comb_loops && R.comb_log2b == lb ? R.comb_loops : 0u; });
-    for (uint32_t staged = 0; staged < 2; ++staged)
-        for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
-            auto in_group = [&](const Resolved& R) { return (R.vote_lds > 0) == (staged == 1) && R.lmax == lm; };
-            const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_lds; });
-            add_step(kStepVote, staged | (lm << 8), staged ? lds : 0,
-                     [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
+    // location and estimation; the subtraction round repeats them for the signals that iterate
+    for (uint32_t round = 0; round < 2; ++round) {
+        auto active = [&](const Resolved& R) { return round == 0 || R.iterate; };
+        if (round == 1) {
+            add_step(kStepSub, 0, max_of(active, [](const Resolved& R) { return R.sub_lds; }),
+                     [&](const Resolved& R) { return R.iterate ? R.L : 0u; });
+            for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)
+                add_step(kStepReselect, lb, 0, [&](const Resolved& R) { return R.iterate && R.log2B == lb ? R.L : 0u; });
         }
-    for (uint32_t lm = 4; lm <= 32; lm <<= 1)
-        add_step(kStepFin, lm,
-                 max_of([&](const Resolved& R) { return R.lmax == lm; }, [](const Resolved& R) { return R.fin_lds; }),
-                 [&](const Resolved& R) { return R.lmax == lm ? 1u : 0u; });
+        for (uint32_t staged = 0; staged < 2; ++staged)
+            for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
+                auto in_group = [&](const Resolved& R) {
+                    return active(R) && (R.vote_lds > 0) == (staged == 1) && R.lmax == lm;
+                };
+                const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_lds; });
+                add_step(kStepVote, staged | (lm << 8) | (round << 16), staged ? lds : 0,
+                         [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
+            }
+        for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
+            auto in_group = [&](const Resolved& R) { return active(R) && R.lmax == lm; };
+            add_step(kStepFin, lm | (round << 8), max_of(in_group, [](const Resolved& R) { return R.fin_lds; }),
+                     [&](const Resolved& R) { return in_group(R) ? 1u : 0u; });
+        }
+    }
     add_step(kStepRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
              [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
 }
@@ -90,8 +104,10 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
         switch (st.kind) {
             case kStepFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
             case kStepFft: e = launch_fft_select(a, st.param, st.units, s); break;
-            case kStepVote: e = launch_vote(a, st.param >> 8, st.units, st.lds, s); break;
-            case kStepFin: e = launch_finalize(a, st.param, st.units, st.lds, s); break;
+            case kStepVote: e = launch_vote(a, (st.param >> 8) & 255u, st.units, st.lds, st.param >> 16, s); break;
+            case kStepFin: e = launch_finalize(a, st.param & 255u, st.units, st.lds, st.param >> 8, s); break;
+            case kStepSub: e = launch_subtract(a, st.units, st.lds, s); break;
+            case kStepReselect: e = launch_reselect(a, st.param, st.units, s); break;
             case kStepRes: e = launch_residual(a, st.units, st.lds, s); break;
             case kStepFftLarge: e = launch_fft_large(a, st.param & 255u, st.param >> 8, st.units, s); break;
             case kStepComb: e = launch_comb(a, st.param, st.units, s); break;

@@ -57,6 +57,18 @@ def test_unsupported_large_B():
     assert t["gain"].shape[0] == 16
 
 
+def test_iterate_validation_and_gain():
+    # the subtraction round runs with the one-workgroup FFT only
+    with pytest.raises(S.SfftError) as e:
+        S.host_tables(S.PlanParams(N=1 << 20, K=100, B=1 << 15, L=5, w=1 << 17, flags=S.SFFT_FLAG_ITERATE))
+    assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+    # the round widens the gain table to three bucket widths; its middle is the plain table, bitwise
+    kw = dict(N=1 << 14, K=10, B=128, L=5, w=512, n_resid=8)
+    a = S.host_tables(S.PlanParams(**kw))
+    b = S.host_tables(S.PlanParams(flags=S.SFFT_FLAG_ITERATE, **kw))
+    assert np.array_equal(a["gain"], b["gain"])
+
+
 @pytest.mark.parametrize("N,K,B,L,w,seed", [
     (1 << 14, 10, 128, 5, 512, 0), (1 << 14, 10, 128, 5, 512, 12345),
     (1 << 20, 50, 1024, 7, 8192, 7), (1 << 12, 3, 64, 9, 256, 99)])
