@@ -205,6 +205,46 @@ def comb_measure(S, torch, dev, args) -> dict:
     return out
 
 
+def iterate_measure(S, torch, dev, args) -> dict:
+    """One subtraction round of the iterative framework on batches of resident
+    signals where the first recovery loses tones to shared buckets: N=2^22 with
+    K=1000 in B=16384 buckets (2K/B = 12%), the C2 shape (N=2^20, K=50, B=1024,
+    10%), and the benchmark shape (K=100, B=16384: the cost of the round where it
+    is rarely needed); each without and with the round: signals/s, tones missed
+    per signal (L0 against the planted support) and exact supports."""
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    shapes = [("n22_k1000_b16384", 1 << 22, 1000, 16384, 9), ("c2", 1 << 20, 50, 1024, 7),
+              ("n22_k100_b16384", 1 << 22, 100, 16384, 9)]
+    out = {}
+    m = args.iter_batch
+    for name, n, k, b, l in shapes:
+        sigs = [make_signal_torch(n, k, 20.0, derive_seed(90, i), dev) for i in range(m)]
+        xs = [q[0] for q in sigs]
+        row = {"N": n, "K": k, "B": b, "L": l, "w": 8 * b, "snr_db": 20.0, "batch": m}
+        for tag, fl in (("plain", 0), ("iterate", S.SFFT_FLAG_ITERATE)):
+            plan = S.Plan(n, k, b, l, 8 * b, seed=17, flags=fl)
+            bt = S.Batch([plan] * m, branches=args.branches)
+            outs = [plan.outputs(dev) for _ in range(m)]
+            for _ in range(2):
+                bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.iter_steps):
+                bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            missed = [len(set(q[1].tolist()) - set(o[0].cpu().numpy().tolist())) for o, q in zip(outs, sigs)]
+            row[tag] = {"signals_per_s": round(m * args.iter_steps / el, 1),
+                        "missed_per_signal": round(sum(missed) / m, 3),
+                        "exact_support": f"{sum(v == 0 for v in missed)}/{m}"}
+            bt.close()
+            plan.close()
+        out[name] = row
+        print(f"# subtraction round {name}: plain {row['plain']}, iterate {row['iterate']}", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -357,6 +397,8 @@ def main() -> int:
     ap.add_argument("--comb-batch", type=int, default=64, help="signals per batch of the comb prefilter runs (0 = skip)")
     ap.add_argument("--comb-steps", type=int, default=10)
     ap.add_argument("--mix-budget-gib", type=int, default=16)
+    ap.add_argument("--iter-batch", type=int, default=16, help="signals per batch of the subtraction-round runs (0 = skip)")
+    ap.add_argument("--iter-steps", type=int, default=5)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
@@ -468,6 +510,7 @@ def main() -> int:
               file=sys.stderr, flush=True)
     sweep = snr_sweep(S, torch, dev, args) if args.sweep_signals > 0 else None
     comb = comb_measure(S, torch, dev, args) if args.comb_batch > 0 else None
+    iterate = iterate_measure(S, torch, dev, args) if args.iter_batch > 0 else None
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -535,6 +578,7 @@ def main() -> int:
         "uneven_batch": uneven,
         "error_vs_snr": sweep,
         "comb_prefilter": comb,
+        "subtraction_round": iterate,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,

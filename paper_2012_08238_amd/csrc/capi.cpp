@@ -99,6 +99,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.vote_units = R.vote_units;
     d.vote_upl = R.vote_upl;
     d.resid_blocks = R.resid_blocks;
+    d.est_units = R.est_units;
     d.lmax = R.lmax;
     d.combine = (R.flags & SFFT_FLAG_MEAN_ESTIMATE) ? 1u : 0u;
     return d;
@@ -124,12 +125,14 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     }
     if (R.comb_loops) HIP_TRY(launch_comb(a, R.comb_log2b, R.comb_loops, s), "comb prefilter launch");
     HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 0, s), "vote launch");
-    HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, 0, s), "estimate launch");
+    HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 0, s), "estimate launch");
+    HIP_TRY(launch_finalize(a, 1, R.fin_lds, 0, s), "top-K launch");
     if (R.iterate) {
         HIP_TRY(launch_subtract(a, R.L, R.sub_lds, s), "subtraction launch");
         HIP_TRY(launch_reselect(a, R.log2B, R.L, s), "reselection launch");
         HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 1, s), "second vote launch");
-        HIP_TRY(launch_finalize(a, R.lmax, 1, R.fin_lds, 1, s), "second estimate launch");
+        HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 1, s), "second estimate launch");
+        HIP_TRY(launch_finalize(a, 1, R.fin_lds, 1, s), "second top-K launch");
     }
     if (R.S) HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
     return SFFT_OK;

@@ -61,6 +61,7 @@ struct SigDesc {
     uint32_t vote_units;        // vote workgroups
     uint32_t vote_upl;          // vote workgroups per enumerated loop (chunks of kVoteUnit candidates)
     uint32_t resid_blocks;      // residual workgroups
+    uint32_t est_units;         // estimation workgroups (striding over the candidates)
     uint32_t lmax;              // power of two >= L used by the median network
     uint32_t combine;           // 0: coordinate-wise median over the loops, 1: mean
     uint32_t comb_loops;        // comb prefilter loops (0 = off)

@@ -28,6 +28,7 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     extern __shared__ uint32_t sbits[];
     __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
     __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
+    __shared__ uint32_t s_scan[kVoteNT / 64 + 1];     // per-wave counts, then the reserved base
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
@@ -78,11 +79,13 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
         bits = sbits;
     }
     __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
     uint32_t* ctr = d.ctr;
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
     const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;   // first-round frequencies (ascending)
+    uint32_t fv[kVotePerThread];
+    uint32_t emask = 0;   // bit qq: candidate qq of this thread passes
+#pragma unroll
     for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
         const uint32_t ci = start + qq * kVoteNT + threadIdx.x;   // candidate index within loop r0
         bool emit = false;
@@ -110,16 +113,21 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
             }
             if (emit && n1) emit = !in_sorted(d.rec_f, n1, f);
         }
-        const uint64_t m = __ballot(emit);
-        if (m) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t base = 0;
-            if ((int)lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
-            base = __shfl(base, leader, 64);
-            if (emit) {
-                const uint32_t pos = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                if (pos < cap) gst(cand + pos, f);
-            }
+        fv[qq] = f;
+        emask |= (emit ? 1u : 0u) << qq;
+    }
+    // one reservation in the candidate list per workgroup (the list is unordered)
+    uint32_t total;
+    const uint32_t off = block_excl_scan<kVoteNT>((uint32_t)__popc(emask), s_scan, total);
+    if (total == 0) return;   // block-uniform
+    if (threadIdx.x == 0) s_scan[kVoteNT / 64] = atomicAdd(ctr, total);
+    __syncthreads();
+    uint32_t pos = s_scan[kVoteNT / 64] + off;
+#pragma unroll
+    for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+        if ((emask >> qq) & 1u) {
+            if (pos < cap) gst(cand + pos, fv[qq]);
+            ++pos;
         }
     }
 }
@@ -187,37 +195,36 @@ __device__ __forceinline__ void stage_rou(double2* dst, const double2* src, uint
 }
 
 
+// Number of candidates of a signal: the vote's list, plus (round 1) the first
+// round's frequencies.
+__device__ __forceinline__ uint32_t candidate_count(const __attribute__((address_space(4))) SigDesc& d,
+                                                    uint32_t round, uint32_t& nc) {
+    nc = min(gld(d.ctr), d.cap);
+    return nc + (round ? min(gld(d.ctr + 2), d.K) : 0u);
+}
+
 // For each f in I': e_r = uhat_r[h_r(f)] * e^{-2 pi i (tau_r f mod N)/N} / Gtab[o_r(f)]
 // (the energy-concentration estimate of the one frequency assumed in the
-// bucket), x'_f = median_r Re e_r + i median_r Im e_r; then the K largest |x'_f|^2
-// (ties -> lower f), returned in ascending f. One workgroup per signal.
-// Dynamic LDS: P values and P frequencies (P = 2^ceil(log2 K)).
-// With the subtraction round, round 0 keeps its K largest in the workspace
-// (rec_f, rec_v, count in ctr[2]) instead of the outputs; round 1 estimates the
-// new candidates from the residual buckets, adds the first round's
-// frequencies as candidates valued v + (combined residual estimate), and
-// writes the K largest of both to the outputs.
+// bucket), x'_f = median_r Re e_r + i median_r Im e_r (or the mean over r); the
+// estimate and its ordering key (-|x'_f|^2, then f) go to est/keys. In round 1
+// the new candidates are estimated from the residual buckets, and each first-
+// round frequency (appended after them) gets v + its combined residual estimate.
+// est_units workgroups per signal stride over the candidates.
 template <int LMAX>
-__global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t round) {
-    extern __shared__ f4v lds_raw[];
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t bc[4];
+__global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t round) {
     __shared__ uint32_t s_sig[kMaxL], s_tau[kMaxL], s_sinv[kMaxL];
     __shared__ double2 s_rou[kRouMax];
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
-    const IoDesc io = io_of(a, sig);
+    uint32_t nc;
+    const uint32_t n = candidate_count(d, round, nc);
+    if (unit * kFinNT >= n) return;   // block-uniform: no candidate for this workgroup
     const uint32_t fftm = d.fft_mode;
     const uint32_t mean = d.combine;
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
     const uint32_t rsh = d.log2N - d.tb;
     const double step = d.step;
-    uint32_t P = 1;
-    while (P < d.K) P <<= 1;
-    float2* s_v = reinterpret_cast<float2*>(lds_raw);
-    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + P);
-    if (threadIdx.x == 0) bc[3] = min(gld(d.ctr), d.cap);
     if (threadIdx.x < L) {
         s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
         s_tau[threadIdx.x] = gld(d.tau + threadIdx.x);
@@ -225,15 +232,14 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
     }
     stage_rou<kFinNT>(s_rou, d.rou, d.tb);
     __syncthreads();
-    const uint32_t nc = bc[3];   // block-uniform by construction
-    const uint32_t n = nc + (round ? min(gld(d.ctr + 2), d.K) : 0u);
     const uint32_t* cand = d.cand;
     const float2* invG = d.invG;
     const float2* uhat = d.uhat;
     const float2* tw = d.tw;
     float2* est = d.est;
     uint64_t* keys = d.keys;
-    for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
+    const uint32_t stride = d.est_units * kFinNT;
+    for (uint32_t i = unit * kFinNT + threadIdx.x; i < n; i += stride) {
         const bool rec = i >= nc;   // a first-round frequency (round 1)
         const uint32_t f = rec ? gld(d.rec_f + (i - nc)) : gld(cand + i);
         float re[LMAX], im[LMAX];
@@ -290,11 +296,35 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
         gst(est + i, make_float2(mr, mi));
         gst(keys + i, ((uint64_t)(0xFFFFFFFFu - __float_as_uint(mag)) << 32) | (uint64_t)f);
     }
-    __syncthreads();
+}
+
+// The K smallest keys of the estimates (the K largest |x'_f|^2, ties -> lower f),
+// returned in ascending f and padded with (-1, 0). The K-th smallest key comes
+// from a radix select over 8-bit digits from the top, which stops as soon as
+// every key with the selected prefix is needed. One workgroup per signal.
+// Dynamic LDS: P values and P frequencies (P = 2^ceil(log2 K)).
+// With the subtraction round, round 0 keeps its K largest in the workspace
+// (rec_f, rec_v, count in ctr[2]) instead of the outputs; round 1 writes the
+// outputs.
+__global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t round) {
+    extern __shared__ f4v lds_raw[];
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t bc[4];
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const IoDesc io = io_of(a, sig);
+    uint32_t P = 1;
+    while (P < d.K) P <<= 1;
+    float2* s_v = reinterpret_cast<float2*>(lds_raw);
+    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + P);
+    uint32_t nc;
+    const uint32_t n = candidate_count(d, round, nc);
+    const float2* est = d.est;
+    const uint64_t* keys = d.keys;
     const uint32_t K = d.K;
     uint64_t thr = ~0ull;
     if (n > K) {
-        // K-th smallest key (keys are unique: the low word is f)
         uint64_t prefix = 0, pmask = 0;
         uint32_t kk = K;
         const uint32_t lane = threadIdx.x & 63u;
@@ -314,30 +344,40 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
                 const uint32_t incl = wave_incl_scan(s);
                 const uint32_t excl = incl - s;
                 if (excl < kk && kk <= incl) {
-                    uint32_t acc = excl, dsel, rem;
+                    uint32_t acc = excl, dsel, rem, cnt;
                     if (acc + h0 >= kk) {
                         dsel = lo;
                         rem = kk - acc;
+                        cnt = h0;
                     } else if (acc += h0, acc + h1 >= kk) {
                         dsel = lo + 1;
                         rem = kk - acc;
+                        cnt = h1;
                     } else if (acc += h1, acc + h2 >= kk) {
                         dsel = lo + 2;
                         rem = kk - acc;
+                        cnt = h2;
                     } else {
                         acc += h2;
                         dsel = lo + 3;
                         rem = kk - acc;
+                        cnt = h3;
                     }
                     bc[0] = dsel;
                     bc[1] = rem;
+                    bc[2] = cnt;
                 }
             }
             __syncthreads();
             prefix |= (uint64_t)bc[0] << shift;
             pmask |= 255ull << shift;
             kk = bc[1];
+            const bool all_needed = bc[2] == kk;   // every key with this prefix is among the K
             __syncthreads();
+            if (all_needed) {
+                prefix |= ~pmask;   // the largest key with the prefix
+                break;
+            }
         }
         thr = prefix;
     }
@@ -591,15 +631,19 @@ hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds, uint32_t round,
-                           hipStream_t s) {
+hipError_t launch_estimate(const Launch& a, uint32_t lmax, uint32_t units, uint32_t round, hipStream_t s) {
     switch (lmax) {
-        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
-        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
-        case 16: hipLaunchKernelGGL(finalize_kernel<16>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
-        case 32: hipLaunchKernelGGL(finalize_kernel<32>, dim3(units), dim3(kFinNT), lds, s, a, round); break;
+        case 4: hipLaunchKernelGGL(estimate_kernel<4>, dim3(units), dim3(kFinNT), 0, s, a, round); break;
+        case 8: hipLaunchKernelGGL(estimate_kernel<8>, dim3(units), dim3(kFinNT), 0, s, a, round); break;
+        case 16: hipLaunchKernelGGL(estimate_kernel<16>, dim3(units), dim3(kFinNT), 0, s, a, round); break;
+        case 32: hipLaunchKernelGGL(estimate_kernel<32>, dim3(units), dim3(kFinNT), 0, s, a, round); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Launch& a, uint32_t units, uint32_t lds, uint32_t round, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(units), dim3(kFinNT), lds, s, a, round);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct Resolved {
     std::vector<uint32_t> sigma, sigma_inv, tau, tpos;
     // units per stage
     uint32_t fold_units, vote_units, vote_upl, resid_blocks, vote_lds, strip_lds, resid_lds, fin_lds;
+    uint32_t est_units;
     uint32_t xcd_order;
     uint32_t fold_variant;      // bucketization kernel variant (kernels.hpp fold_variant)
 };

@@ -23,12 +23,12 @@ hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint
 // round 1: the vote of the subtraction round (the first round's frequencies are excluded)
 hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
                        hipStream_t s);
-// one workgroup per signal; lmax in {4, 8, 16, 32} >= L of every signal of the launch
-// lds_bytes: K-sized output staging (Resolved::fin_lds / resid_lds)
-// round 0 of an iterating signal keeps its K largest in the workspace; round 1
-// adds the first round's coefficients to the candidates and writes the outputs
-hipError_t launch_finalize(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
-                           hipStream_t s);
+// estimates of the candidates: est_units workgroups per signal; lmax in {4, 8, 16, 32} >= L of
+// every signal of the launch; round 1 adds the first round's coefficients to the candidates
+hipError_t launch_estimate(const Launch& a, uint32_t lmax, uint32_t units, uint32_t round, hipStream_t s);
+// the K largest estimates: one workgroup per signal; lds_bytes = Resolved::fin_lds (max over the launch);
+// round 0 of an iterating signal keeps them in the workspace, otherwise they go to the outputs
+hipError_t launch_finalize(const Launch& a, uint32_t units, uint32_t lds_bytes, uint32_t round, hipStream_t s);
 // subtraction round: one workgroup per (signal, loop); lds_bytes = Resolved::sub_lds (max over the launch)
 hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // selection of the residual buckets: one workgroup per (signal, loop); every signal has B = 2^log2B <= 16384

@@ -153,6 +153,8 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies
     R.fin_lds = P * 8u + P * 4u;         // selected values, frequencies (sort size P)
     R.iterate = (p.flags & SFFT_FLAG_ITERATE) ? 1u : 0u;
+    // estimation: enough workgroups for the candidate capacity, at most 32 (they stride)
+    R.est_units = (uint32_t)std::min<uint64_t>(32u, ((uint64_t)R.cap + R.K * R.iterate + kFinNT - 1) / kFinNT);
     // subtraction round: phased values [K], sort keys [P], offsets [K], run starts [B] (16 bit)
     R.sub_lds = R.iterate ? ((R.K * 8u + P * 4u + R.K * 4u + R.B * 2u + 15u) & ~15u) : 0u;
     R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;

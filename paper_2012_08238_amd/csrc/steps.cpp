@@ -16,10 +16,11 @@ constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
 
 size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
-    // vote: 2 x kLmaxCount; finalize: kLmaxCount; residual: 1
-    // + comb prefilter: one launch per comb size (2^1 .. 2^14)
-    // + subtraction round: subtraction 1, reselection kFftLog2Max, vote and finalize again
-    const size_t launches = n + 3 * kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + 6 * kLmaxCount + 2;
+    // two-pass fft: 3 per size; comb prefilter: one per comb size (2^1 .. 2^14);
+    // per round: vote 2 x kLmaxCount, estimate kLmaxCount, top-K 1; subtraction 1,
+    // reselection kFftLog2Max; residual 1
+    const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + kFftLog2Max +
+                            2 * (3 * kLmaxCount + 1) + 1 + kFftLog2Max + 1;
     return launches * (n + 1);
 }
 
@@ -82,9 +83,10 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
             }
         for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
             auto in_group = [&](const Resolved& R) { return active(R) && R.lmax == lm; };
-            add_step(kStepFin, lm | (round << 8), max_of(in_group, [](const Resolved& R) { return R.fin_lds; }),
-                     [&](const Resolved& R) { return in_group(R) ? 1u : 0u; });
+            add_step(kStepEst, lm | (round << 8), 0, [&](const Resolved& R) { return in_group(R) ? R.est_units : 0u; });
         }
+        add_step(kStepFin, round, max_of(active, [](const Resolved& R) { return R.fin_lds; }),
+                 [&](const Resolved& R) { return active(R) ? 1u : 0u; });
     }
     add_step(kStepRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
              [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
@@ -105,7 +107,8 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
             case kStepFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
             case kStepFft: e = launch_fft_select(a, st.param, st.units, s); break;
             case kStepVote: e = launch_vote(a, (st.param >> 8) & 255u, st.units, st.lds, st.param >> 16, s); break;
-            case kStepFin: e = launch_finalize(a, st.param & 255u, st.units, st.lds, st.param >> 8, s); break;
+            case kStepEst: e = launch_estimate(a, st.param & 255u, st.units, st.param >> 8, s); break;
+            case kStepFin: e = launch_finalize(a, st.units, st.lds, st.param, s); break;
             case kStepSub: e = launch_subtract(a, st.units, st.lds, s); break;
             case kStepReselect: e = launch_reselect(a, st.param, st.units, s); break;
             case kStepRes: e = launch_residual(a, st.units, st.lds, s); break;
