@@ -284,6 +284,82 @@ def vote_counts(J_list, sigma, N: int, B: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Stage 2a': location by phase encoding (the sFFT3.0 row of Table 1; phase
+# encoding method of the location section). Loops come in pairs 2j, 2j+1 with
+# the same scaling and shifts tau and tau+1. Here a shift advances the time
+# index (y_i = x[sigma i + tau]), so one more sample multiplies a lone
+# frequency's bucket value by e^{+2 pi i f/N} and f = angle * N / (2 pi); the
+# paper writes the same relation with the opposite sign because its shift
+# operator delays and its root of unity is e^{-2 pi i/N}.
+# ---------------------------------------------------------------------------
+def pair_permutations(sigma, tau, N: int):
+    """Loop 2j+1 takes loop 2j's scaling and the next shift: sigma_{2j+1} =
+    sigma_{2j}, tau_{2j+1} = tau_{2j} + 1 mod N (the draws of the odd loops are
+    replaced)."""
+    sigma = np.array(sigma, dtype=np.int64, copy=True)
+    tau = np.array(tau, dtype=np.int64, copy=True)
+    sigma[1::2] = sigma[0::2]
+    tau[1::2] = (tau[0::2] + 1) % N
+    return sigma, tau
+
+
+def decode_phase(u0, u1, N: int):
+    """Frequency of a single-ton bucket from its values at shifts tau and tau+1:
+    t = angle(u1 conj(u0)) N / (2 pi) (the angle of u1/u0 in (-pi, pi]) and
+    f = floor(t + 1/2) mod N. Returns (f, t)."""
+    theta = np.angle(np.asarray(u1) * np.conj(np.asarray(u0)))
+    t = theta * N / (2.0 * math.pi)
+    f = np.floor(t + 0.5).astype(np.int64) % N
+    return f, t
+
+
+def phase_locate(uhat_list, J_list, sigma, N: int, B: int, T: int = 1):
+    """Candidates of the phase-encoding location: in pair j every selected
+    bucket h of loop 2j decodes a frequency f from loops 2j and 2j+1; it counts
+    for f when sigma_{2j} f hashes back to h (a single-ton bucket passes this
+    check, a multi-ton one in general does not). Frequencies counted by at
+    least T pairs are returned (mask over [0, N)), with every decode as
+    (pair, bucket, t, f, passed)."""
+    count = np.zeros(N, dtype=np.int64)
+    decodes = []
+    for j in range(len(uhat_list) // 2):
+        h = np.asarray(J_list[2 * j], dtype=np.int64)
+        f, t = decode_phase(uhat_list[2 * j][h], uhat_list[2 * j + 1][h], N)
+        ok = bucket_of((int(sigma[2 * j]) * f) % N, N, B) == h
+        np.add.at(count, f[ok], 1)
+        decodes.append((j, h, t, f, ok))
+    return count >= T, decodes
+
+
+def decoding_loops(I, uhat_list, J_list, sigma, N: int, B: int) -> np.ndarray:
+    """use[r, k]: loop r belongs to a pair that decodes frequency I[k] (the
+    bucket of sigma f is selected in the pair's first loop and decodes to f).
+    Phase-encoding location estimates each frequency from these loops only:
+    there its bucket is a single-ton."""
+    I = np.asarray(I, dtype=np.int64)
+    L = len(uhat_list)
+    use = np.zeros((L, I.shape[0]), dtype=bool)
+    for j in range(L // 2):
+        h = bucket_of((int(sigma[2 * j]) * I) % N, N, B)
+        chosen = np.zeros(B, dtype=bool)
+        chosen[np.asarray(J_list[2 * j], dtype=np.int64)] = True
+        f, _ = decode_phase(uhat_list[2 * j][h], uhat_list[2 * j + 1][h], N)
+        ok = chosen[h] & (f == I)
+        use[2 * j] = ok
+        use[2 * j + 1] = ok
+    return use
+
+
+def combine_masked(e: np.ndarray, use: np.ndarray, how: str) -> np.ndarray:
+    """Median (or mean) over r of e[r, k] restricted to use[r, k] (at least one)."""
+    out = np.empty(e.shape[1], dtype=np.complex128)
+    for k in range(e.shape[1]):
+        sub = e[use[:, k], k]
+        out[k] = median_combine(sub[:, None])[0] if how == "median" else sub.mean()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Stage 2b: estimation by energy concentration, median over bucketizations.
 # ---------------------------------------------------------------------------
 def loop_estimates(I, uhat_list, sigma, tau, G, N: int, B: int) -> np.ndarray:
@@ -415,7 +491,8 @@ def check_params(N, K, B, L, w, d=2):
 def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
          T: int | None = None, c_g: float = C_G, sigma=None, tau=None,
          n_resid: int = 4096, tpos=None, combine: str = "median",
-         comb_b: int = 0, comb_loops: int = 0, comb_keep: int = 0, iterate: bool = False) -> OracleResult:
+         comb_b: int = 0, comb_loops: int = 0, comb_keep: int = 0, iterate: bool = False,
+         location: str = "vote") -> OracleResult:
     """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout.
     combine: "median" (coordinate-wise, default) or "mean" of the loop estimates.
     comb_loops > 0 adds the comb prefilter: a frequency is a candidate only if
@@ -425,18 +502,31 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     coefficients are subtracted from every loop's buckets, the residual buckets
     are selected and voted again (frequencies already recovered excluded),
     new candidates are estimated from the residual, the recovered ones are
-    corrected by the median residual estimate, and the K largest are returned."""
+    corrected by the median residual estimate, and the K largest are returned.
+    location="phase" locates by phase encoding instead of voting: L is even,
+    loops 2j and 2j+1 share a scaling with shifts tau and tau+1, each selected
+    bucket of loop 2j decodes one frequency, and T (default 1) is the number of
+    pairs that must decode it; a located frequency is estimated from the loops
+    of the pairs that decoded it, and with iterate=True the recovered values
+    are kept while the residual is decoded for new frequencies."""
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     check_params(N, K, B, L, w, d)
+    phase = location == "phase"
+    if location not in ("vote", "phase"):
+        raise ValueError("location must be 'vote' or 'phase'")
+    if phase and L % 2:
+        raise ValueError("phase-encoding location needs an even number of loops")
     if T is None:
-        T = L // 2 + 1                       # strict majority of the L votes
+        T = 1 if phase else L // 2 + 1       # one decoding pair / strict majority of the L votes
     if sigma is None:
         sigma, tau, tp = draw_permutations(N, L, seed, n_resid)
         if tpos is None:
             tpos = tp
     sigma = np.asarray(sigma, dtype=np.int64)
     tau = np.asarray(tau, dtype=np.int64)
+    if phase:
+        sigma, tau = pair_permutations(sigma, tau, N)
     if tpos is None:
         tpos = np.zeros(0, dtype=np.int64)
     sigma_inv = np.array([modinv(s, N) for s in sigma], dtype=np.int64)
@@ -446,8 +536,13 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     uhat = [bucketize(x, g, int(sigma[r]), int(tau[r]), B) for r in range(L)]
     sel = [select_buckets(u, d * K) for u in uhat]
     J = [s[0] for s in sel]
-    counts = vote_counts(J, sigma, N, B)
-    voted = counts >= T
+    decodes = None
+    if phase:
+        voted, decodes = phase_locate(uhat, J, sigma, N, B, T)
+        counts = None
+    else:
+        counts = vote_counts(J, sigma, N, B)
+        voted = counts >= T
     cmask, cmargins, ctaus = None, [], np.zeros(0, dtype=np.int64)
     if comb_loops:
         ctaus = draw_comb_shifts(N, L, seed, n_resid, comb_loops)
@@ -456,7 +551,12 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     I = np.nonzero(voted)[0].astype(np.int64)
     e = loop_estimates(I, uhat, sigma, tau, G, N, B)
     comb = {"median": median_combine, "mean": mean_combine}[combine]
-    v = comb(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
+    use = None
+    if phase:
+        use = decoding_loops(I, uhat, J, sigma, N, B)
+        v = combine_masked(e, use, combine)
+    else:
+        v = comb(e) if I.shape[0] else np.zeros(0, dtype=np.complex128)
     idx, val, fmargin = finalize(I, v, K)
     it = {}
     if iterate:
@@ -466,22 +566,32 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
         ures = [subtract_recovered(uhat[r], K1, V1, int(sigma[r]), int(tau[r]), Gw, N, B) for r in range(L)]
         sel2 = [select_buckets(u, d * K) for u in ures]
         J2 = [s[0] for s in sel2]
-        voted2 = vote_counts(J2, sigma, N, B) >= T
+        decodes2 = None
+        if phase:
+            voted2, decodes2 = phase_locate(ures, J2, sigma, N, B, T)
+        else:
+            voted2 = vote_counts(J2, sigma, N, B) >= T
         if cmask is not None:
             voted2 &= cmask[np.arange(N, dtype=np.int64) % comb_b]
         voted2[K1] = False
         I2 = np.nonzero(voted2)[0].astype(np.int64)
         e2 = loop_estimates(I2, ures, sigma, tau, G, N, B)
-        v2 = comb(e2) if I2.shape[0] else np.zeros(0, dtype=np.complex128)
         eK = loop_estimates(K1, ures, sigma, tau, G, N, B)
-        vK = V1 + (comb(eK) if K1.shape[0] else 0)
+        if phase:
+            # new frequencies from the pairs that decode them in the residual; the
+            # recovered values (single-ton estimates) are kept
+            v2 = combine_masked(e2, decoding_loops(I2, ures, J2, sigma, N, B), combine)
+            vK = V1
+        else:
+            v2 = comb(e2) if I2.shape[0] else np.zeros(0, dtype=np.complex128)
+            vK = V1 + (comb(eK) if K1.shape[0] else 0)
         it = dict(idx1=idx, val1=val, final_margin1=fmargin, ures=ures, J2=J2,
-                  select_margin2=[s[1] for s in sel2], I2=I2, e2=e2, eK=eK)
+                  select_margin2=[s[1] for s in sel2], I2=I2, e2=e2, eK=eK, decodes2=decodes2)
         idx, val, fmargin = finalize(np.concatenate([I2, K1]), np.concatenate([v2, vK]), K)
     e_res, e_in = residual_energy(x, idx, val, tpos) if len(tpos) else (0.0, 0.0)
     trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,
                  J=J, select_margin=[s[1] for s in sel], counts=counts, I=I,
-                 e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos),
+                 e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos), decodes=decodes, use=use,
                  comb_mask=cmask, comb_margin=cmargins, comb_tau=ctaus, **it)
     return OracleResult(idx=idx, val=val, e_res=e_res, e_in=e_in, trace=trace)
 

@@ -349,6 +349,82 @@ def check_subtract_tone():
     assert list(r.idx) == list(sig.freqs) and abs(r.val[0] - sig.tones[0]) < 1e-9
 
 
+def check_decode_shift_library():
+    # the library FFT's shift theorem: advancing x by one sample multiplies xhat_f by
+    # e^{+2 pi i f/N}; decoding the two spectra at f returns f (wrap-around included)
+    N = 1 << 12
+    rng = np.random.default_rng(12)
+    for f in (0, 1, 7, N // 2 - 1, N // 2, N // 2 + 1, N - 1, 1234):
+        xh = np.zeros(N, dtype=np.complex128)
+        xh[f] = np.exp(1j * rng.uniform(0, 6.28))
+        x = np.fft.ifft(xh) * N
+        X0, X1 = np.fft.fft(x), np.fft.fft(np.roll(x, -1))
+        got, t = O.decode_phase(X0[f], X1[f], N)
+        assert int(got) == f and abs(t - round(t)) < 1e-9
+
+
+def check_pair_permutations():
+    sig, tau = O.pair_permutations([3, 99, 5, 7], [10, 20, 4095, 1], 4096)
+    assert sig.tolist() == [3, 3, 5, 5] and tau.tolist() == [10, 11, 4095, 0]
+
+
+def _bucket_bruteforce(x, g, sigma, tau, B, h):
+    # u_b = sum_{i = b mod B} g_i x[sigma i + tau]; uhat[h] = sum_b u_b e^{-2 pi i b h / B}
+    N = x.shape[0]
+    u = [0j] * B
+    for i in range(g.shape[0]):
+        u[i % B] += g[i] * x[(sigma * i + tau) % N]
+    return sum(u[b] * complex(math.cos(-2 * math.pi * b * h / B), math.sin(-2 * math.pi * b * h / B))
+               for b in range(B))
+
+
+def check_phase_locate_bruteforce():
+    # tiny signal, plain loops: every decode of the selected buckets and the pair counts
+    N, B, w, K = 256, 16, 128, 2
+    sig = make_signal(N, K, 30.0, seed=31)
+    g = O.flat_window(w, B)
+    sigma, tau, _ = O.draw_permutations(N, 4, 5)
+    sigma, tau = O.pair_permutations(sigma, tau, N)
+    uh = [O.bucketize(sig.x, g, int(sigma[r]), int(tau[r]), B) for r in range(4)]
+    J = [O.select_buckets(u, 2 * K)[0] for u in uh]
+    mask, _ = O.phase_locate(uh, J, sigma, N, B, 1)
+    count = {}
+    for j in range(2):
+        for h in J[2 * j]:
+            a = _bucket_bruteforce(sig.x, g, int(sigma[2 * j]), int(tau[2 * j]), B, int(h))
+            b = _bucket_bruteforce(sig.x, g, int(sigma[2 * j + 1]), int(tau[2 * j + 1]), B, int(h))
+            z = b * a.conjugate()
+            t = math.atan2(z.imag, z.real) * N / (2 * math.pi)
+            f = int(math.floor(t + 0.5)) % N
+            M = N // B
+            if ((sigma[2 * j] * f) % N + M // 2) // M % B == h:
+                count[f] = count.get(f, 0) + 1
+    assert sorted(np.nonzero(mask)[0].tolist()) == sorted(count)
+    assert set(sig.freqs.tolist()) <= set(count)
+
+
+def check_phase_exact_sparse():
+    # one noiseless tone: located by every pair, value exact
+    sig = make_signal(1 << 12, 1, None, seed=8)
+    r = O.sfft(sig.x, 1, 64, 4, 512, seed=3, n_resid=0, location="phase")
+    assert list(r.idx) == list(sig.freqs) and abs(r.val[0] - sig.tones[0]) < 1e-9
+    assert all(bool(d[4][0]) for d in r.trace["decodes"] if d[1][0] == O.bucket_of(
+        (int(r.trace["sigma"][2 * d[0]]) * int(sig.freqs[0])) % (1 << 12), 1 << 12, 64))
+    # exactly sparse, 2K/B = 31% (two pairs): the first round loses the tones that
+    # share a bucket in both pairs; the subtraction round finds them; located values
+    # are single-ton estimates (window leakage from neighbouring buckets only)
+    hits = [0, 0]
+    for s in range(12):
+        sig = make_signal(1 << 14, 20, None, seed=40 + s)
+        for i, it in enumerate((False, True)):
+            r = O.sfft(sig.x, 20, 128, 4, 1024, seed=s, n_resid=0, location="phase", iterate=it)
+            ok = set(r.idx.tolist()) == set(sig.freqs.tolist())
+            hits[i] += ok
+            if ok:
+                assert np.max(np.abs(r.val - sig.tones)) < 1e-2
+    assert hits[1] >= 8 and hits[0] <= 4
+
+
 def check_finalize():
     rng = np.random.default_rng(10)
     I = rng.choice(1000, 40, replace=False)
@@ -515,6 +591,26 @@ def _median_is_mean(e):
     return e.mean(axis=0)
 
 
+_GOOD_DECODE = O.decode_phase
+
+
+def _decode_wrong_sign(u0, u1, N):
+    return _GOOD_DECODE(u1, u0, N)
+
+
+def _decode_truncates(u0, u1, N):
+    f, t = _GOOD_DECODE(u0, u1, N)
+    return np.floor(t).astype(np.int64) % N, t
+
+
+def _pairs_same_shift(sigma, tau, N):
+    sigma = np.array(sigma, dtype=np.int64, copy=True)
+    tau = np.array(tau, dtype=np.int64, copy=True)
+    sigma[1::2] = sigma[0::2]
+    tau[1::2] = tau[0::2]
+    return sigma, tau
+
+
 MUTANTS = [
     ("bucket_of", _bucket_half_down),
     ("gain_table", _gain_wrong_sign),
@@ -522,10 +618,13 @@ MUTANTS = [
     ("loop_estimates", _estimates_wrong_phase),
     ("bucketize", _bucketize_transposed),
     ("median_combine", _median_is_mean),
+    ("decode_phase", _decode_wrong_sign),
+    ("decode_phase", _decode_truncates),
+    ("pair_permutations", _pairs_same_shift),
 ]
 
 
-@pytest.mark.parametrize("name,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
+@pytest.mark.parametrize("name,bad", MUTANTS, ids=[m[0] + "-" + m[1].__name__.strip("_") for m in MUTANTS])
 def test_planted_mistakes(monkeypatch, name, bad):
     monkeypatch.setattr(O, name, bad)
     failed = []
