@@ -76,6 +76,17 @@ typedef enum {
                                          residual buckets, each recovered value is corrected by the combined
                                          residual estimate, and the K largest of both are returned.
                                          Requires B <= 16384 (else SFFT_E_UNSUPPORTED). */
+#define SFFT_FLAG_PHASE_LOCATION 0x40u /* locate by phase encoding (the sFFT3.0 row of Table 1, phase
+                                         encoding method) instead of voting: L is even and loops 2j, 2j+1
+                                         form a pair with sigma_{2j+1} = sigma_{2j}, tau_{2j+1} = tau_{2j}+1
+                                         (the odd loops' draws are replaced; explicit sigma/tau must already
+                                         be paired). Each selected bucket h of loop 2j decodes
+                                         f = floor(angle(u_{2j+1}[h] conj(u_{2j}[h])) N/(2 pi) + 1/2) mod N,
+                                         kept when sigma_{2j} f hashes to h; a frequency decoded by at least T
+                                         pairs (vote_threshold, default 1, at most L/2) is a candidate and is
+                                         estimated from the loops of the pairs that decode it only. With
+                                         SFFT_FLAG_ITERATE the recovered values are kept and the residual is
+                                         decoded for new frequencies. Requires B <= 16384. */
 
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {

@@ -72,6 +72,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.rec_f = reinterpret_cast<uint32_t*>(ws + w.rec_f);
     d.rec_v = reinterpret_cast<float2*>(ws + w.rec_v);
     d.iterate = R.iterate;
+    d.phase = R.phase;
     d.comb_loops = R.comb_loops;
     d.comb_log2b = R.comb_log2b;
     d.comb_keep = R.comb_keep;
@@ -124,13 +125,19 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
         HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
     }
     if (R.comb_loops) HIP_TRY(launch_comb(a, R.comb_log2b, R.comb_loops, s), "comb prefilter launch");
-    HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 0, s), "vote launch");
+    if (R.phase)
+        HIP_TRY(launch_decode(a, R.vote_units, 0, s), "phase decode launch");
+    else
+        HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 0, s), "vote launch");
     HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 0, s), "estimate launch");
     HIP_TRY(launch_finalize(a, 1, R.fin_lds, 0, s), "top-K launch");
     if (R.iterate) {
         HIP_TRY(launch_subtract(a, R.L, R.sub_lds, s), "subtraction launch");
         HIP_TRY(launch_reselect(a, R.log2B, R.L, s), "reselection launch");
-        HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 1, s), "second vote launch");
+        if (R.phase)
+            HIP_TRY(launch_decode(a, R.vote_units, 1, s), "second phase decode launch");
+        else
+            HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_lds, 1, s), "second vote launch");
         HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 1, s), "second estimate launch");
         HIP_TRY(launch_finalize(a, 1, R.fin_lds, 1, s), "second top-K launch");
     }

@@ -68,6 +68,7 @@ struct SigDesc {
     uint32_t comb_log2b;        // log2 Bc
     uint32_t comb_keep;         // residues kept per comb loop
     uint32_t iterate;           // 1: one subtraction round after the first recovery
+    uint32_t phase;             // 1: location by phase encoding over loop pairs (2j, 2j+1)
 };
 
 // Per-signal caller buffers of one execution.
@@ -99,6 +100,8 @@ constexpr uint32_t kFftNT = 256;
 constexpr uint32_t kFinNT = 256;
 constexpr uint32_t kResNT = 256;
 constexpr uint32_t kSubNT = 256;
+constexpr uint32_t kDecPerThread = 4;                     // decoded buckets per thread
+constexpr uint32_t kDecUnit = kVoteNT * kDecPerThread;    // decoded buckets per workgroup
 constexpr uint32_t kStripLdsBytes = 65536;  // strip tile budget
 
 }  // namespace sfft

@@ -132,6 +132,110 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     }
 }
 
+// ---------------------------------------------------------------- phase-encoding location
+// Frequency decoded from bucket h of pair j (loops 2j and 2j+1, shifts tau and
+// tau+1): the lone frequency of a single-ton bucket turns its value by
+// e^{+2 pi i f/N} per sample of shift, so f = floor(t + 1/2) mod N with
+// t = angle(u_{2j+1}[h] conj(u_{2j}[h])) N / (2 pi) (FP64 from the float buckets).
+__device__ __forceinline__ uint32_t decode_bucket(const float2* uhat, uint32_t B, uint32_t j, uint32_t h,
+                                                  uint32_t N) {
+    const float2 a = gld(uhat + (size_t)(2u * j) * B + h);
+    const float2 b = gld(uhat + (size_t)(2u * j + 1u) * B + h);
+    const double re = (double)b.x * (double)a.x + (double)b.y * (double)a.y;
+    const double im = (double)b.y * (double)a.x - (double)b.x * (double)a.y;
+    const double t = atan2(im, re) * (double)N / 6.283185307179586;
+    return (uint32_t)(int64_t)floor(t + 0.5) & (N - 1u);
+}
+
+// Whether pair j locates f: the bucket h of sigma_{2j} f is selected in loop 2j
+// and decodes to f.
+__device__ __forceinline__ bool pair_decodes(const __attribute__((address_space(4))) SigDesc& d, uint32_t sg,
+                                             uint32_t j, uint32_t f) {
+    const uint32_t B = d.B, M = d.M, wpl = (B + 31u) >> 5;
+    const uint32_t h = ((((sg * f) & d.maskN) + (M >> 1)) >> d.log2M) & (B - 1u);
+    if (!((gld(d.jbits + (size_t)(2u * j) * wpl + (h >> 5)) >> (h & 31u)) & 1u)) return false;
+    return decode_bucket(d.uhat, B, j, h, d.N) == f;
+}
+
+// Phase-encoding location (sFFT3.0 row of Table 1): every selected bucket of the
+// first loop of every pair decodes one frequency; it is a candidate when its
+// bucket hash matches (single-ton check), at least T pairs decode it, it is
+// counted from the first pair that does (no duplicates), the comb prefilter (if
+// any) keeps its residue, and (round 1) it was not recovered before. One thread
+// per (pair, selected bucket), kDecPerThread per thread; one list reservation
+// per workgroup.
+__global__ __launch_bounds__(kVoteNT) void decode_kernel(Launch a, uint32_t round) {
+    __shared__ uint32_t s_comb[kMaxCombB / 32];
+    __shared__ uint32_t s_scan[kVoteNT / 64 + 1];
+    __shared__ uint32_t s_sig[kMaxL / 2];
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const uint32_t np = d.L >> 1, dK = d.dK, B = d.B, M = d.M, log2M = d.log2M, maskN = d.maskN;
+    if (threadIdx.x < np) s_sig[threadIdx.x] = gld(d.sigma + 2u * threadIdx.x);
+    const uint32_t ncomb = d.comb_loops, cmask = (1u << d.comb_log2b) - 1u;
+    if (ncomb) {
+        const uint32_t cw = max(1u, (cmask + 1u) >> 5);
+        for (uint32_t i = threadIdx.x; i < cw; i += kVoteNT) {
+            uint32_t v = 0;
+            for (uint32_t c = 0; c < ncomb; ++c) v |= gld(d.cbits + c * cw + i);
+            s_comb[i] = v;
+        }
+    }
+    __syncthreads();
+    uint32_t* ctr = d.ctr;
+    const uint32_t cap = d.cap, T = d.T, total_in = np * dK;
+    const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;
+    uint32_t fv[kDecPerThread];
+    uint32_t emask = 0;
+#pragma unroll
+    for (uint32_t qq = 0; qq < kDecPerThread; ++qq) {
+        const uint32_t idx = unit * kDecUnit + qq * kVoteNT + threadIdx.x;
+        bool emit = false;
+        uint32_t f = 0;
+        if (idx < total_in) {
+            const uint32_t j = idx / dK;
+            const uint32_t h = gld(d.jlist + (size_t)(2u * j) * dK + (idx - j * dK));
+            f = decode_bucket(d.uhat, B, j, h, d.N);
+            emit = ((((s_sig[j] * f) & maskN) + (M >> 1)) >> log2M & (B - 1u)) == h;
+            if (emit) {
+                uint32_t cnt = 1;
+                for (uint32_t jj = 0; jj < np; ++jj) {
+                    if (jj == j) continue;
+                    if (pair_decodes(d, s_sig[jj], jj, f)) {
+                        if (jj < j) {   // counted from an earlier pair
+                            emit = false;
+                            break;
+                        }
+                        ++cnt;
+                    }
+                }
+                emit = emit && cnt >= T;
+            }
+            if (emit && ncomb) {
+                const uint32_t res = f & cmask;
+                emit = (s_comb[res >> 5] >> (res & 31u)) & 1u;
+            }
+            if (emit && n1) emit = !in_sorted(d.rec_f, n1, f);
+        }
+        fv[qq] = f;
+        emask |= (emit ? 1u : 0u) << qq;
+    }
+    uint32_t total;
+    const uint32_t off = block_excl_scan<kVoteNT>((uint32_t)__popc(emask), s_scan, total);
+    if (total == 0) return;   // block-uniform
+    if (threadIdx.x == 0) s_scan[kVoteNT / 64] = atomicAdd(ctr, total);
+    __syncthreads();
+    uint32_t pos = s_scan[kVoteNT / 64] + off;
+#pragma unroll
+    for (uint32_t qq = 0; qq < kDecPerThread; ++qq) {
+        if ((emask >> qq) & 1u) {
+            if (pos < cap) gst(d.cand + pos, fv[qq]);
+            ++pos;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- estimation + output
 template <int N>
 __device__ __forceinline__ void sort_net(float* v) {
@@ -239,15 +343,32 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
     float2* est = d.est;
     uint64_t* keys = d.keys;
     const uint32_t stride = d.est_units * kFinNT;
+    const uint32_t phase = d.phase;
     for (uint32_t i = unit * kFinNT + threadIdx.x; i < n; i += stride) {
         const bool rec = i >= nc;   // a first-round frequency (round 1)
         const uint32_t f = rec ? gld(d.rec_f + (i - nc)) : gld(cand + i);
+        if (rec && phase) {
+            // phase location keeps the recovered single-ton estimates
+            const float2 v0 = gld(d.rec_v + (i - nc));
+            const float mag = fmaf(v0.x, v0.x, v0.y * v0.y);
+            gst(est + i, v0);
+            gst(keys + i, ((uint64_t)(0xFFFFFFFFu - __float_as_uint(mag)) << 32) | (uint64_t)f);
+            continue;
+        }
+        // loops that estimate f: all, or (phase location) those of the pairs that decode it
+        uint32_t use = (L >= 32u) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+        if (phase) {
+            use = 0;
+            for (uint32_t j = 0; j < (L >> 1); ++j)
+                if (pair_decodes(d, s_sig[2u * j], j, f)) use |= 3u << (2u * j);
+        }
+        const uint32_t m = (uint32_t)__popc(use);
         float re[LMAX], im[LMAX];
 #pragma unroll
         for (int r = 0; r < LMAX; ++r) {
             re[r] = __builtin_inff();
             im[r] = __builtin_inff();
-            if ((uint32_t)r < L) {
+            if ((uint32_t)r < L && ((use >> r) & 1u)) {
                 const uint32_t p = (s_sig[r] * f) & maskN;
                 const uint32_t h = ((p + (M >> 1)) >> log2M) & (B - 1u);
                 const uint32_t o = (p - (h << log2M) + (N >> 1)) & maskN;   // o + N/2
@@ -276,16 +397,16 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
             float sr = 0.f, si = 0.f;
 #pragma unroll
             for (int r = 0; r < LMAX; ++r) {
-                if ((uint32_t)r < L) {
+                if ((uint32_t)r < L && ((use >> r) & 1u)) {
                     sr += re[r];
                     si += im[r];
                 }
             }
-            mr = sr / (float)L;
-            mi = si / (float)L;
+            mr = sr / (float)m;
+            mi = si / (float)m;
         } else {
-            mr = median_of<LMAX>(re, L);
-            mi = median_of<LMAX>(im, L);
+            mr = median_of<LMAX>(re, m);
+            mi = median_of<LMAX>(im, m);
         }
         if (rec) {
             const float2 v0 = gld(d.rec_v + (i - nc));
@@ -628,6 +749,11 @@ hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t 
         case 32: hipLaunchKernelGGL(vote_kernel<32>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const Launch& a, uint32_t units, uint32_t round, hipStream_t s) {
+    hipLaunchKernelGGL(decode_kernel, dim3(units), dim3(kVoteNT), 0, s, a, round);
     return hipGetLastError();
 }
 

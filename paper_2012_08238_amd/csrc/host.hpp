@@ -23,6 +23,7 @@ struct Resolved {
     uint32_t fft_mode;          // 0 one-workgroup FFT (B <= 16384), 1 two-pass FFT
     uint32_t comb_b, comb_log2b, comb_loops, comb_keep, comb_words;  // comb prefilter
     uint32_t iterate, sub_lds;  // one subtraction round (iterative framework); its LDS bytes
+    uint32_t phase;             // location by phase encoding over loop pairs
     std::vector<uint32_t> comb_tau;
     uint32_t fft_p1_units, fft_p2_units;   // two-pass FFT workgroups per signal
     uint64_t seed;

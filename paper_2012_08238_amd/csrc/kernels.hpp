@@ -23,6 +23,9 @@ hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint
 // round 1: the vote of the subtraction round (the first round's frequencies are excluded)
 hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
                        hipStream_t s);
+// phase-encoding location: kDecUnit selected buckets per workgroup; round 1 excludes the first round's
+// frequencies
+hipError_t launch_decode(const Launch& a, uint32_t units, uint32_t round, hipStream_t s);
 // estimates of the candidates: est_units workgroups per signal; lmax in {4, 8, 16, 32} >= L of
 // every signal of the launch; round 1 adds the first round's coefficients to the candidates
 hipError_t launch_estimate(const Launch& a, uint32_t lmax, uint32_t units, uint32_t round, hipStream_t s);

@@ -28,8 +28,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     if (p.d < 1 || (int64_t)p.d * p.K > p.B) return bad("need 1 <= d*K <= B");
     if (p.L < 1 || p.L > kMaxL) return bad("L must be in [1, 32]");
     if (p.w < 2 || p.w > p.N || (p.w & 1)) return bad("w must be even and in [2, N]");
-    const int32_t T = p.vote_threshold ? p.vote_threshold : p.L / 2 + 1;
-    if (T < 1 || T > p.L) return bad("vote threshold must be in [1, L]");
+    const bool phase = (p.flags & SFFT_FLAG_PHASE_LOCATION) != 0;
+    if (phase && (p.L & 1)) return bad("phase-encoding location needs an even L");
+    const int32_t T = p.vote_threshold ? p.vote_threshold : (phase ? 1 : p.L / 2 + 1);
+    if (T < 1 || T > (phase ? p.L / 2 : p.L)) return bad("vote threshold must be in [1, L] (phase location: [1, L/2])");
     if (p.n_resid < 0 || p.n_resid > (1 << 24)) return bad("n_resid must be in [0, 2^24]");
     if (p.gauss_c < 0 || !isfinite(p.gauss_c)) return bad("gauss_c must be >= 0 and finite");
     if ((p.sigma == nullptr) != (p.tau == nullptr)) return bad("sigma and tau must be given together");
@@ -48,6 +50,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     }
     if ((p.flags & SFFT_FLAG_ITERATE) && p.B > kMaxFftLds) {
         *err = "the subtraction round needs B <= 16384";
+        return SFFT_E_UNSUPPORTED;
+    }
+    if (phase && p.B > kMaxFftLds) {
+        *err = "phase-encoding location needs B <= 16384";
         return SFFT_E_UNSUPPORTED;
     }
     R.N = (uint32_t)p.N;
@@ -73,7 +79,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     uint32_t lm = 4;
     while (lm < R.L) lm <<= 1;
     R.lmax = lm;
-    const uint64_t cap = (uint64_t)(R.L - R.T + 1) * R.dK * R.M;
+    R.phase = phase ? 1u : 0u;
+    // candidates: every enumerated frequency of loops 0..L-T (votes), one per
+    // selected bucket of the first loop of each pair (phase decoding)
+    const uint64_t cap = phase ? (uint64_t)(R.L / 2) * R.dK : (uint64_t)(R.L - R.T + 1) * R.dK * R.M;
     if (cap >= (1ull << 31)) {
         *err = "candidate capacity (L-T+1)*d*K*N/B exceeds 2^31";
         return SFFT_E_UNSUPPORTED;
@@ -103,8 +112,16 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         for (uint32_t r = 0; r < R.L; ++r) {
             if (!(p.sigma[r] & 1u) || p.sigma[r] >= R.N || p.tau[r] >= R.N)
                 return bad("explicit sigma must be odd and < N, tau < N");
+            if (phase && (r & 1) && (p.sigma[r] != p.sigma[r - 1] || p.tau[r] != ((p.tau[r - 1] + 1u) & (R.N - 1))))
+                return bad("phase location: explicit loops 2j+1 must repeat sigma_{2j} with tau_{2j}+1");
             R.sigma[r] = p.sigma[r];
             R.tau[r] = p.tau[r];
+        }
+    } else if (phase) {
+        // pairs (2j, 2j+1): same scaling, shifts tau and tau+1 (the odd draws are replaced)
+        for (uint32_t r = 1; r < R.L; r += 2) {
+            R.sigma[r] = R.sigma[r - 1];
+            R.tau[r] = (R.tau[r - 1] + 1u) & (R.N - 1);
         }
     }
     for (uint32_t r = 0; r < R.L; ++r)
@@ -135,7 +152,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.fold_units = R.mode ? R.B / C : (R.L * R.B + kFoldNT - 1) / kFoldNT;
     // vote workgroups: chunks of kVoteUnit candidates that never straddle two loops
     R.vote_upl = (R.dK * R.M + kVoteUnit - 1) / kVoteUnit;
-    R.vote_units = (R.L - R.T + 1) * R.vote_upl;
+    R.vote_units = phase ? (R.L / 2 * R.dK + kDecUnit - 1) / kDecUnit : (R.L - R.T + 1) * R.vote_upl;
     const uint32_t wpl = (R.B + 31) / 32;
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
     R.vote_lds = vbytes <= 65536u ? vbytes : 0u;

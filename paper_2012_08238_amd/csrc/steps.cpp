@@ -17,10 +17,10 @@ constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
 size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // two-pass fft: 3 per size; comb prefilter: one per comb size (2^1 .. 2^14);
-    // per round: vote 2 x kLmaxCount, estimate kLmaxCount, top-K 1; subtraction 1,
-    // reselection kFftLog2Max; residual 1
+    // per round: vote 2 x kLmaxCount, phase decode 1, estimate kLmaxCount, top-K 1;
+    // subtraction 1, reselection kFftLog2Max; residual 1
     const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + kFftLog2Max +
-                            2 * (3 * kLmaxCount + 1) + 1 + kFftLog2Max + 1;
+                            2 * (3 * kLmaxCount + 2) + 1 + kFftLog2Max + 1;
     return launches * (n + 1);
 }
 
@@ -75,12 +75,13 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
         for (uint32_t staged = 0; staged < 2; ++staged)
             for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
                 auto in_group = [&](const Resolved& R) {
-                    return active(R) && (R.vote_lds > 0) == (staged == 1) && R.lmax == lm;
+                    return active(R) && !R.phase && (R.vote_lds > 0) == (staged == 1) && R.lmax == lm;
                 };
                 const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_lds; });
                 add_step(kStepVote, staged | (lm << 8) | (round << 16), staged ? lds : 0,
                          [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
             }
+        add_step(kStepDecode, round, 0, [&](const Resolved& R) { return active(R) && R.phase ? R.vote_units : 0u; });
         for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
             auto in_group = [&](const Resolved& R) { return active(R) && R.lmax == lm; };
             add_step(kStepEst, lm | (round << 8), 0, [&](const Resolved& R) { return in_group(R) ? R.est_units : 0u; });
@@ -107,6 +108,7 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
             case kStepFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
             case kStepFft: e = launch_fft_select(a, st.param, st.units, s); break;
             case kStepVote: e = launch_vote(a, (st.param >> 8) & 255u, st.units, st.lds, st.param >> 16, s); break;
+            case kStepDecode: e = launch_decode(a, st.units, st.param, s); break;
             case kStepEst: e = launch_estimate(a, st.param & 255u, st.units, st.param >> 8, s); break;
             case kStepFin: e = launch_finalize(a, st.units, st.lds, st.param, s); break;
             case kStepSub: e = launch_subtract(a, st.units, st.lds, s); break;

@@ -57,6 +57,26 @@ def test_unsupported_large_B():
     assert t["gain"].shape[0] == 16
 
 
+def test_phase_location_pairs_and_validation():
+    N, L, seed = 1 << 14, 6, 21
+    t = S.host_tables(S.PlanParams(N, 10, 128, L, 512, seed=seed, n_resid=64, flags=S.SFFT_FLAG_PHASE_LOCATION))
+    sigma, tau, tpos = O.draw_permutations(N, L, seed, 64)
+    ps, pt = O.pair_permutations(sigma, tau, N)
+    assert np.array_equal(t["sigma"], ps.astype(np.uint32)) and np.array_equal(t["tau"], pt.astype(np.uint32))
+    assert np.array_equal(t["tpos"], tpos.astype(np.uint32))
+    kw = dict(N=N, K=10, B=128, w=512, flags=S.SFFT_FLAG_PHASE_LOCATION)
+    for bad in (dict(L=5), dict(L=4, vote_threshold=3)):
+        with pytest.raises(S.SfftError) as e:
+            S.host_tables(S.PlanParams(**kw, **bad))
+        assert e.value.status == _capi.SFFT_E_INVALID
+    with pytest.raises(S.SfftError) as e:   # explicit loops must already be paired
+        S.host_tables(S.PlanParams(**kw, L=2, sigma=np.array([3, 5], np.uint32), tau=np.array([1, 2], np.uint32)))
+    S.host_tables(S.PlanParams(**kw, L=2, sigma=np.array([3, 3], np.uint32), tau=np.array([N - 1, 0], np.uint32)))
+    with pytest.raises(S.SfftError) as e:
+        S.host_tables(S.PlanParams(N=1 << 20, K=10, B=1 << 15, L=4, w=1 << 18, flags=S.SFFT_FLAG_PHASE_LOCATION))
+    assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+
+
 def test_iterate_validation_and_gain():
     # the subtraction round runs with the one-workgroup FFT only
     with pytest.raises(S.SfftError) as e:
