@@ -245,6 +245,48 @@ def iterate_measure(S, torch, dev, args) -> dict:
     return out
 
 
+def phase_measure(S, torch, dev, args) -> dict:
+    """Phase-encoding location (the sFFT3.0 row) against voting on exactly sparse
+    signals, N=2^22, K=100, w=8B, batches of resident signals: voting with the
+    benchmark plan (B=16384, L=9) and phase location with two pairs (L=4) at
+    B=16384 and B=4096, with and without the subtraction round: signals/s,
+    exact supports and the largest value error against the planted tones."""
+    import numpy as np
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    n, k = 1 << 22, 100
+    m = args.phase_batch
+    sigs = [make_signal_torch(n, k, None, derive_seed(110, i), dev) for i in range(m)]
+    xs = [q[0] for q in sigs]
+    P, I = S.SFFT_FLAG_PHASE_LOCATION, S.SFFT_FLAG_ITERATE
+    runs = [("vote_b16384_L9", 16384, 9, 0), ("phase_b16384_L4", 16384, 4, P), ("phase_b16384_L4+iterate", 16384, 4, P | I),
+            ("phase_b4096_L4", 4096, 4, P), ("phase_b4096_L4+iterate", 4096, 4, P | I)]
+    out = {"N": n, "K": k, "snr_db": None, "batch": m}
+    for name, b, l, fl in runs:
+        plan = S.Plan(n, k, b, l, 8 * b, seed=19, flags=fl)
+        bt = S.Batch([plan] * m, branches=args.branches)
+        outs = [plan.outputs(dev) for _ in range(m)]
+        for _ in range(2):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.phase_steps):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        exact, verr = 0, 0.0
+        for o, q in zip(outs, sigs):
+            gi, gv = o[0].cpu().numpy(), o[1].cpu().numpy()
+            if set(gi.tolist()) == set(q[1].tolist()):
+                exact += 1
+                verr = max(verr, float(np.max(np.abs(gv - q[2][np.searchsorted(q[1], gi)]))))
+        out[name] = {"B": b, "L": l, "signals_per_s": round(m * args.phase_steps / el, 1),
+                     "exact_support": f"{exact}/{m}", "max_value_err_exact": verr}
+        bt.close()
+        plan.close()
+        print(f"# phase location {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -399,6 +441,8 @@ def main() -> int:
     ap.add_argument("--mix-budget-gib", type=int, default=16)
     ap.add_argument("--iter-batch", type=int, default=16, help="signals per batch of the subtraction-round runs (0 = skip)")
     ap.add_argument("--iter-steps", type=int, default=5)
+    ap.add_argument("--phase-batch", type=int, default=64, help="signals per batch of the phase-location runs (0 = skip)")
+    ap.add_argument("--phase-steps", type=int, default=10)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
@@ -511,6 +555,7 @@ def main() -> int:
     sweep = snr_sweep(S, torch, dev, args) if args.sweep_signals > 0 else None
     comb = comb_measure(S, torch, dev, args) if args.comb_batch > 0 else None
     iterate = iterate_measure(S, torch, dev, args) if args.iter_batch > 0 else None
+    phase = phase_measure(S, torch, dev, args) if args.phase_batch > 0 else None
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -579,6 +624,7 @@ def main() -> int:
         "error_vs_snr": sweep,
         "comb_prefilter": comb,
         "subtraction_round": iterate,
+        "phase_location": phase,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,
