@@ -81,6 +81,17 @@ def draw_comb_shifts(N: int, L: int, seed: int, n_resid: int, n_comb: int) -> np
     return np.array([draws[2 * L + n_resid + c] & (N - 1) for c in range(n_comb)], dtype=np.int64)
 
 
+def draw_est_permutations(N: int, L: int, seed: int, n_resid: int, n_comb: int, L_est: int):
+    """Scalings and shifts of the estimation-only loops: the next 2 L_est outputs
+    of the same SplitMix64 stream (sigma, tau alternating), after the permutation
+    draws, the residual positions and the comb shifts."""
+    base = 2 * L + n_resid + n_comb
+    draws = splitmix64(seed, base + 2 * L_est)
+    sigma = np.array([(draws[base + 2 * r] & (N - 1)) | 1 for r in range(L_est)], dtype=np.int64)
+    tau = np.array([draws[base + 2 * r + 1] & (N - 1) for r in range(L_est)], dtype=np.int64)
+    return sigma, tau
+
+
 def modinv(sigma: int, N: int) -> int:
     """sigma^{-1} mod N (sigma odd, N a power of two)."""
     return pow(int(sigma), -1, int(N))
@@ -492,7 +503,7 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
          T: int | None = None, c_g: float = C_G, sigma=None, tau=None,
          n_resid: int = 4096, tpos=None, combine: str = "median",
          comb_b: int = 0, comb_loops: int = 0, comb_keep: int = 0, iterate: bool = False,
-         location: str = "vote") -> OracleResult:
+         location: str = "vote", est_loops: int = 0, est_B: int = 0, est_w: int = 0) -> OracleResult:
     """Flat-window voting sFFT of signal x (length N = 2^m), FP64 throughout.
     combine: "median" (coordinate-wise, default) or "mean" of the loop estimates.
     comb_loops > 0 adds the comb prefilter: a frequency is a candidate only if
@@ -508,7 +519,11 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     bucket of loop 2j decodes one frequency, and T (default 1) is the number of
     pairs that must decode it; a located frequency is estimated from the loops
     of the pairs that decoded it, and with iterate=True the recovered values
-    are kept while the residual is decoded for new frequencies."""
+    are kept while the residual is decoded for new frequencies.
+    est_loops > 0 adds loops that only estimate (location and estimation loops
+    separated): est_loops more random bucketizations with est_B buckets and a
+    flat window of est_w samples (default w est_B / B); every located frequency
+    is estimated by the median (or mean) over all L + est_loops loops."""
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     check_params(N, K, B, L, w, d)
@@ -550,6 +565,19 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
         voted &= cmask[np.arange(N, dtype=np.int64) % comb_b]
     I = np.nonzero(voted)[0].astype(np.int64)
     e = loop_estimates(I, uhat, sigma, tau, G, N, B)
+    est = {}
+    if est_loops:
+        if phase or iterate:
+            raise ValueError("estimation-only loops combine with voting location and one round only")
+        Bx = est_B
+        wx = est_w or w * Bx // B
+        check_params(N, K, Bx, est_loops, wx, 1)
+        sx, tx = draw_est_permutations(N, L, seed, n_resid, comb_loops, est_loops)
+        gx = flat_window(wx, Bx, c_g)
+        Gx = gain_table(gx, N, Bx)
+        ux = [bucketize(x, gx, int(sx[r]), int(tx[r]), Bx) for r in range(est_loops)]
+        e = np.vstack([e, loop_estimates(I, ux, sx, tx, Gx, N, Bx)])
+        est = dict(est_sigma=sx, est_tau=tx, est_uhat=ux)
     comb = {"median": median_combine, "mean": mean_combine}[combine]
     use = None
     if phase:
@@ -592,7 +620,7 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,
                  J=J, select_margin=[s[1] for s in sel], counts=counts, I=I,
                  e=e, v=v, final_margin=fmargin, T=T, tpos=np.asarray(tpos), decodes=decodes, use=use,
-                 comb_mask=cmask, comb_margin=cmargins, comb_tau=ctaus, **it)
+                 comb_mask=cmask, comb_margin=cmargins, comb_tau=ctaus, **it, **est)
     return OracleResult(idx=idx, val=val, e_res=e_res, e_in=e_in, trace=trace)
 
 

@@ -425,6 +425,39 @@ def check_phase_exact_sparse():
     assert hits[1] >= 8 and hits[0] <= 4
 
 
+def check_est_loops():
+    # a lone tone: every estimation-only loop (its own B and window) returns the tone exactly
+    N = 1 << 12
+    sig = make_signal(N, 1, None, seed=17)
+    r = O.sfft(sig.x, 1, 32, 3, 256, seed=4, n_resid=0, est_loops=4, est_B=128)
+    e = r.trace["e"]
+    assert e.shape[0] == 7
+    col = int(np.nonzero(r.trace["I"] == sig.freqs[0])[0][0])
+    assert np.max(np.abs(e[:, col] - sig.tones[0])) < 1e-9
+    assert list(r.idx) == list(sig.freqs) and abs(r.val[0] - sig.tones[0]) < 1e-9
+    # the extra loops' bucket values are the isolated-tone identity of their own B and
+    # window (default w est_B / B = 1024)
+    g = O.flat_window(1024, 128)
+    for k in range(4):
+        s_, t_ = int(r.trace["est_sigma"][k]), int(r.trace["est_tau"][k])
+        f = int(sig.freqs[0])
+        h = int(O.bucket_of((s_ * f) % N, N, 128))
+        o = int(O.offset_in_bucket((s_ * f) % N, N, 128))
+        G = O.gain_table(g, N, 128)[o + N // 256]
+        want = G * sig.tones[0] * np.exp(2j * np.pi * ((t_ * f) % N) / N)
+        assert abs(r.trace["est_uhat"][k][h] - want) < 1e-9
+    # collision-heavy location (2K/B = 16%, SNR 10 dB): loops with 4x the buckets that only
+    # estimate repair the values, and with them the top-K choice
+    for s in range(3):
+        sig = make_signal(1 << 16, 20, 10.0, seed=300 + s)
+        xh = np.fft.fft(sig.x) / (1 << 16)
+        r0 = O.sfft(sig.x, 20, 256, 5, 2048, seed=s, n_resid=0)
+        m0 = O.recovery_errors(xh, r0.idx, r0.val, 20)
+        r = O.sfft(sig.x, 20, 256, 5, 2048, seed=s, n_resid=0, est_loops=4, est_B=1024)
+        m1 = O.recovery_errors(xh, r.idx, r.val, 20)
+        assert m1["L0"] == 0 and m1["L1"] < 0.05 and m0["L1"] > 2 * m1["L1"]
+
+
 def check_finalize():
     rng = np.random.default_rng(10)
     I = rng.choice(1000, 40, replace=False)
