@@ -113,6 +113,16 @@ typedef struct {
     int32_t comb_b;
     int32_t comb_loops;
     int32_t comb_keep;
+    /* Estimation-only loops (location and estimation loops separated): est_loops in
+     * [0, 32 - L] more random bucketizations with est_B buckets (power of two,
+     * K <= est_B <= 16384, N/est_B >= 2) and a flat window of est_w samples (0 = w est_B / B;
+     * even, <= N). They are not selected or voted; every located frequency is estimated by
+     * the median (or mean) over all L + est_loops loops. Their sigma, tau are the next
+     * 2 est_loops draws of the stream, after the comb shifts. Not combinable with
+     * SFFT_FLAG_ITERATE or SFFT_FLAG_PHASE_LOCATION (SFFT_E_UNSUPPORTED). */
+    int32_t est_loops;
+    int32_t est_B;
+    int64_t est_w;
 } sfft_params;
 
 /* Resolved plan description (what the plan actually runs). */
@@ -162,14 +172,15 @@ sfft_status sfft_plan_ex(sfft_plan_t* out, const sfft_params* p);
 /* Release a plan. Waits for the plan's in-flight work first. */
 sfft_status sfft_destroy(sfft_plan_t p);
 
-/* Host copies of sigma_r, sigma_r^{-1} mod N and tau_r (uint32[L] each; any may be NULL). */
+/* Host copies of sigma_r, sigma_r^{-1} mod N and tau_r (uint32[L + est_loops] each, the
+ * estimation-only loops last; any may be NULL). */
 sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau);
 
 /* Resolved description of the plan. */
 sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out);
 
 /* Host-only build of the plan's FP64 tables without any device (for checking
- * the host logic): sigma, sigma_inv, tau uint32[L]; tpos uint32[S];
+ * the host logic): sigma, sigma_inv, tau uint32[L + est_loops]; tpos uint32[S];
  * window double[w]; gain double[2*(N/B)] as (re, im) pairs for
  * o = -N/2B .. N/2B-1. Any pointer may be NULL. */
 sfft_status sfft_host_tables(const sfft_params* p, uint32_t* sigma, uint32_t* sigma_inv,

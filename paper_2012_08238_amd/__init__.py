@@ -41,6 +41,9 @@ class PlanParams:
     comb_b: int = 0
     comb_loops: int = 0
     comb_keep: int = 0
+    est_loops: int = 0
+    est_B: int = 0
+    est_w: int = 0
 
     def to_c(self):
         """Return (Params struct, keep-alive list)."""
@@ -57,6 +60,9 @@ class PlanParams:
         p.comb_b = self.comb_b
         p.comb_loops = self.comb_loops
         p.comb_keep = self.comb_keep
+        p.est_loops = self.est_loops
+        p.est_B = self.est_B
+        p.est_w = self.est_w
         keep = []
         if self.sigma is not None:
             s = np.ascontiguousarray(self.sigma, dtype=np.uint32)
@@ -82,7 +88,7 @@ def host_tables(params: PlanParams) -> dict:
     """FP64 host tables of a plan, built without a device (sfft_host_tables)."""
     lib = load()
     p, keep = params.to_c()
-    L, w, M = params.L, params.w, params.N // params.B
+    L, w, M = params.L + params.est_loops, params.w, params.N // params.B
     S = 0 if params.flags & SFFT_FLAG_NO_RESIDUAL else (params.n_resid or 4096)
     out = dict(sigma=np.zeros(L, np.uint32), sigma_inv=np.zeros(L, np.uint32), tau=np.zeros(L, np.uint32),
                tpos=np.zeros(max(S, 1), np.uint32), window=np.zeros(w, np.float64),
@@ -112,7 +118,8 @@ class Plan:
     @classmethod
     def from_params(cls, params: PlanParams) -> "Plan":
         kw = {k: getattr(params, k) for k in ("seed", "d", "vote_threshold", "n_resid", "gauss_c", "flags",
-                                               "strip_cols", "sigma", "tau", "comb_b", "comb_loops", "comb_keep")}
+                                               "strip_cols", "sigma", "tau", "comb_b", "comb_loops", "comb_keep",
+                                               "est_loops", "est_B", "est_w")}
         return cls(params.N, params.K, params.B, params.L, params.w, **kw)
 
     @property
@@ -125,7 +132,8 @@ class Plan:
         return {f: getattr(d, f) for f, _ in _capi.PlanDesc._fields_}
 
     def perms(self):
-        L = self.params.L
+        """sigma, sigma^{-1}, tau of every loop (the estimation-only loops last)."""
+        L = self.params.L + self.params.est_loops
         s, si, t = (np.zeros(L, np.uint32) for _ in range(3))
         check(load().sfft_plan_get_perms(self._h, s.ctypes.data, si.ctypes.data, t.ctypes.data),
               "sfft_plan_get_perms")

@@ -29,7 +29,8 @@ class Params(C.Structure):
                 ("vote_threshold", C.c_int32), ("n_resid", C.c_int32), ("gauss_c", C.c_double),
                 ("flags", C.c_uint32), ("strip_cols", C.c_int32),
                 ("sigma", C.POINTER(C.c_uint32)), ("tau", C.POINTER(C.c_uint32)),
-                ("comb_b", C.c_int32), ("comb_loops", C.c_int32), ("comb_keep", C.c_int32)]
+                ("comb_b", C.c_int32), ("comb_loops", C.c_int32), ("comb_keep", C.c_int32),
+                ("est_loops", C.c_int32), ("est_B", C.c_int32), ("est_w", C.c_int64)]
 
 
 class PlanDesc(C.Structure):

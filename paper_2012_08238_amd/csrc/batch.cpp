@@ -17,7 +17,9 @@ using namespace sfft;
 
 struct sfft_batch_s {
     int device = 0;
-    int32_t n = 0;
+    int32_t n = 0;                 // signals (plans)
+    int32_t ne = 0;                // launch entries: one per plan, two for a plan with estimation-only loops
+    std::vector<int32_t> ent_plan; // entry -> signal
     std::vector<sfft_plan_t> plans;
     char* d_ws = nullptr;
     SigDesc* d_descs = nullptr;
@@ -41,7 +43,7 @@ struct sfft_batch_s {
     // captured on separate streams of one graph, so one group's later stages
     // overlap another group's bucketization
     struct Branch {
-        int32_t g0 = 0, n = 0;
+        int32_t g0 = 0, n = 0;     // entry range
         std::vector<Step> steps;
     };
     std::vector<Branch> branches;
@@ -76,7 +78,7 @@ void batch_free(sfft_batch_t b) {
 
 // part 0: bucketization steps, part 1: the others
 sfft_status issue_part(sfft_batch_t b, hipStream_t s, int part) {
-    const hipError_t e = issue_steps(b->steps, b->d_descs, b->d_ios, b->d_prefix, (uint32_t)b->n, b->xcd_order, part, s);
+    const hipError_t e = issue_steps(b->steps, b->d_descs, b->d_ios, b->d_prefix, (uint32_t)b->ne, b->xcd_order, part, s);
     return e == hipSuccess ? SFFT_OK : hip_fail(e, "batched launch");
 }
 
@@ -122,17 +124,33 @@ sfft_status sfft_batch_create_ex(sfft_batch_t* out, const sfft_plan_t* plans, in
         batch_free(b);
         return hip_fail(e, "hipSetDevice");
     }
-    // one workspace per signal
-    std::vector<size_t> ws_off(n);
-    size_t tot = 0;
+    // launch entries: each plan, followed by its estimation-only loops (if any)
+    std::vector<const Resolved*> ent;
+    std::vector<int32_t> first(n + 1, 0);
     for (int32_t i = 0; i < n; ++i) {
-        ws_off[i] = tot;
-        tot += (workspace_layout(plan_resolved(plans[i])).total + 255) & ~size_t(255);
+        const Resolved& R = plan_resolved(plans[i]);
+        first[i] = (int32_t)ent.size();
+        ent.push_back(&R);
+        b->ent_plan.push_back(i);
+        if (R.est) {
+            ent.push_back(R.est.get());
+            b->ent_plan.push_back(i);
+        }
+    }
+    first[n] = (int32_t)ent.size();
+    const int32_t ne = (int32_t)ent.size();
+    b->ne = ne;
+    // one workspace per entry
+    std::vector<size_t> ws_off(ne);
+    size_t tot = 0;
+    for (int32_t k = 0; k < ne; ++k) {
+        ws_off[k] = tot;
+        tot += (workspace_layout(*ent[k]).total + 255) & ~size_t(255);
     }
     b->ws_bytes = tot;
-    if (hipMalloc(&b->d_ws, tot) != hipSuccess || hipMalloc(&b->d_descs, sizeof(SigDesc) * n) != hipSuccess ||
-        hipMalloc(&b->d_ios, sizeof(IoDesc) * n) != hipSuccess ||
-        hipHostMalloc(&b->h_ios, sizeof(IoDesc) * n, hipHostMallocDefault) != hipSuccess) {
+    if (hipMalloc(&b->d_ws, tot) != hipSuccess || hipMalloc(&b->d_descs, sizeof(SigDesc) * ne) != hipSuccess ||
+        hipMalloc(&b->d_ios, sizeof(IoDesc) * ne) != hipSuccess ||
+        hipHostMalloc(&b->h_ios, sizeof(IoDesc) * ne, hipHostMallocDefault) != hipSuccess) {
         batch_free(b);
         return set_error(SFFT_E_NOMEM, "batch allocation");
     }
@@ -141,21 +159,28 @@ sfft_status sfft_batch_create_ex(sfft_batch_t* out, const sfft_plan_t* plans, in
         batch_free(b);
         return hip_fail(e, "workspace clear");
     }
-    std::vector<SigDesc> descs(n);
-    for (int32_t i = 0; i < n; ++i)
-        descs[i] = make_desc(plan_resolved(plans[i]), const_cast<char*>(plan_tables(plans[i])), b->d_ws + ws_off[i]);
-    e = hipMemcpy(b->d_descs, descs.data(), sizeof(SigDesc) * n, hipMemcpyHostToDevice);
+    std::vector<SigDesc> descs(ne);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t k = first[i];
+        char* tab = const_cast<char*>(plan_tables(plans[i]));
+        descs[k] = make_desc(*ent[k], tab, b->d_ws + ws_off[k]);
+        if (ent[k]->est) {
+            descs[k + 1] = make_desc(*ent[k + 1], tab + plan_est_table_offset(plans[i]), b->d_ws + ws_off[k + 1]);
+            link_est(&descs[k], b->d_descs + k + 1, *ent[k]);
+        }
+    }
+    e = hipMemcpy(b->d_descs, descs.data(), sizeof(SigDesc) * ne, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         batch_free(b);
         return hip_fail(e, "descriptor upload");
     }
-    // one launch per stage and variant, each with its own prefix over all n signals
+    // one launch per stage and variant, each with its own prefix over all entries
     std::vector<uint32_t> prefix;
     std::vector<const Resolved*> sig(n);
     for (int32_t i = 0; i < n; ++i) sig[i] = &plan_resolved(plans[i]);
     const int32_t nb = std::min(n_branches, n);
     if (nb == 1) {
-        plan_steps(sig, &b->steps, &prefix);
+        plan_steps(ent, &b->steps, &prefix);
     } else {
         // contiguous groups of about equal signal bytes, none empty
         std::vector<double> pre(n + 1, 0.0);
@@ -169,11 +194,11 @@ sfft_status sfft_batch_create_ex(sfft_batch_t* out, const sfft_plan_t* plans, in
             cut[g] = std::min(c, n - (nb - g));
         }
         for (int32_t g = 0; g < nb; ++g) {
-            const int32_t start = cut[g], end = cut[g + 1];
+            const int32_t start = first[cut[g]], end = first[cut[g + 1]];   // signals -> entries
             sfft_batch_s::Branch br;
             br.g0 = start;
             br.n = end - start;
-            std::vector<const Resolved*> part(sig.begin() + start, sig.begin() + end);
+            std::vector<const Resolved*> part(ent.begin() + start, ent.begin() + end);
             plan_steps(part, &br.steps, &prefix);
             b->branches.push_back(std::move(br));
         }
@@ -200,7 +225,7 @@ sfft_status sfft_batch_create_ex(sfft_batch_t* out, const sfft_plan_t* plans, in
         batch_free(b);
         return hip_fail(e, "batch setup");
     }
-    b->last_io.resize(n);
+    b->last_io.resize(ne);
     *out = b;
     return SFFT_OK;
 }
@@ -218,22 +243,26 @@ static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* 
         if (q == hipErrorNotReady) return set_error(SFFT_E_BUSY, "batch is executing on another stream");
         if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
     }
-    std::vector<IoDesc> io(b->n);
     for (int32_t i = 0; i < b->n; ++i) {
         if (!x_dev[i] || !out_idx[i] || !out_val[i]) return set_error(SFFT_E_INVALID, "null signal or output pointer");
         if (reinterpret_cast<uintptr_t>(x_dev[i]) & 15u) return set_error(SFFT_E_INVALID, "x_dev must be 16-byte aligned");
-        io[i] = IoDesc{reinterpret_cast<const float2*>(x_dev[i]), out_idx[i], reinterpret_cast<float2*>(out_val[i]),
+    }
+    // per entry (a plan's estimation-only loops read the same signal)
+    std::vector<IoDesc> io(b->ne);
+    for (int32_t k = 0; k < b->ne; ++k) {
+        const int32_t i = b->ent_plan[k];
+        io[k] = IoDesc{reinterpret_cast<const float2*>(x_dev[i]), out_idx[i], reinterpret_cast<float2*>(out_val[i]),
                        out_resid ? out_resid[i] : nullptr};
     }
-    const bool same = b->io_valid && memcmp(io.data(), b->last_io.data(), sizeof(IoDesc) * b->n) == 0;
+    const bool same = b->io_valid && memcmp(io.data(), b->last_io.data(), sizeof(IoDesc) * b->ne) == 0;
     if (!same) {
         // the pinned staging buffer may still feed the previous run's copy
         if (b->launched) {
             e = hipEventSynchronize(b->done);
             if (e != hipSuccess) return hip_fail(e, "wait for previous batch run");
         }
-        memcpy(b->h_ios, io.data(), sizeof(IoDesc) * b->n);
-        e = hipMemcpyAsync(b->d_ios, b->h_ios, sizeof(IoDesc) * b->n, hipMemcpyHostToDevice, s);
+        memcpy(b->h_ios, io.data(), sizeof(IoDesc) * b->ne);
+        e = hipMemcpyAsync(b->d_ios, b->h_ios, sizeof(IoDesc) * b->ne, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "I/O descriptor upload");
         b->last_io = io;
         b->io_valid = true;

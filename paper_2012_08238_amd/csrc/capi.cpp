@@ -103,15 +103,20 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.est_units = R.est_units;
     d.lmax = R.lmax;
     d.combine = (R.flags & SFFT_FLAG_MEAN_ESTIMATE) ? 1u : 0u;
+    d.eloops = nullptr;
+    d.L_est = 0;
     return d;
 }
 
-// Launch the five stages for one signal (nsig == 0 form of Launch).
-sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc& io, hipStream_t s) {
+void link_est(SigDesc* d, const SigDesc* d_est_dev, const Resolved& R) {
+    d->eloops = d_est_dev;
+    d->L_est = R.L_est();
+}
+
+// Bucketization and B-point FFT (+ selection) of one descriptor.
+static sfft_status launch_buckets(const Resolved& R, const SigDesc* d_desc, const IoDesc& io, hipStream_t s) {
     Launch a{};
     a.descs = d_desc;
-    a.ios = nullptr;
-    a.prefix = nullptr;
     a.nsig = 0;
     a.xcd_order = R.xcd_order;
     a.one_io = io;
@@ -124,6 +129,20 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     } else {
         HIP_TRY(launch_fft_select(a, R.log2B, R.L, s), "fft/select launch");
     }
+    return SFFT_OK;
+}
+
+// Launch every stage for one signal (nsig == 0 form of Launch). d_desc[1] holds
+// the estimation-only loops when the plan has them.
+sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc& io, hipStream_t s) {
+    sfft_status st = launch_buckets(R, d_desc, io, s);
+    if (st == SFFT_OK && R.est) st = launch_buckets(*R.est, d_desc + 1, io, s);
+    if (st != SFFT_OK) return st;
+    Launch a{};
+    a.descs = d_desc;
+    a.nsig = 0;
+    a.xcd_order = 0;
+    a.one_io = io;
     if (R.comb_loops) HIP_TRY(launch_comb(a, R.comb_log2b, R.comb_loops, s), "comb prefilter launch");
     if (R.phase)
         HIP_TRY(launch_decode(a, R.vote_units, 0, s), "phase decode launch");
@@ -153,9 +172,10 @@ using namespace sfft;
 struct sfft_plan_s {
     Resolved R;
     int device = 0;
-    char* d_tab = nullptr;
-    char* d_ws = nullptr;
-    SigDesc* d_desc = nullptr;
+    char* d_tab = nullptr;       // tables of the plan, then (at tab_e) of its estimation-only loops
+    char* d_ws = nullptr;        // workspace, idem (at ws_e)
+    size_t tab_e = 0, ws_e = 0;
+    SigDesc* d_desc = nullptr;   // [1 + has estimation-only loops]
     size_t tab_bytes = 0, ws_bytes = 0;
     hipEvent_t done = nullptr;
     hipStream_t last_stream = nullptr;
@@ -190,20 +210,37 @@ sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
     e = init_kernel_attributes();
     if (e != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
-    const TabLayout tl = table_layout(Rr);
-    const WsLayout wl = workspace_layout(Rr);
-    pl->tab_bytes = tl.total;
-    pl->ws_bytes = wl.total;
-    if (hipMalloc(&pl->d_tab, tl.total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device tables"));
-    if (hipMalloc(&pl->d_ws, wl.total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device workspace"));
-    if (hipMalloc(&pl->d_desc, sizeof(SigDesc)) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device descriptor"));
-    const std::vector<char> h = pack_tables(Rr, T);
-    e = hipMemcpy(pl->d_tab, h.data(), tl.total, hipMemcpyHostToDevice);
+    std::vector<char> h = pack_tables(Rr, T);
+    size_t ws_total = workspace_layout(Rr).total;
+    const int nd = Rr.est ? 2 : 1;
+    if (Rr.est) {
+        // the estimation-only loops' tables and workspace follow, 256-byte aligned
+        HostTables Te;
+        build_tables(*Rr.est, &Te);
+        const std::vector<char> he = pack_tables(*Rr.est, Te);
+        pl->tab_e = (h.size() + 255) & ~size_t(255);
+        h.resize(pl->tab_e, 0);
+        h.insert(h.end(), he.begin(), he.end());
+        pl->ws_e = (ws_total + 255) & ~size_t(255);
+        ws_total = pl->ws_e + workspace_layout(*Rr.est).total;
+    }
+    pl->tab_bytes = h.size();
+    pl->ws_bytes = ws_total;
+    if (hipMalloc(&pl->d_tab, h.size()) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device tables"));
+    if (hipMalloc(&pl->d_ws, ws_total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device workspace"));
+    if (hipMalloc(&pl->d_desc, sizeof(SigDesc) * nd) != hipSuccess)
+        return cleanup(set_error(SFFT_E_NOMEM, "device descriptor"));
+    e = hipMemcpy(pl->d_tab, h.data(), h.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "table upload"));
-    e = hipMemset(pl->d_ws, 0, wl.total);
+    e = hipMemset(pl->d_ws, 0, ws_total);
     if (e != hipSuccess) return cleanup(hip_fail(e, "workspace clear"));
-    const SigDesc d = make_desc(Rr, pl->d_tab, pl->d_ws);
-    e = hipMemcpy(pl->d_desc, &d, sizeof(SigDesc), hipMemcpyHostToDevice);
+    SigDesc d[2];
+    d[0] = make_desc(Rr, pl->d_tab, pl->d_ws);
+    if (Rr.est) {
+        d[1] = make_desc(*Rr.est, pl->d_tab + pl->tab_e, pl->d_ws + pl->ws_e);
+        link_est(&d[0], pl->d_desc + 1, Rr);
+    }
+    e = hipMemcpy(pl->d_desc, d, sizeof(SigDesc) * nd, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "descriptor upload"));
     e = hipEventCreateWithFlags(&pl->done, hipEventDisableTiming);
     if (e != hipSuccess) return cleanup(hip_fail(e, "event"));
@@ -213,6 +250,7 @@ sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
 
 const Resolved& plan_resolved(sfft_plan_t p) { return p->R; }
 const char* plan_tables(sfft_plan_t p) { return p->d_tab; }
+size_t plan_est_table_offset(sfft_plan_t p) { return p->tab_e; }
 int plan_device(sfft_plan_t p) { return p->device; }
 size_t plan_table_bytes(sfft_plan_t p) { return p->tab_bytes; }
 size_t plan_ws_bytes(sfft_plan_t p) { return p->ws_bytes; }
@@ -288,12 +326,21 @@ sfft_status sfft_destroy(sfft_plan_t p) {
     return SFFT_OK;
 }
 
-sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau) {
-    if (!p) return set_error(SFFT_E_INVALID, "null plan");
-    const Resolved& R = p->R;
+static void copy_perms(const Resolved& R, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau) {
+    const uint32_t Le = R.L_est();
     if (sigma) memcpy(sigma, R.sigma.data(), R.L * 4);
     if (sigma_inv) memcpy(sigma_inv, R.sigma_inv.data(), R.L * 4);
     if (tau) memcpy(tau, R.tau.data(), R.L * 4);
+    if (Le) {
+        if (sigma) memcpy(sigma + R.L, R.est->sigma.data(), Le * 4);
+        if (sigma_inv) memcpy(sigma_inv + R.L, R.est->sigma_inv.data(), Le * 4);
+        if (tau) memcpy(tau + R.L, R.est->tau.data(), Le * 4);
+    }
+}
+
+sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_inv, uint32_t* tau) {
+    if (!p) return set_error(SFFT_E_INVALID, "null plan");
+    copy_perms(p->R, sigma, sigma_inv, tau);
     return SFFT_OK;
 }
 
@@ -324,9 +371,7 @@ sfft_status sfft_host_tables(const sfft_params* p, uint32_t* sigma, uint32_t* si
     std::string err;
     const sfft_status st = resolve_params(*p, &R, &err);
     if (st != SFFT_OK) return set_error(st, err);
-    if (sigma) memcpy(sigma, R.sigma.data(), R.L * 4);
-    if (sigma_inv) memcpy(sigma_inv, R.sigma_inv.data(), R.L * 4);
-    if (tau) memcpy(tau, R.tau.data(), R.L * 4);
+    copy_perms(R, sigma, sigma_inv, tau);
     if (tpos && R.S) memcpy(tpos, R.tpos.data(), (size_t)R.S * 4);
     if (window || gain) {
         HostTables T;

@@ -69,6 +69,8 @@ struct SigDesc {
     uint32_t comb_keep;         // residues kept per comb loop
     uint32_t iterate;           // 1: one subtraction round after the first recovery
     uint32_t phase;             // 1: location by phase encoding over loop pairs (2j, 2j+1)
+    const SigDesc* eloops;      // estimation-only loops of the same signal (own B, window, tables), or null
+    uint32_t L_est;             // their number
 };
 
 // Per-signal caller buffers of one execution.

@@ -329,10 +329,16 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
     const uint32_t rsh = d.log2N - d.tb;
     const double step = d.step;
-    if (threadIdx.x < L) {
-        s_sig[threadIdx.x] = gld(d.sigma + threadIdx.x);
-        s_tau[threadIdx.x] = gld(d.tau + threadIdx.x);
-        s_sinv[threadIdx.x] = gld(d.sigma_inv + threadIdx.x);
+    // loops L .. L+Le-1: the estimation-only loops (own B, window gain, buckets; same N)
+    const uint32_t Le = d.L_est, Lt = L + Le;
+    const CDesc ed = Le ? (CDesc)d.eloops : (CDesc)a.descs + (a.nsig ? sig : 0u);
+    const uint32_t Be = ed->B, Me = ed->M, log2Me = ed->log2M;
+    if (threadIdx.x < Lt) {
+        const bool xe = threadIdx.x >= L;
+        const uint32_t q = xe ? threadIdx.x - L : threadIdx.x;
+        s_sig[threadIdx.x] = gld((xe ? ed->sigma : d.sigma) + q);
+        s_tau[threadIdx.x] = gld((xe ? ed->tau : d.tau) + q);
+        s_sinv[threadIdx.x] = gld((xe ? ed->sigma_inv : d.sigma_inv) + q);
     }
     stage_rou<kFinNT>(s_rou, d.rou, d.tb);
     __syncthreads();
@@ -356,7 +362,7 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
             continue;
         }
         // loops that estimate f: all, or (phase location) those of the pairs that decode it
-        uint32_t use = (L >= 32u) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+        uint32_t use = (Lt >= 32u) ? 0xFFFFFFFFu : ((1u << Lt) - 1u);
         if (phase) {
             use = 0;
             for (uint32_t j = 0; j < (L >> 1); ++j)
@@ -368,14 +374,18 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
         for (int r = 0; r < LMAX; ++r) {
             re[r] = __builtin_inff();
             im[r] = __builtin_inff();
-            if ((uint32_t)r < L && ((use >> r) & 1u)) {
+            if ((uint32_t)r < Lt && ((use >> r) & 1u)) {
+                const bool xe = (uint32_t)r >= L;
+                const uint32_t Bx = xe ? Be : B, Mx = xe ? Me : M, l2M = xe ? log2Me : log2M;
                 const uint32_t p = (s_sig[r] * f) & maskN;
-                const uint32_t h = ((p + (M >> 1)) >> log2M) & (B - 1u);
-                const uint32_t o = (p - (h << log2M) + (N >> 1)) & maskN;   // o + N/2
-                const uint32_t gi = o - (N >> 1) + (M >> 1);
-                const float2 g = gld(invG + gi);
+                const uint32_t h = ((p + (Mx >> 1)) >> l2M) & (Bx - 1u);
+                const uint32_t o = (p - (h << l2M) + (N >> 1)) & maskN;   // o + N/2
+                const uint32_t gi = o - (N >> 1) + (Mx >> 1);
+                const float2 g = gld((xe ? ed->invG : invG) + gi);
                 float2 uv;
-                if (fftm) {
+                if (xe) {
+                    uv = gld(ed->uhat + (size_t)(r - L) * Be + h);
+                } else if (fftm) {
                     // two-pass FFT layout: X[h] = e^{+2 pi i (s tau h mod B)/B} V[s h mod B], s = sigma^{-1}
                     const uint32_t si = s_sinv[r];
                     const float2 t = gld(tw + ((si * s_tau[r] * h) & (B - 1u)));   // e^{-2 pi i ./B}
@@ -397,7 +407,7 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
             float sr = 0.f, si = 0.f;
 #pragma unroll
             for (int r = 0; r < LMAX; ++r) {
-                if ((uint32_t)r < L && ((use >> r) & 1u)) {
+                if ((uint32_t)r < Lt && ((use >> r) & 1u)) {
                     sr += re[r];
                     si += im[r];
                 }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <complex>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,8 @@ struct Resolved {
     uint32_t comb_b, comb_log2b, comb_loops, comb_keep, comb_words;  // comb prefilter
     uint32_t iterate, sub_lds;  // one subtraction round (iterative framework); its LDS bytes
     uint32_t phase;             // location by phase encoding over loop pairs
+    uint32_t est_only;          // a plan's estimation-only loops (bucketization + FFT only)
+    std::shared_ptr<const struct Resolved> est;  // the estimation-only loops of this plan, or null
     std::vector<uint32_t> comb_tau;
     uint32_t fft_p1_units, fft_p2_units;   // two-pass FFT workgroups per signal
     uint64_t seed;
@@ -33,6 +36,7 @@ struct Resolved {
     // units per stage
     uint32_t fold_units, vote_units, vote_upl, resid_blocks, vote_lds, strip_lds, resid_lds, fin_lds;
     uint32_t est_units;
+    uint32_t L_est() const { return est ? est->L : 0u; }
     uint32_t xcd_order;
     uint32_t fold_variant;      // bucketization kernel variant (kernels.hpp fold_variant)
 };

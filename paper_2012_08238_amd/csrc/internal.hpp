@@ -16,6 +16,9 @@ sfft_status hip_fail(hipError_t e, const char* what);
 hipError_t init_kernel_attributes();
 
 SigDesc make_desc(const Resolved& R, char* tab, char* ws);
+// Point a plan's descriptor at the device descriptor of its estimation-only loops.
+void link_est(SigDesc* d, const SigDesc* d_est_dev, const Resolved& R);
+size_t plan_est_table_offset(sfft_plan_t p);
 sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc& io, hipStream_t s);
 
 sfft_status plan_create(const sfft_params& p, sfft_plan_t* out);

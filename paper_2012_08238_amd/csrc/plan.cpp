@@ -56,6 +56,17 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         *err = "phase-encoding location needs B <= 16384";
         return SFFT_E_UNSUPPORTED;
     }
+    if (p.est_loops < 0 || p.est_loops > kMaxL - p.L) return bad("est_loops must be in [0, 32 - L]");
+    if (p.est_loops > 0) {
+        if (p.est_B < 2 || !is_pow2((uint64_t)p.est_B) || p.N / p.est_B < 2 || p.est_B < p.K)
+            return bad("est_B must be a power of two with K <= est_B and N/est_B >= 2");
+        const int64_t we = p.est_w ? p.est_w : p.w * (int64_t)p.est_B / p.B;
+        if (we < 2 || we > p.N || (we & 1)) return bad("est_w must be even and in [2, N]");
+        if (p.est_B > kMaxFftLds || (p.flags & (SFFT_FLAG_ITERATE | SFFT_FLAG_PHASE_LOCATION))) {
+            *err = "estimation-only loops need est_B <= 16384 and neither the subtraction round nor phase location";
+            return SFFT_E_UNSUPPORTED;
+        }
+    }
     R.N = (uint32_t)p.N;
     R.K = (uint32_t)p.K;
     R.B = (uint32_t)p.B;
@@ -77,7 +88,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.rsh = (R.log2N + 1) / 2;
     R.tb = std::min<uint32_t>(8u, R.log2N);
     uint32_t lm = 4;
-    while (lm < R.L) lm <<= 1;
+    while (lm < R.L + (uint32_t)std::max<int32_t>(p.est_loops, 0)) lm <<= 1;   // every estimating loop
     R.lmax = lm;
     R.phase = phase ? 1u : 0u;
     // candidates: every enumerated frequency of loops 0..L-T (votes), one per
@@ -108,6 +119,35 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.comb_words = R.comb_loops ? std::max<uint32_t>(1u, R.comb_b / 32) : 0u;
     R.comb_tau.resize(R.comb_loops);
     for (uint32_t c = 0; c < R.comb_loops; ++c) R.comb_tau[c] = (uint32_t)(rng.next() & (R.N - 1));
+    // estimation-only loops: the next draws, resolved as a plan of their own
+    if (p.est_loops > 0) {
+        std::vector<uint32_t> es(p.est_loops), et(p.est_loops);
+        for (int32_t r = 0; r < p.est_loops; ++r) {
+            es[r] = (uint32_t)((rng.next() & (R.N - 1)) | 1u);
+            et[r] = (uint32_t)(rng.next() & (R.N - 1));
+        }
+        sfft_params pe = p;
+        pe.B = p.est_B;
+        pe.L = p.est_loops;
+        pe.w = p.est_w ? p.est_w : p.w * (int64_t)p.est_B / p.B;
+        pe.d = 1;
+        pe.vote_threshold = p.est_loops;   // keeps the (unused) capacity bound at K N/est_B
+        pe.n_resid = 0;
+        pe.flags = SFFT_FLAG_NO_RESIDUAL | (p.flags & SFFT_FLAG_XCD_ORDER);
+        pe.strip_cols = 0;
+        pe.sigma = es.data();
+        pe.tau = et.data();
+        pe.comb_b = pe.comb_loops = pe.comb_keep = 0;
+        pe.est_loops = 0;
+        auto E = std::make_shared<Resolved>();
+        const sfft_status st = resolve_params(pe, E.get(), err);
+        if (st != SFFT_OK) return st;
+        E->est_only = 1;
+        E->cap = 0;   // no candidates of their own
+        E->vote_units = 0;
+        E->est_units = 0;
+        R.est = std::move(E);
+    }
     if (p.sigma) {
         for (uint32_t r = 0; r < R.L; ++r) {
             if (!(p.sigma[r] & 1u) || p.sigma[r] >= R.N || p.tau[r] >= R.N)

@@ -26,8 +26,9 @@ constexpr int kMaxStreams = 16;
 
 struct ServedPlan {
     Resolved R;
-    std::vector<char> image;  // device table image (table_layout order)
-    size_t ws_bytes = 0;
+    std::vector<char> image;  // device table image (table_layout order), then the estimation-only loops' at tab_e
+    size_t ws_bytes = 0;      // workspace, then the estimation-only loops' at ws_e
+    size_t tab_e = 0, ws_e = 0;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -48,8 +49,9 @@ public:
     }
 
     sfft_status init() {
-        stage_bytes_ = align256(sizeof(SigDesc) * max_wave_) + align256(sizeof(IoDesc) * max_wave_) +
-                       max_prefix_entries(max_wave_) * 4;
+        // a request takes two launch entries when its plan has estimation-only loops
+        const size_t me = 2 * (size_t)max_wave_;
+        stage_bytes_ = align256(sizeof(SigDesc) * me) + align256(sizeof(IoDesc) * me) + max_prefix_entries(me) * 4;
         for (Slot& s : slots_) {
             if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
@@ -71,20 +73,31 @@ public:
 
     int launch(int slot, const std::vector<serve::WaveItem<IoDesc>>& items) override {
         Slot& sl = slots_[slot];
-        const size_t n = items.size();
-        if (n == 0 || n > (size_t)max_wave_) return SFFT_E_INVALID;
+        const size_t nreq = items.size();
+        if (nreq == 0 || nreq > (size_t)max_wave_) return SFFT_E_INVALID;
+        // launch entries: each request, followed by its plan's estimation-only loops (if any)
+        size_t n = 0;
+        for (size_t i = 0; i < nreq; ++i) n += get(items[i].plan)->R.est ? 2 : 1;
         std::vector<const Resolved*> sig(n);
         uint32_t xcd = 1;
         const size_t o_io = align256(sizeof(SigDesc) * n);
         const size_t o_pre = o_io + align256(sizeof(IoDesc) * n);
         SigDesc* hd = reinterpret_cast<SigDesc*>(sl.h_stage);
         IoDesc* hi = reinterpret_cast<IoDesc*>(sl.h_stage + o_io);
-        for (size_t i = 0; i < n; ++i) {
+        for (size_t i = 0, k = 0; i < nreq; ++i) {
             const ServedPlan* p = get(items[i].plan);
-            sig[i] = &p->R;
+            sig[k] = &p->R;
             xcd &= p->R.xcd_order;
-            hd[i] = make_desc(p->R, arena_ + items[i].tab_off, arena_ + items[i].ws_off);
-            hi[i] = items[i].io;
+            hd[k] = make_desc(p->R, arena_ + items[i].tab_off, arena_ + items[i].ws_off);
+            hi[k] = items[i].io;
+            if (p->R.est) {
+                sig[k + 1] = p->R.est.get();
+                hd[k + 1] = make_desc(*p->R.est, arena_ + items[i].tab_off + p->tab_e, arena_ + items[i].ws_off + p->ws_e);
+                hi[k + 1] = items[i].io;
+                link_est(&hd[k], reinterpret_cast<const SigDesc*>(sl.d_stage) + k + 1, p->R);
+                ++k;
+            }
+            ++k;
         }
         std::vector<Step> steps;
         std::vector<uint32_t> prefix;
@@ -157,6 +170,9 @@ std::string plan_key(const sfft_params& p) {
     put(&p.comb_b, 4);
     put(&p.comb_loops, 4);
     put(&p.comb_keep, 4);
+    put(&p.est_loops, 4);
+    put(&p.est_B, 4);
+    put(&p.est_w, 8);
     const int32_t has = p.sigma != nullptr;
     put(&has, 4);
     if (p.sigma && p.tau && p.L > 0 && p.L <= kMaxL) {
@@ -208,6 +224,16 @@ sfft_status served_plan(sfft_server_t s, const sfft_params& p, uint32_t* id, siz
     build_tables(sp->R, &T);
     sp->image = pack_tables(sp->R, T);
     sp->ws_bytes = workspace_layout(sp->R).total;
+    if (sp->R.est) {
+        HostTables Te;
+        build_tables(*sp->R.est, &Te);
+        const std::vector<char> he = pack_tables(*sp->R.est, Te);
+        sp->tab_e = align256(sp->image.size());
+        sp->image.resize(sp->tab_e, 0);
+        sp->image.insert(sp->image.end(), he.begin(), he.end());
+        sp->ws_e = align256(sp->ws_bytes);
+        sp->ws_bytes = sp->ws_e + workspace_layout(*sp->R.est).total;
+    }
     const size_t tab = sp->image.size(), ws = sp->ws_bytes;
     if (align256(tab) + align256(ws) > s->core->arena_capacity())
         return set_error(SFFT_E_NOMEM, "request needs " + std::to_string(align256(tab) + align256(ws)) +

@@ -87,7 +87,7 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
             add_step(kStepEst, lm | (round << 8), 0, [&](const Resolved& R) { return in_group(R) ? R.est_units : 0u; });
         }
         add_step(kStepFin, round, max_of(active, [](const Resolved& R) { return R.fin_lds; }),
-                 [&](const Resolved& R) { return active(R) ? 1u : 0u; });
+                 [&](const Resolved& R) { return active(R) && !R.est_only ? 1u : 0u; });
     }
     add_step(kStepRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
              [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });

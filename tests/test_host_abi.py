@@ -77,6 +77,35 @@ def test_phase_location_pairs_and_validation():
     assert e.value.status == _capi.SFFT_E_UNSUPPORTED
 
 
+def test_est_loops_perms_and_validation():
+    N, L, seed, S_ = 1 << 14, 5, 33, 64
+    for comb in (0, 2):
+        kw = dict(seed=seed, n_resid=S_, est_loops=3, est_B=512)
+        if comb:
+            kw.update(comb_b=256, comb_loops=comb)
+        t = S.host_tables(S.PlanParams(N, 10, 128, L, 512, **kw))
+        sigma, tau, _ = O.draw_permutations(N, L, seed, S_)
+        es, et = O.draw_est_permutations(N, L, seed, S_, comb, 3)
+        assert np.array_equal(t["sigma"], np.concatenate([sigma, es]).astype(np.uint32))
+        assert np.array_equal(t["tau"], np.concatenate([tau, et]).astype(np.uint32))
+        inv = np.array([O.modinv(s_, N) for s_ in np.concatenate([sigma, es])], dtype=np.uint32)
+        assert np.array_equal(t["sigma_inv"], inv)
+    base = dict(N=N, K=10, B=128, L=5, w=512)
+    for bad in (dict(est_loops=28, est_B=256), dict(est_loops=2, est_B=8), dict(est_loops=2, est_B=300),
+                dict(est_loops=2, est_B=256, est_w=3), dict(est_loops=-1)):
+        with pytest.raises(S.SfftError) as e:
+            S.host_tables(S.PlanParams(**base, **bad))
+        assert e.value.status == _capi.SFFT_E_INVALID
+    for bad in (dict(N=1 << 17, est_loops=2, est_B=1 << 15), dict(est_loops=2, est_B=256, flags=S.SFFT_FLAG_ITERATE),
+                dict(est_loops=2, est_B=256, flags=S.SFFT_FLAG_PHASE_LOCATION, L=4)):
+        kw = dict(base)
+        kw.update(bad)
+        with pytest.raises(S.SfftError) as e:
+            S.host_tables(S.PlanParams(**kw))
+        assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+    S.host_tables(S.PlanParams(**dict(base, L=16), est_loops=16, est_B=64))   # 32 loops in all
+
+
 def test_iterate_validation_and_gain():
     # the subtraction round runs with the one-workgroup FFT only
     with pytest.raises(S.SfftError) as e:
