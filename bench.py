@@ -287,6 +287,54 @@ def phase_measure(S, torch, dev, args) -> dict:
     return out
 
 
+def est_loops_measure(S, torch, dev, args) -> dict:
+    """Location and estimation loops separated: location with fewer buckets plus
+    loops with 4x the buckets that only estimate, against the plain plan, on
+    batches of resident signals at SNR 20 dB: signals/s, tones missed per signal
+    and the median value error of the tones found (against the planted tones)."""
+    import numpy as np
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    runs = [("c2_plain", 1 << 20, 50, 1024, 7, 0, 0), ("c2_loc512_est4x4096", 1 << 20, 50, 512, 7, 4, 4096),
+            ("n22_plain_b16384", 1 << 22, 100, 16384, 9, 0, 0), ("n22_loc4096_est4x16384", 1 << 22, 100, 4096, 9, 4, 16384)]
+    m = args.est_batch
+    out = {"snr_db": 20.0, "batch": m}
+    cache = {}
+    for name, n, k, b, l, el, eb in runs:
+        if (n, k) not in cache:
+            cache.clear()
+            cache[(n, k)] = [make_signal_torch(n, k, 20.0, derive_seed(130, i), dev) for i in range(m)]
+        sigs = cache[(n, k)]
+        xs = [q[0] for q in sigs]
+        plan = S.Plan(n, k, b, l, 8 * b, seed=23, est_loops=el, est_B=eb)
+        bt = S.Batch([plan] * m, branches=args.branches)
+        outs = [plan.outputs(dev) for _ in range(m)]
+        for _ in range(2):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.est_steps):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - t0
+        missed, errs = 0, []
+        for o, q in zip(outs, sigs):
+            gi, gv = o[0].cpu().numpy(), o[1].cpu().numpy()
+            got = dict(zip(gi.tolist(), gv.tolist()))
+            for f, tone in zip(q[1].tolist(), q[2].tolist()):
+                if f in got:
+                    errs.append(abs(got[f] - tone))
+                else:
+                    missed += 1
+        out[name] = {"N": n, "K": k, "B": b, "L": l, "est_loops": el, "est_B": eb,
+                     "signals_per_s": round(m * args.est_steps / el_s, 1), "missed_per_signal": round(missed / m, 3),
+                     "median_value_err": float(np.median(errs)) if errs else None}
+        bt.close()
+        plan.close()
+        print(f"# estimation loops {name}: {out[name]}", file=sys.stderr, flush=True)
+    cache.clear()
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -443,6 +491,8 @@ def main() -> int:
     ap.add_argument("--iter-steps", type=int, default=5)
     ap.add_argument("--phase-batch", type=int, default=64, help="signals per batch of the phase-location runs (0 = skip)")
     ap.add_argument("--phase-steps", type=int, default=10)
+    ap.add_argument("--est-batch", type=int, default=32, help="signals per batch of the estimation-loop runs (0 = skip)")
+    ap.add_argument("--est-steps", type=int, default=10)
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
@@ -556,6 +606,7 @@ def main() -> int:
     comb = comb_measure(S, torch, dev, args) if args.comb_batch > 0 else None
     iterate = iterate_measure(S, torch, dev, args) if args.iter_batch > 0 else None
     phase = phase_measure(S, torch, dev, args) if args.phase_batch > 0 else None
+    est_loops = est_loops_measure(S, torch, dev, args) if args.est_batch > 0 else None
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -625,6 +676,7 @@ def main() -> int:
         "comb_prefilter": comb,
         "subtraction_round": iterate,
         "phase_location": phase,
+        "estimation_loops": est_loops,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,
