@@ -335,6 +335,96 @@ def est_loops_measure(S, torch, dev, args) -> dict:
     return out
 
 
+def copy_bandwidth(torch, dev) -> float:
+    """Achievable HBM bandwidth on this device: a 2 GiB device-to-device tensor
+    copy (read + write bytes / time), best of 10."""
+    n = 1 << 28   # complex64 elements: 2 GiB
+    a = torch.empty(n, dtype=torch.complex64, device=dev)
+    a.real.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
+def dense_fft_context(torch, dev, xs) -> dict:
+    """What the sparse path avoids: a dense N-point FFT of every signal of the
+    batch on the same GPU (rocFFT through torch.fft, complex64), and one dense
+    FP64 FFT of one signal on the host (numpy.fft, the fftw analogue)."""
+    import numpy as np
+    x = torch.stack(xs[:16])
+    torch.fft.fft(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        torch.fft.fft(x)
+    torch.cuda.synchronize()
+    gpu = 16 * reps / (time.perf_counter() - t0)
+    xh = xs[0].cpu().numpy().astype(np.complex128)
+    np.fft.fft(xh)
+    t0 = time.perf_counter()
+    np.fft.fft(xh)
+    cpu_s = time.perf_counter() - t0
+    del x
+    torch.cuda.empty_cache()
+    return {"gpu_dense_fft_signals_per_s": round(gpu, 1), "gpu_dense_fft": "torch.fft.fft (rocFFT), complex64, 16 signals",
+            "cpu_dense_fft_fp64_s": round(cpu_s, 4), "cpu_dense_fft": "numpy.fft.fft, one N=2^22 signal, FP64"}
+
+
+def k_sweep_measure(S, torch, dev, args) -> dict:
+    """The C3 sweep: N=2^22, SNR 20 dB, L=9, w=8B, K in {50, 100, 200, 500, 1000}
+    with B = 2^round(log2 sqrt(N K)) (16384, 16384, 32768, 32768, 65536); batches of
+    resident signals: signals/s, tones missed per signal, median value error
+    against the planted tones (the FP32-vs-FP64 parity of these shapes is a GPU
+    test)."""
+    import numpy as np
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    out = {"N": N, "L": L, "snr_db": SNR_DB, "batch": args.ksweep_batch, "points": []}
+    m = args.ksweep_batch
+    for k in (50, 100, 200, 500, 1000):
+        b = 1 << int(round(np.log2(np.sqrt(N * k))))
+        sigs = [make_signal_torch(N, k, SNR_DB, derive_seed(150 + k, i), dev) for i in range(m)]
+        xs = [q[0] for q in sigs]
+        plan = S.Plan(N, k, b, L, 8 * b, seed=29)
+        bt = S.Batch([plan] * m, branches=args.branches)
+        outs = [plan.outputs(dev) for _ in range(m)]
+        for _ in range(2):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.ksweep_steps):
+            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        missed, errs = 0, []
+        for o, q in zip(outs, sigs):
+            got = dict(zip(o[0].cpu().numpy().tolist(), o[1].cpu().numpy().tolist()))
+            for f, tone in zip(q[1].tolist(), q[2].tolist()):
+                if f in got:
+                    errs.append(abs(got[f] - tone))
+                else:
+                    missed += 1
+        pt = {"K": k, "B": b, "w": 8 * b, "signals_per_s": round(m * args.ksweep_steps / el, 1),
+              "missed_per_signal": round(missed / m, 3), "median_value_err": float(np.median(errs)) if errs else None}
+        out["points"].append(pt)
+        bt.close()
+        plan.close()
+        del sigs, xs, outs
+        print(f"# K sweep {pt}", file=sys.stderr, flush=True)
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -493,6 +583,9 @@ def main() -> int:
     ap.add_argument("--phase-steps", type=int, default=10)
     ap.add_argument("--est-batch", type=int, default=32, help="signals per batch of the estimation-loop runs (0 = skip)")
     ap.add_argument("--est-steps", type=int, default=10)
+    ap.add_argument("--ksweep-batch", type=int, default=16, help="signals per batch of the K sweep (0 = skip)")
+    ap.add_argument("--ksweep-steps", type=int, default=5)
+    ap.add_argument("--no-context", action="store_true", help="skip the copy-bandwidth and dense-FFT context")
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
@@ -607,6 +700,12 @@ def main() -> int:
     iterate = iterate_measure(S, torch, dev, args) if args.iter_batch > 0 else None
     phase = phase_measure(S, torch, dev, args) if args.phase_batch > 0 else None
     est_loops = est_loops_measure(S, torch, dev, args) if args.est_batch > 0 else None
+    ksweep = k_sweep_measure(S, torch, dev, args) if args.ksweep_batch > 0 else None
+    context = None
+    if not args.no_context:
+        context = dense_fft_context(torch, dev, xs)
+        context["hbm_copy_GBps"] = round(copy_bandwidth(torch, dev), 1)
+        print(f"# context {context}", file=sys.stderr, flush=True)
     uneven = None
     if args.uneven > 0:
         uneven = uneven_measure(S, torch, dev, args)
@@ -621,6 +720,11 @@ def main() -> int:
                 "launch_us": round(fold_avg_s * 1e6, 2), "launch_timing": launch_source}
     if traffic:
         roofline["effective_GBps"] = round(traffic / fold_avg_s / 1e9, 1)
+    if context:
+        # the same kernel against what a plain copy reaches on this device
+        roofline["achievable_copy_GBps"] = context["hbm_copy_GBps"]
+        if traffic:
+            roofline["effective_frac_of_copy"] = round(traffic / fold_avg_s / 1e9 / context["hbm_copy_GBps"], 4)
 
     cpu = None
     parity = None
@@ -677,6 +781,8 @@ def main() -> int:
         "subtraction_round": iterate,
         "phase_location": phase,
         "estimation_loops": est_loops,
+        "k_sweep_c3": ksweep,
+        "context": context,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": {"exact_support": f"{exact}/{M}", "median_residual_ratio": resid_ratio,
