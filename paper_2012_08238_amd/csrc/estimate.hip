@@ -15,6 +15,27 @@ __device__ __forceinline__ bool in_sorted(const uint32_t* a, uint32_t n, uint32_
     return lo < n && gld(a + lo) == f;
 }
 
+// Append each lane's candidates (bit qq of emask: fv[qq]) to the unordered
+// candidate list with one reservation per wave that has any (no block barrier).
+template <int P>
+__device__ __forceinline__ void append_wave(const uint32_t (&fv)[P], uint32_t emask, uint32_t* ctr, uint32_t* cand,
+                                            uint32_t cap) {
+    if (__ballot(emask != 0u) == 0ull) return;   // wave-uniform
+    const uint32_t cnt = (uint32_t)__popc(emask);
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t total = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if ((threadIdx.x & 63u) == 63u) base = atomicAdd(ctr, total);
+    uint32_t pos = __shfl(base, 63, 64) + incl - cnt;
+#pragma unroll
+    for (int qq = 0; qq < P; ++qq) {
+        if ((emask >> qq) & 1u) {
+            if (pos < cap) gst(cand + pos, fv[qq]);
+            ++pos;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- votes
 // A frequency with >= T votes out of L is voted by one of the loops 0..L-T
 // (pigeonhole), so only the frequencies of those loops' selected buckets are
@@ -28,7 +49,6 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     extern __shared__ uint32_t sbits[];
     __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
     __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
-    __shared__ uint32_t s_scan[kVoteNT / 64 + 1];     // per-wave counts, then the reserved base
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
@@ -116,20 +136,7 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
         fv[qq] = f;
         emask |= (emit ? 1u : 0u) << qq;
     }
-    // one reservation in the candidate list per workgroup (the list is unordered)
-    uint32_t total;
-    const uint32_t off = block_excl_scan<kVoteNT>((uint32_t)__popc(emask), s_scan, total);
-    if (total == 0) return;   // block-uniform
-    if (threadIdx.x == 0) s_scan[kVoteNT / 64] = atomicAdd(ctr, total);
-    __syncthreads();
-    uint32_t pos = s_scan[kVoteNT / 64] + off;
-#pragma unroll
-    for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-        if ((emask >> qq) & 1u) {
-            if (pos < cap) gst(cand + pos, fv[qq]);
-            ++pos;
-        }
-    }
+    append_wave<kVotePerThread>(fv, emask, ctr, cand, cap);
 }
 
 // ---------------------------------------------------------------- phase-encoding location
@@ -163,10 +170,9 @@ __device__ __forceinline__ bool pair_decodes(const __attribute__((address_space(
 // counted from the first pair that does (no duplicates), the comb prefilter (if
 // any) keeps its residue, and (round 1) it was not recovered before. One thread
 // per (pair, selected bucket), kDecPerThread per thread; one list reservation
-// per workgroup.
+// per wave.
 __global__ __launch_bounds__(kVoteNT) void decode_kernel(Launch a, uint32_t round) {
     __shared__ uint32_t s_comb[kMaxCombB / 32];
-    __shared__ uint32_t s_scan[kVoteNT / 64 + 1];
     __shared__ uint32_t s_sig[kMaxL / 2];
     uint32_t sig, unit;
     resolve(a, sig, unit);
@@ -221,19 +227,7 @@ __global__ __launch_bounds__(kVoteNT) void decode_kernel(Launch a, uint32_t roun
         fv[qq] = f;
         emask |= (emit ? 1u : 0u) << qq;
     }
-    uint32_t total;
-    const uint32_t off = block_excl_scan<kVoteNT>((uint32_t)__popc(emask), s_scan, total);
-    if (total == 0) return;   // block-uniform
-    if (threadIdx.x == 0) s_scan[kVoteNT / 64] = atomicAdd(ctr, total);
-    __syncthreads();
-    uint32_t pos = s_scan[kVoteNT / 64] + off;
-#pragma unroll
-    for (uint32_t qq = 0; qq < kDecPerThread; ++qq) {
-        if ((emask >> qq) & 1u) {
-            if (pos < cap) gst(d.cand + pos, fv[qq]);
-            ++pos;
-        }
-    }
+    append_wave<kDecPerThread>(fv, emask, ctr, d.cand, cap);
 }
 
 // ---------------------------------------------------------------- estimation + output

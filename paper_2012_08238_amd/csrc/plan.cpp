@@ -210,8 +210,22 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies
     R.fin_lds = P * 8u + P * 4u;         // selected values, frequencies (sort size P)
     R.iterate = (p.flags & SFFT_FLAG_ITERATE) ? 1u : 0u;
-    // estimation: enough workgroups for the candidate capacity, at most 32 (they stride)
-    R.est_units = (uint32_t)std::min<uint64_t>(32u, ((uint64_t)R.cap + R.K * R.iterate + kFinNT - 1) / kFinNT);
+    // estimation workgroups stride over the candidates, so their number only sets the
+    // parallelism: about four candidates per thread for the expected count, at most 32.
+    // Voting: K plus the false frequencies, N P(Binom(L, dK/B) >= T) (each loop selects a
+    // bucket of a random frequency with probability dK/B); phase location: the capacity.
+    double expect = (double)R.cap;
+    if (!phase) {
+        const double q = std::min(1.0, (double)R.dK / (double)R.B);
+        double tail = 0.0, c = 1.0;   // c = binomial coefficient C(L, j)
+        for (uint32_t j = 0; j <= R.L; ++j) {
+            if (j >= R.T) tail += c * pow(q, (double)j) * pow(1.0 - q, (double)(R.L - j));
+            c = c * (double)(R.L - j) / (double)(j + 1);
+        }
+        expect = std::min((double)R.cap, (double)R.K + (double)R.N * tail);
+    }
+    expect += (double)(R.K * R.iterate);
+    R.est_units = (uint32_t)std::max(1.0, std::min(32.0, std::ceil(expect / (4.0 * kFinNT))));
     // subtraction round: phased values [K], sort keys [P], offsets [K], run starts [B] (16 bit)
     R.sub_lds = R.iterate ? ((R.K * 8u + P * 4u + R.K * 4u + R.B * 2u + 15u) & ~15u) : 0u;
     R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;
