@@ -40,7 +40,7 @@ struct SigDesc {
     uint64_t* keys;             // [cap (+ K with iteration)] ordering keys of the estimates
     double* rpart;              // [2 * resid_blocks] residual partial sums
     double* resid_own;          // [2] residual when the caller gives no buffer
-    uint32_t* ctr;              // [4] counters: 0 candidates, 1 residual blocks done, 2 first-round outputs
+    uint32_t* ctr;              // [4] counters: 0 candidates, 2 first-round outputs
     float2* ubuf;               // [L][B] two-pass FFT intermediate (B > kMaxFftLds only)
     uint32_t* cbits;            // [comb_loops][max(1, Bc/32)] residues kept by each comb loop
     uint32_t* gmax;             // [L][B/16] largest energy of each 16 consecutive DFT outputs (idem)
@@ -101,6 +101,7 @@ constexpr uint32_t kFoldNT = 256;
 constexpr uint32_t kFftNT = 256;
 constexpr uint32_t kFinNT = 256;
 constexpr uint32_t kResNT = 256;
+constexpr uint32_t kResSamples = 64;   // residual samples per workgroup (its waves split the tones)
 constexpr uint32_t kSubNT = 256;
 constexpr uint32_t kDecPerThread = 4;                     // decoded buckets per thread
 constexpr uint32_t kDecUnit = kVoteNT * kDecPerThread;    // decoded buckets per workgroup

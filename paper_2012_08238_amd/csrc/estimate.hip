@@ -659,14 +659,16 @@ __global__ __launch_bounds__(kSubNT) void subtract_kernel(Launch a) {
 
 // ---------------------------------------------------------------- FP64 residual
 // E_res = mean_t |x_t - sum_k v_k e^{+2 pi i (t f_k mod N)/N}|^2 and
-// E_in = mean_t |x_t|^2 over the S residual samples. The outputs are staged in
-// LDS (dynamic: K values, K frequencies); the phase of the exact integer
-// t f mod N is evaluated in FP64 (phase_of). Partial sums are reduced in a
-// fixed order by the last workgroup to finish.
+// E_in = mean_t |x_t|^2 over the S residual samples. A workgroup takes 64
+// samples; its four waves sum the model over every fourth output (wave w: k = w,
+// w+4, ...) for the same samples, and the four partial sums are added in wave
+// order. The outputs are staged in LDS (dynamic: K values, K frequencies); the
+// phase of the exact integer t f mod N is evaluated in FP64 (phase_of). Each
+// workgroup writes its two partial sums; residual_sum_kernel reduces them.
 __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
-    __shared__ double sh[2][kResNT / 64];
-    __shared__ uint32_t is_last;
+    constexpr uint32_t NW = kResNT / 64;
+    __shared__ double2 s_part[NW][kResSamples];
     __shared__ double2 s_rou[kRouMax];
     uint32_t sig, unit;
     resolve(a, sig, unit);
@@ -684,61 +686,84 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
         s_v[k] = gld(io.out_val + k);
     }
     __syncthreads();
-    const uint32_t j = unit * kResNT + threadIdx.x;
-    double ea = 0.0, eb = 0.0;
-    if (j < d.S) {
-        const uint32_t t = gld(d.tpos + j);
-        const float2 xv = gld(io.x + t);
-        const double xr = xv.x, xi = xv.y;
-        double mr = 0.0, mi = 0.0;
-        for (uint32_t k = 0; k < K; ++k) {
-            const uint32_t f = s_f[k];
-            if (f == 0xFFFFFFFFu) continue;   // padding (uniform across the block)
-            const double2 p = phase_of(s_rou, (t * f) & maskN, rsh, step);
-            const float2 v = s_v[k];
-            mr += (double)v.x * p.x - (double)v.y * p.y;
-            mi += (double)v.x * p.y + (double)v.y * p.x;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t j = unit * kResSamples + lane;
+    const bool valid = j < d.S;
+    const uint32_t t = valid ? gld(d.tpos + j) : 0u;
+    double mr = 0.0, mi = 0.0;
+#pragma unroll 2
+    for (uint32_t k = wv; k < K; k += NW) {
+        const uint32_t f = s_f[k];
+        if (f == 0xFFFFFFFFu) continue;   // padding (uniform across the wave)
+        const double2 p = phase_of(s_rou, (t * f) & maskN, rsh, step);
+        const float2 v = s_v[k];
+        mr += (double)v.x * p.x - (double)v.y * p.y;
+        mi += (double)v.x * p.y + (double)v.y * p.x;
+    }
+    s_part[wv][lane] = make_double2(mr, mi);
+    __syncthreads();
+    if (wv == 0) {
+        double ea = 0.0, eb = 0.0;
+        if (valid) {
+            double m_r = 0.0, m_i = 0.0;
+#pragma unroll
+            for (uint32_t w = 0; w < NW; ++w) {
+                m_r += s_part[w][lane].x;
+                m_i += s_part[w][lane].y;
+            }
+            const float2 xv = gld(io.x + t);
+            const double xr = xv.x, xi = xv.y;
+            const double er = xr - m_r, ei = xi - m_i;
+            ea = er * er + ei * ei;
+            eb = xr * xr + xi * xi;
         }
-        const double er = xr - mr, ei = xi - mi;
-        ea = er * er + ei * ei;
-        eb = xr * xr + xi * xi;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ea += __shfl_down(ea, off, 64);
+            eb += __shfl_down(eb, off, 64);
+        }
+        if (lane == 0) {
+            gst(d.rpart + 2 * unit, ea);
+            gst(d.rpart + 2 * unit + 1, eb);
+        }
+    }
+}
+
+// The residual's per-workgroup partial sums reduced in a fixed order (per
+// thread, a shuffle tree, then the waves in order) into the two outputs. One
+// workgroup per signal, launched after residual_kernel (the launch boundary
+// makes the partials visible; no device-wide fence per workgroup is needed).
+__global__ __launch_bounds__(kResNT) void residual_sum_kernel(Launch a) {
+    constexpr uint32_t NW = kResNT / 64;
+    __shared__ double2 s_red[NW];
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    const IoDesc io = io_of(a, sig);
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const double* rp = d.rpart;
+    double A = 0.0, Bs = 0.0;   // thread i: partials i, i + 256, ... in order
+    for (uint32_t u = threadIdx.x; u < d.resid_blocks; u += kResNT) {
+        A += gld(rp + 2 * u);
+        Bs += gld(rp + 2 * u + 1);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        ea += __shfl_down(ea, off, 64);
-        eb += __shfl_down(eb, off, 64);
+        A += __shfl_down(A, off, 64);
+        Bs += __shfl_down(Bs, off, 64);
     }
-    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        sh[0][wid] = ea;
-        sh[1][wid] = eb;
-    }
+    if (lane == 0) s_red[wv] = make_double2(A, Bs);
     __syncthreads();
     if (threadIdx.x == 0) {
-        double A = 0.0, Bs = 0.0;
+        double tA = 0.0, tB = 0.0;
 #pragma unroll
-        for (int w = 0; w < kResNT / 64; ++w) {
-            A += sh[0][w];
-            Bs += sh[1][w];
-        }
-        gst(d.rpart + 2 * unit, A);
-        gst(d.rpart + 2 * unit + 1, Bs);
-        __threadfence();
-        const uint32_t prev = atomicAdd(d.ctr + 1, 1u);
-        is_last = (prev + 1u == d.resid_blocks) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (is_last && threadIdx.x == 0) {
-        __threadfence();
-        const volatile double* rp = d.rpart;
-        double A = 0.0, Bs = 0.0;
-        for (uint32_t u = 0; u < d.resid_blocks; ++u) {
-            A += rp[2 * u];
-            Bs += rp[2 * u + 1];
+        for (uint32_t w = 0; w < NW; ++w) {
+            tA += s_red[w].x;
+            tB += s_red[w].y;
         }
         double* out = io.out_resid ? io.out_resid : d.resid_own;
-        gst(out + 0, A / (double)d.S);
-        gst(out + 1, Bs / (double)d.S);
+        gst(out + 0, tA / (double)d.S);
+        gst(out + 1, tB / (double)d.S);
     }
 }
 
@@ -792,6 +817,11 @@ hipError_t set_estimate_attributes() {
 
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {
     hipLaunchKernelGGL(residual_kernel, dim3(units), dim3(kResNT), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_sum(const Launch& a, uint32_t units, hipStream_t s) {
+    hipLaunchKernelGGL(residual_sum_kernel, dim3(units), dim3(kResNT), 0, s, a);
     return hipGetLastError();
 }
 

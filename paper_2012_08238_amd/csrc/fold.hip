@@ -20,7 +20,6 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_kernel(Launch a) {
     const float2* x = io_of(a, sig).x;
     if (unit == 0 && threadIdx.x == 0) {
         gst(d.ctr + 0, 0u);
-        gst(d.ctr + 1, 0u);
     }
     const uint32_t log2C = d.log2C, C = 1u << log2C, R = d.M, B = d.B, log2B = d.log2B;
     const uint32_t col0 = unit << log2C;
@@ -94,7 +93,6 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
     const float2* x = io_of(a, sig).x;
     if (unit == 0 && threadIdx.x == 0) {
         gst(d.ctr + 0, 0u);
-        gst(d.ctr + 1, 0u);
     }
     const uint32_t log2C = d.log2C, C = 1u << log2C, R = d.M, B = d.B, log2B = d.log2B;
     const uint32_t col0 = unit << log2C;
@@ -202,7 +200,6 @@ __global__ __launch_bounds__(kFoldNT) void fold_gather_kernel(Launch a) {
     const float2* x = io_of(a, sig).x;
     if (unit == 0 && threadIdx.x == 0) {
         gst(d.ctr + 0, 0u);
-        gst(d.ctr + 1, 0u);
     }
     const uint32_t log2B = d.log2B, B = d.B;
     const uint32_t it = unit * kFoldNT + threadIdx.x;

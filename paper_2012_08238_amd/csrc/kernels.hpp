@@ -37,6 +37,8 @@ hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds_bytes, 
 // selection of the residual buckets: one workgroup per (signal, loop); every signal has B = 2^log2B <= 16384
 hipError_t launch_reselect(const Launch& a, uint32_t log2B, uint32_t units, hipStream_t s);
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
+// the residual's partial sums into the outputs: one workgroup per signal, after launch_residual
+hipError_t launch_residual_sum(const Launch& a, uint32_t units, hipStream_t s);
 // raises the dynamic-LDS limit of the kernels that use more than 64 KB
 hipError_t set_kernel_attributes_impl();
 hipError_t set_fold_attributes();

@@ -204,7 +204,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         R.fft_p1_units = R.L * ((1u << lb2) / 16u);
         R.fft_p2_units = R.L * ((1u << lb1) / 16u);
     }
-    R.resid_blocks = (R.S + kResNT - 1) / kResNT;
+    R.resid_blocks = (R.S + kResSamples - 1) / kResSamples;
     uint32_t P = 1;
     while (P < R.K) P <<= 1;
     R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies

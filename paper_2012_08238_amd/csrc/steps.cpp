@@ -18,9 +18,9 @@ size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // two-pass fft: 3 per size; comb prefilter: one per comb size (2^1 .. 2^14);
     // per round: vote 2 x kLmaxCount, phase decode 1, estimate kLmaxCount, top-K 1;
-    // subtraction 1, reselection kFftLog2Max; residual 1
+    // subtraction 1, reselection kFftLog2Max; residual and its sum 2
     const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + kFftLog2Max +
-                            2 * (3 * kLmaxCount + 2) + 1 + kFftLog2Max + 1;
+                            2 * (3 * kLmaxCount + 2) + 1 + kFftLog2Max + 2;
     return launches * (n + 1);
 }
 
@@ -91,6 +91,7 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
     }
     add_step(kStepRes, 0, max_of([](const Resolved& R) { return R.S > 0; }, [](const Resolved& R) { return R.resid_lds; }),
              [&](const Resolved& R) { return R.S ? R.resid_blocks : 0u; });
+    add_step(kStepResSum, 0, 0, [&](const Resolved& R) { return R.S ? 1u : 0u; });
 }
 
 hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, const IoDesc* d_ios,
@@ -114,6 +115,7 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
             case kStepSub: e = launch_subtract(a, st.units, st.lds, s); break;
             case kStepReselect: e = launch_reselect(a, st.param, st.units, s); break;
             case kStepRes: e = launch_residual(a, st.units, st.lds, s); break;
+            case kStepResSum: e = launch_residual_sum(a, st.units, s); break;
             case kStepFftLarge: e = launch_fft_large(a, st.param & 255u, st.param >> 8, st.units, s); break;
             case kStepComb: e = launch_comb(a, st.param, st.units, s); break;
         }

@@ -14,7 +14,7 @@ namespace sfft {
 
 enum StepKind : uint32_t {
     kStepFold = 0, kStepFft = 1, kStepVote = 2, kStepFin = 3, kStepRes = 4, kStepFftLarge = 5, kStepComb = 6,
-    kStepSub = 7, kStepReselect = 8, kStepEst = 9, kStepDecode = 10
+    kStepSub = 7, kStepReselect = 8, kStepEst = 9, kStepDecode = 10, kStepResSum = 11
 };
 
 struct Step {
