@@ -7,7 +7,9 @@ L = 9 random bucketizations, window w = 8B = 131072, 2K buckets kept per loop,
 strict-majority vote, median estimate, FP64 residual on 4096 samples.
 A step is one pass of the whole path over a batch of signals resident in HBM
 (one HIP graph replay: bucketization, FFT + selection, votes, estimation and
-output, residual). value = signals recovered per second.
+output, residual); two steps are kept in flight on two streams with their own
+workspaces and outputs, so one step's last stages overlap the next step's
+bucketization. value = signals recovered per second.
 
 Also reported: the bucketization kernel's roofline against MI355X HBM peak
 (algorithmic bytes 8 N (1 - (1 - w/N)^L) per signal, the sampled fraction of
@@ -554,7 +556,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64, help="signals per step (64 x 32 MB = 2 GB, beyond the 256 MB cache)")
     ap.add_argument("--latency-runs", type=int, default=100)
@@ -566,6 +568,7 @@ def main() -> int:
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
     ap.add_argument("--single-passes", type=int, default=3, help="passes over the batch through sfft_execute alone")
     ap.add_argument("--branches", type=int, default=4, help="parallel stream branches of the batch graph")
+    ap.add_argument("--inflight", type=int, default=2, help="steps in flight (batches alternating over streams)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="duration of the Poisson serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-burst", type=int, default=1024, help="requests of the saturated serving run")
@@ -625,24 +628,40 @@ def main() -> int:
     print(f"# setup {time.perf_counter() - t_setup:.1f}s: {M} signals of N=2^22 resident, "
           f"fold_mode={desc['fold_mode']} strip_cols={desc['strip_cols']}", file=sys.stderr, flush=True)
 
+    # steps in flight: consecutive steps alternate over `inflight` batches (own workspaces and
+    # outputs) on their own streams, so one step's last stages overlap the next step's
+    # bucketization; every step still runs every stage over all M signals
+    nf = max(1, args.inflight)
+    batches, outsets, streams = [batch], [(idxs, vals, ress)], [torch.cuda.current_stream()]
+    for _ in range(nf - 1):
+        batches.append(S.Batch([plan] * M, branches=args.branches))
+        oi = torch.empty((M, K), dtype=torch.int64, device=dev)
+        ov = torch.empty((M, K), dtype=torch.complex64, device=dev)
+        orr = torch.empty((M, 2), dtype=torch.float64, device=dev)
+        outsets.append(([oi[i] for i in range(M)], [ov[i] for i in range(M)], [orr[i] for i in range(M)]))
+        streams.append(torch.cuda.Stream(device=dev))
     for _ in range(args.warmup):
-        batch.run(xs, idxs, vals, ress)
+        for j in range(nf):
+            batches[j].run(xs, *outsets[j], stream=streams[j])
     torch.cuda.synchronize()
     from paper_2012_08238_amd._hip import HipEvent
     ev = [(HipEvent(), HipEvent()) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        if args.branches == 1:
+        if args.branches == 1 and nf == 1:
             batch.run_timed(xs, idxs, vals, ress, ev[k][0], ev[k][1])
         else:
-            batch.run(xs, idxs, vals, ress)
+            j = k % nf
+            batches[j].run(xs, *outsets[j], stream=streams[j])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    for b_ in batches[1:]:
+        b_.close()
     launch_source = "bucketization launches of the timed steps"
-    if args.branches > 1:
-        # the branched graph runs each group's bucketization beside other stages:
+    if args.branches > 1 or nf > 1:
+        # branches and steps in flight run the bucketization beside other stages:
         # time the kernel over the whole batch in an unbranched graph instead
         kb = S.Batch([plan] * M)
         kb.run(xs, idxs, vals, ress)
@@ -764,7 +783,8 @@ def main() -> int:
         "config": {"workload": f"sFFT N=2^22 K=100 SNR20dB B=16384 L=9 w={W}, batch of resident signals",
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
-                   "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "parallelism": "single-gpu"},
+                   "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "steps_in_flight": nf,
+                   "parallelism": "single-gpu"},
         "latency": ({"p50_ms": serving["poisson"]["p50_ms"], "p99_ms": serving["poisson"]["p99_ms"],
                      "source": f"serving loop, Poisson arrivals at {serving['poisson']['rate_req_s']:.0f} req/s, "
                                "submission to completion"} if serving else None),
