@@ -7,9 +7,10 @@ L = 9 random bucketizations, window w = 8B = 131072, 2K buckets kept per loop,
 strict-majority vote, median estimate, FP64 residual on 4096 samples.
 A step is one pass of the whole path over a batch of signals resident in HBM
 (one HIP graph replay: bucketization, FFT + selection, votes, estimation and
-output, residual); two steps are kept in flight on two streams with their own
-workspaces and outputs, so one step's last stages overlap the next step's
-bucketization. value = signals recovered per second.
+output, residual); three steps are kept in flight on three streams with their
+own workspaces and outputs, so one step's last stages overlap the next step's
+bucketization, and the B-point FFT runs in two passes of small workgroups that
+can share compute units with it. value = signals recovered per second.
 
 Also reported: the bucketization kernel's roofline against MI355X HBM peak
 (algorithmic bytes 8 N (1 - (1 - w/N)^L) per signal, the sampled fraction of
@@ -80,6 +81,7 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     srv = S.Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_inflight=args.serve_inflight,
                    n_streams=args.serve_streams)
     fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
+    fflags |= S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" else 0
     h = srv.prepare(S.PlanParams(N, K, B, L, args.w_over_b * B, seed=PLAN_SEED, strip_cols=args.strip_cols,
                                  flags=fflags))
     n = max(1, int(args.serve_rate * args.serve_seconds))
@@ -184,7 +186,7 @@ def comb_measure(S, torch, dev, args) -> dict:
             cache[(n, k)] = [make_signal_torch(n, k, 20.0, derive_seed(70, i), dev) for i in range(m)]
         sigs = cache[(n, k)]
         plan = S.Plan(n, k, b, l, 8 * b, seed=13, comb_b=cb, comb_loops=cl)
-        bt = S.Batch([plan] * m, branches=args.branches)
+        bt = S.Batch([plan] * m, branches=args.section_branches)
         outs = [plan.outputs(dev) for _ in range(m)]
         xs = [q[0] for q in sigs]
         for _ in range(2):
@@ -225,7 +227,7 @@ def iterate_measure(S, torch, dev, args) -> dict:
         row = {"N": n, "K": k, "B": b, "L": l, "w": 8 * b, "snr_db": 20.0, "batch": m}
         for tag, fl in (("plain", 0), ("iterate", S.SFFT_FLAG_ITERATE)):
             plan = S.Plan(n, k, b, l, 8 * b, seed=17, flags=fl)
-            bt = S.Batch([plan] * m, branches=args.branches)
+            bt = S.Batch([plan] * m, branches=args.section_branches)
             outs = [plan.outputs(dev) for _ in range(m)]
             for _ in range(2):
                 bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
@@ -265,7 +267,7 @@ def phase_measure(S, torch, dev, args) -> dict:
     out = {"N": n, "K": k, "snr_db": None, "batch": m}
     for name, b, l, fl in runs:
         plan = S.Plan(n, k, b, l, 8 * b, seed=19, flags=fl)
-        bt = S.Batch([plan] * m, branches=args.branches)
+        bt = S.Batch([plan] * m, branches=args.section_branches)
         outs = [plan.outputs(dev) for _ in range(m)]
         for _ in range(2):
             bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
@@ -308,7 +310,7 @@ def est_loops_measure(S, torch, dev, args) -> dict:
         sigs = cache[(n, k)]
         xs = [q[0] for q in sigs]
         plan = S.Plan(n, k, b, l, 8 * b, seed=23, est_loops=el, est_B=eb)
-        bt = S.Batch([plan] * m, branches=args.branches)
+        bt = S.Batch([plan] * m, branches=args.section_branches)
         outs = [plan.outputs(dev) for _ in range(m)]
         for _ in range(2):
             bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
@@ -399,7 +401,7 @@ def k_sweep_measure(S, torch, dev, args) -> dict:
         sigs = [make_signal_torch(N, k, SNR_DB, derive_seed(150 + k, i), dev) for i in range(m)]
         xs = [q[0] for q in sigs]
         plan = S.Plan(N, k, b, L, 8 * b, seed=29)
-        bt = S.Batch([plan] * m, branches=args.branches)
+        bt = S.Batch([plan] * m, branches=args.section_branches)
         outs = [plan.outputs(dev) for _ in range(m)]
         for _ in range(2):
             bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
@@ -519,7 +521,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
         x, f, _ = make_signal_torch(n, k, snr, derive_seed(40, i), dev)
         xs.append(x)
         truth.append(f)
-    b = S.Batch(plans, branches=args.branches)
+    b = S.Batch(plans, branches=args.section_branches)
     outs = [p.outputs(dev) for p in plans]
     idx, val, res = [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs]
     setup = time.perf_counter() - t0
@@ -565,10 +567,14 @@ def main() -> int:
     ap.add_argument("--strip-cols", type=int, default=0, help="bucketization tile width (0 = plan default)")
     ap.add_argument("--w-over-b", type=int, default=8, help="window length w as a multiple of B")
     ap.add_argument("--fold", choices=["auto", "strip", "gather"], default="auto", help="bucketization form")
+    ap.add_argument("--fft", choices=["two-pass", "one-workgroup"], default="two-pass",
+                    help="B-point FFT form of the step's plan (two passes of small workgroups share compute units "
+                         "with the next step's bucketization)")
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
     ap.add_argument("--single-passes", type=int, default=3, help="passes over the batch through sfft_execute alone")
-    ap.add_argument("--branches", type=int, default=4, help="parallel stream branches of the batch graph")
-    ap.add_argument("--inflight", type=int, default=2, help="steps in flight (batches alternating over streams)")
+    ap.add_argument("--branches", type=int, default=1, help="parallel stream branches of the step's batch graph")
+    ap.add_argument("--inflight", type=int, default=3, help="steps in flight (batches alternating over streams)")
+    ap.add_argument("--section-branches", type=int, default=4, help="graph branches of the other sections' batches")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="duration of the Poisson serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-burst", type=int, default=1024, help="requests of the saturated serving run")
@@ -617,7 +623,8 @@ def main() -> int:
     W = args.w_over_b * B
     fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
     plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols,
-                  flags=fflags | (S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0))
+                  flags=fflags | (S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0) |
+                  (S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" else 0))
     desc = plan.desc
     batch = S.Batch([plan] * M, branches=args.branches)
     idx = torch.empty((M, K), dtype=torch.int64, device=dev)
@@ -784,6 +791,7 @@ def main() -> int:
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
                    "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "steps_in_flight": nf,
+                   "fft": args.fft,
                    "parallelism": "single-gpu"},
         "latency": ({"p50_ms": serving["poisson"]["p50_ms"], "p99_ms": serving["poisson"]["p99_ms"],
                      "source": f"serving loop, Poisson arrivals at {serving['poisson']['rate_req_s']:.0f} req/s, "

@@ -21,6 +21,7 @@ SFFT_FLAG_XCD_ORDER = 0x8
 SFFT_FLAG_MEAN_ESTIMATE = 0x10
 SFFT_FLAG_ITERATE = 0x20
 SFFT_FLAG_PHASE_LOCATION = 0x40
+SFFT_FLAG_FFT_TWO_PASS = 0x80
 
 
 class Params(C.Structure):

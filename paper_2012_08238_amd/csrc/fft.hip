@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void fft_large_p1_kernel(Launch a) {
     float2* y = d.ubuf + (size_t)r * C::B;
     const float2* tw = d.tw;
     constexpr int NE = 16 * C::B1 / C::NT;   // values per thread
-    constexpr int CHK = 8;
+    constexpr int CHK = NE < 8 ? NE : 8;
     static_assert(NE % CHK == 0, "load chunks");
 #pragma unroll
     for (int q0 = 0; q0 < NE; q0 += CHK) {
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(256) void fft_large_p2_kernel(Launch a) {
     float2* V = d.uhat + (size_t)r * C::B;
     uint32_t* gm = d.gmax + (size_t)r * C::G;
     constexpr int NE = 16 * C::B2 / C::NT;
-    constexpr int CHK = 8;
+    constexpr int CHK = NE < 8 ? NE : 8;
     static_assert(NE % CHK == 0, "load chunks");
 #pragma unroll
     for (int q0 = 0; q0 < NE; q0 += CHK) {
@@ -788,18 +788,23 @@ __global__ __launch_bounds__(1024) void select_large_kernel(Launch a) {
     }
     __syncthreads();
     // bitmap out; buckets in ascending order into jlist
-    constexpr int WPT = NW / NT;
-    static_assert(WPT >= 1 && NW % NT == 0, "bitmap words per thread");
+    // WPT words per thread (B < 32 NT: the first NW threads hold one word each)
+    constexpr int WPT = NW >= NT ? NW / NT : 1;
+    static_assert(NW % WPT == 0 && (NW >= NT ? NW % NT == 0 : true), "bitmap words per thread");
     uint32_t* jb = d.jbits + (size_t)r * NW;
     uint32_t* jl = d.jlist + (size_t)r * dK;
     uint32_t wv[WPT], cnt = 0;
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
-        wv[q] = bits[threadIdx.x * WPT + q];
+        const uint32_t wi = threadIdx.x * WPT + q;
+        wv[q] = wi < (uint32_t)NW ? bits[wi] : 0u;
         cnt += (uint32_t)__popc(wv[q]);
     }
 #pragma unroll
-    for (int q = 0; q < WPT; ++q) gst(jb + threadIdx.x * WPT + q, wv[q]);
+    for (int q = 0; q < WPT; ++q) {
+        const uint32_t wi = threadIdx.x * WPT + q;
+        if (wi < (uint32_t)NW) gst(jb + wi, wv[q]);
+    }
     uint32_t tot;
     uint32_t pos = block_excl_scan<NT>(cnt, scan, tot);
 #pragma unroll
@@ -923,6 +928,9 @@ hipError_t launch_large_t(const Launch& a, uint32_t pass, uint32_t units, hipStr
 
 hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint32_t units, hipStream_t s) {
     switch (log2B) {
+        case 12: return launch_large_t<12>(a, pass, units, s);
+        case 13: return launch_large_t<13>(a, pass, units, s);
+        case 14: return launch_large_t<14>(a, pass, units, s);
         case 15: return launch_large_t<15>(a, pass, units, s);
         case 16: return launch_large_t<16>(a, pass, units, s);
         case 17: return launch_large_t<17>(a, pass, units, s);
@@ -933,6 +941,9 @@ hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint
 
 hipError_t set_fft_attributes() {
     hipError_t e;
+    if ((e = set_large_attr<12>()) != hipSuccess) return e;
+    if ((e = set_large_attr<13>()) != hipSuccess) return e;
+    if ((e = set_large_attr<14>()) != hipSuccess) return e;
     if ((e = set_large_attr<15>()) != hipSuccess) return e;
     if ((e = set_large_attr<16>()) != hipSuccess) return e;
     if ((e = set_large_attr<17>()) != hipSuccess) return e;

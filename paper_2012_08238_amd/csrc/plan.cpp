@@ -56,6 +56,13 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         *err = "phase-encoding location needs B <= 16384";
         return SFFT_E_UNSUPPORTED;
     }
+    if (p.flags & SFFT_FLAG_FFT_TWO_PASS) {
+        if (p.B < 4096 || p.B > kMaxFftLds) return bad("FFT_TWO_PASS applies to 4096 <= B <= 16384");
+        if (p.flags & (SFFT_FLAG_ITERATE | SFFT_FLAG_PHASE_LOCATION)) {
+            *err = "the two-pass FFT combines with neither the subtraction round nor phase location";
+            return SFFT_E_UNSUPPORTED;
+        }
+    }
     if (p.est_loops < 0 || p.est_loops > kMaxL - p.L) return bad("est_loops must be in [0, 32 - L]");
     if (p.est_loops > 0) {
         if (p.est_B < 2 || !is_pow2((uint64_t)p.est_B) || p.N / p.est_B < 2 || p.est_B < p.K)
@@ -198,7 +205,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.vote_lds = vbytes <= 65536u ? vbytes : 0u;
     // B-point FFT: in one workgroup's LDS up to kMaxFftLds, else two passes
     // (B = B1 * B2, tiles of 16 sequences per workgroup) and a selection workgroup per loop
-    R.fft_mode = R.B > (uint32_t)kMaxFftLds ? 1u : 0u;
+    R.fft_mode = (R.B > (uint32_t)kMaxFftLds || (p.flags & SFFT_FLAG_FFT_TWO_PASS)) ? 1u : 0u;
     if (R.fft_mode) {
         const uint32_t lb1 = (R.log2B + 1) / 2, lb2 = R.log2B / 2;
         R.fft_p1_units = R.L * ((1u << lb2) / 16u);

@@ -10,7 +10,8 @@ namespace sfft {
 
 namespace {
 constexpr uint32_t kFftLog2Max = 14;   // one-workgroup FFT sizes 2^1 .. 2^14
-constexpr uint32_t kLargeLog2Max = 18; // two-pass FFT sizes 2^15 .. 2^18, three launches each
+constexpr uint32_t kLargeLog2Min = 12; // two-pass FFT sizes 2^12 .. 2^18 (below 2^15 on request), three launches each
+constexpr uint32_t kLargeLog2Max = 18;
 constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
 }  // namespace
 
@@ -19,7 +20,7 @@ size_t max_prefix_entries(size_t n) {
     // two-pass fft: 3 per size; comb prefilter: one per comb size (2^1 .. 2^14);
     // per round: vote 2 x kLmaxCount, phase decode 1, estimate kLmaxCount, top-K 1;
     // subtraction 1, reselection kFftLog2Max; residual and its sum 2
-    const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kFftLog2Max) + kFftLog2Max +
+    const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kLargeLog2Min + 1) + kFftLog2Max +
                             2 * (3 * kLmaxCount + 2) + 1 + kFftLog2Max + 2;
     return launches * (n + 1);
 }
@@ -54,11 +55,11 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
         add_step(kStepFold, v, lds, [&](const Resolved& R) { return R.fold_variant == v ? R.fold_units : 0u; });
     }
     for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)
-        add_step(kStepFft, lb, 0, [&](const Resolved& R) { return R.log2B == lb ? R.L : 0u; });
+        add_step(kStepFft, lb, 0, [&](const Resolved& R) { return !R.fft_mode && R.log2B == lb ? R.L : 0u; });
     for (uint32_t pass = 0; pass < 3; ++pass)
-        for (uint32_t lb = kFftLog2Max + 1; lb <= kLargeLog2Max; ++lb)
+        for (uint32_t lb = kLargeLog2Min; lb <= kLargeLog2Max; ++lb)
             add_step(kStepFftLarge, lb | (pass << 8), 0, [&](const Resolved& R) {
-                if (R.log2B != lb) return 0u;
+                if (!R.fft_mode || R.log2B != lb) return 0u;
                 return pass == 0 ? R.fft_p1_units : (pass == 1 ? R.fft_p2_units : R.L);
             });
     for (uint32_t lb = 1; lb <= kFftLog2Max; ++lb)

@@ -89,3 +89,17 @@ def test_large_b_in_batch(dev):
     b.close()
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("N,K,B,L", [(1 << 20, 50, 4096, 7), (1 << 20, 60, 8192, 5), (1 << 22, 100, 16384, 9)])
+def test_two_pass_fft_below_2_15(dev, N, K, B, L):
+    """The two-pass FFT on request for 4096 <= B <= 16384: same parity bar as the
+    one-workgroup form, and the same support as it."""
+    import paper_2012_08238_amd as S
+    sig = make_signal(N, K, 20.0, seed=320 + L)
+    g = _run(dev, sig.x, K=K, B=B, L=L, w=8 * B, seed=7, flags=S.SFFT_FLAG_FFT_TWO_PASS)
+    one = _run(dev, sig.x, K=K, B=B, L=L, w=8 * B, seed=7)
+    r = _oracle(sig.x, K, B, L, 8 * B, 7)
+    compare(g, r, K, B, L, 8 * B, 7)
+    check_residual(g, sig.x, r.trace["tpos"])
+    assert np.array_equal(g["idx"], one["idx"])

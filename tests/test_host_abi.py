@@ -106,6 +106,19 @@ def test_est_loops_perms_and_validation():
     S.host_tables(S.PlanParams(**dict(base, L=16), est_loops=16, est_B=64))   # 32 loops in all
 
 
+def test_two_pass_fft_validation():
+    base = dict(N=1 << 20, K=50, L=5, flags=S.SFFT_FLAG_FFT_TWO_PASS)
+    for B in (4096, 8192, 16384):
+        S.host_tables(S.PlanParams(**base, B=B, w=8 * B, n_resid=8))
+    with pytest.raises(S.SfftError) as e:
+        S.host_tables(S.PlanParams(**base, B=2048, w=16384))
+    assert e.value.status == _capi.SFFT_E_INVALID
+    with pytest.raises(S.SfftError) as e:
+        S.host_tables(S.PlanParams(N=1 << 20, K=50, L=5, B=4096, w=32768,
+                                   flags=S.SFFT_FLAG_FFT_TWO_PASS | S.SFFT_FLAG_ITERATE))
+    assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+
+
 def test_iterate_validation_and_gain():
     # the subtraction round runs with the one-workgroup FFT only
     with pytest.raises(S.SfftError) as e:
