@@ -209,3 +209,27 @@ def test_iterate_deterministic(dev):
     for u, v in zip(a, b):
         assert torch.equal(u, v)
     p.close()
+
+
+def test_iterate_max_sizes(dev):
+    """K = 4096 at B = 16384 (the subtraction's LDS at its 96 KB bound, sort of 4096 keys):
+    the first round is bitwise the plan without the round, the outputs are valid and
+    deterministic, and the residual buckets match the oracle's when the first rounds agree."""
+    N, K, B, L, w = 1 << 16, 4096, 16384, 5, 32768
+    sig = make_signal(N, K, 30.0, seed=77)
+    kw = dict(K=K, B=B, L=L, w=w, seed=1, n_resid=500)
+    g = _run(dev, sig.x, **kw)
+    g2 = _run(dev, sig.x, **kw)
+    plain = _run(dev, sig.x, iterate=False, **kw)
+    assert np.array_equal(g["idx"], g2["idx"]) and np.array_equal(g["val"], g2["val"])
+    n1 = int(np.sum(plain["idx"] >= 0))
+    assert np.array_equal(g["trace"]["rec_idx"], plain["idx"][:n1])
+    ok = g["idx"] >= 0
+    got = g["idx"][ok]
+    assert np.all(np.diff(got) > 0) and np.all(g["idx"][~ok] == -1) and np.all(g["val"][~ok] == 0)
+    r = O.sfft(sig.x.astype(np.complex64).astype(np.complex128), K, B, L, w, seed=1, n_resid=500, iterate=True)
+    if np.array_equal(g["trace"]["rec_idx"], r.trace["idx1"][r.trace["idx1"] >= 0]):
+        for rr in range(L):
+            scale = np.max(np.abs(r.trace["uhat"][rr]))
+            assert np.max(np.abs(g["trace"]["uhat"][rr] - r.trace["ures"][rr])) <= RES_TOL * scale
+    check_residual(g, sig.x, r.trace["tpos"])

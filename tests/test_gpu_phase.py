@@ -215,3 +215,15 @@ def test_phase_in_batch_bitwise(dev):
         batch.close()
     for p in plans:
         p.close()
+
+
+def test_phase_sixteen_pairs(dev):
+    """L = 32 (16 pairs, the loop maximum) with the subtraction round."""
+    N, K, B, L, w = 1 << 16, 200, 2048, 32, 16384
+    sig = make_signal(N, K, None, seed=78)
+    for it in (False, True):
+        g = _run(dev, sig.x, iterate=it, K=K, B=B, L=L, w=w, seed=2, n_resid=500)
+        r = O.sfft(sig.x.astype(np.complex64).astype(np.complex128), K, B, L, w, seed=2, n_resid=500,
+                   location="phase", iterate=it)
+        compare_phase(g, r, K, B, L, N, it)
+        check_residual(g, sig.x, r.trace["tpos"])
