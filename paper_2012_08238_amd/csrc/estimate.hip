@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
             const uint32_t p = ((h << log2M) - (M >> 1) + (ci & (M - 1u))) & maskN;
             f = (sinv0 * p) & maskN;
             // all L bitmap tests issued together (no serial chain); bit r of `votes`
-            // is set when loop r selected the bucket of f (loop r0 always did)
+            // is set when loop r selected the bucket of f (loop r0 always did; testing it
+            // too keeps the unrolled tests free of a per-loop predicate)
             uint32_t votes = 0;
 #pragma unroll
             for (int r = 0; r < LMAX; ++r) {
