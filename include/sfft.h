@@ -76,13 +76,6 @@ typedef enum {
                                          residual buckets, each recovered value is corrected by the combined
                                          residual estimate, and the K largest of both are returned.
                                          Requires B <= 16384 (else SFFT_E_UNSUPPORTED). */
-#define SFFT_FLAG_FFT_TWO_PASS 0x80u  /* take the B-point FFT in two passes through the workspace (the
-                                         form used for B > 16384) also for 4096 <= B <= 16384: small
-                                         workgroups that can share a compute unit with other work instead
-                                         of one workgroup holding the whole transform in LDS. Results equal
-                                         the one-workgroup form to FP32 rounding. Not combinable with
-                                         SFFT_FLAG_ITERATE or SFFT_FLAG_PHASE_LOCATION (SFFT_E_UNSUPPORTED);
-                                         other B: SFFT_E_INVALID. */
 #define SFFT_FLAG_PHASE_LOCATION 0x40u /* locate by phase encoding (the sFFT3.0 row of Table 1, phase
                                          encoding method) instead of voting: L is even and loops 2j, 2j+1
                                          form a pair with sigma_{2j+1} = sigma_{2j}, tau_{2j+1} = tau_{2j}+1
@@ -94,6 +87,13 @@ typedef enum {
                                          estimated from the loops of the pairs that decode it only. With
                                          SFFT_FLAG_ITERATE the recovered values are kept and the residual is
                                          decoded for new frequencies. Requires B <= 16384. */
+#define SFFT_FLAG_FFT_TWO_PASS 0x80u  /* take the B-point FFT in two passes through the workspace (the
+                                         form used for B > 16384) also for 4096 <= B <= 16384: small
+                                         workgroups that can share a compute unit with other work instead
+                                         of one workgroup holding the whole transform in LDS. Results equal
+                                         the one-workgroup form to FP32 rounding. Not combinable with
+                                         SFFT_FLAG_ITERATE or SFFT_FLAG_PHASE_LOCATION (SFFT_E_UNSUPPORTED);
+                                         other B: SFFT_E_INVALID. */
 
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {
@@ -138,7 +138,7 @@ typedef struct {
     int32_t K, B, L, d, T, n_resid;
     int32_t fold_mode;      /* 0 = gather, 1 = strip */
     int32_t strip_cols;
-    int64_t cand_cap;       /* capacity of the candidate list = (L-T+1)*d*K*N/B */
+    int64_t cand_cap;       /* capacity of the candidate list: (L-T+1)*d*K*N/B (votes), (L/2)*d*K (phase) */
     size_t table_bytes;     /* resident device tables */
     size_t workspace_bytes; /* one execution's device workspace */
     double sampled_fraction_expected; /* 1-(1-w/N)^L (Table 2, sFFT1.0 sampling, log N -> L) */
