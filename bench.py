@@ -521,16 +521,25 @@ def uneven_measure(S, torch, dev, args) -> dict:
         x, f, _ = make_signal_torch(n, k, snr, derive_seed(40, i), dev)
         xs.append(x)
         truth.append(f)
-    b = S.Batch(plans, branches=args.section_branches)
-    outs = [p.outputs(dev) for p in plans]
-    idx, val, res = [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs]
+    # steps in flight as in the main step: batches with their own workspaces and outputs
+    # alternate over streams
+    nf = max(1, args.uneven_inflight)
+    bs = [S.Batch(plans, branches=args.section_branches) for _ in range(nf)]
+    outsets = [[p.outputs(dev) for p in plans] for _ in range(nf)]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev) for _ in range(nf - 1)]
+    outs = outsets[0]
     setup = time.perf_counter() - t0
+
+    def run(j):
+        o = outsets[j]
+        bs[j].run(xs, [q[0] for q in o], [q[1] for q in o], [q[2] for q in o], stream=streams[j])
     for _ in range(2):
-        b.run(xs, idx, val, res)
+        for j in range(nf):
+            run(j)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.uneven_steps):
-        b.run(xs, idx, val, res)
+    for s in range(args.uneven_steps):
+        run(s % nf)
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
     rec = [len(set(o[0].cpu().numpy().tolist()) & set(f.tolist())) / k
@@ -543,10 +552,11 @@ def uneven_measure(S, torch, dev, args) -> dict:
     torch.cuda.synchronize()
     single = len(plans) / (time.perf_counter() - t2)
     nbytes = sum(n for n, _, _ in specs) * 8
-    b.close()
+    for b in bs:
+        b.close()
     for p in plans:
         p.close()
-    return {"signals": len(specs), "resident_bytes": nbytes, "steps": args.uneven_steps,
+    return {"signals": len(specs), "resident_bytes": nbytes, "steps": args.uneven_steps, "steps_in_flight": nf,
             "ms_per_step": round(el / args.uneven_steps * 1e3, 4),
             "signals_per_s": round(len(specs) * args.uneven_steps / el, 1),
             "single_signal_path_signals_per_s": round(single, 1),
@@ -596,7 +606,8 @@ def main() -> int:
     ap.add_argument("--ksweep-steps", type=int, default=5)
     ap.add_argument("--no-context", action="store_true", help="skip the copy-bandwidth and dense-FFT context")
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
-    ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--uneven-steps", type=int, default=60)
+    ap.add_argument("--uneven-inflight", type=int, default=2, help="steps in flight of the uneven batch")
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
                     help="autotuner JSON table for the uneven batch ('' = the untuned rule; missing classes are tuned)")
     args = ap.parse_args()
