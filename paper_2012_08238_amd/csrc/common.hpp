@@ -99,7 +99,8 @@ constexpr uint32_t kVotePerThread = 16;
 constexpr uint32_t kVoteUnit = kVoteNT * kVotePerThread;  // candidates per vote workgroup
 constexpr uint32_t kFoldNT = 256;
 constexpr uint32_t kFftNT = 256;
-constexpr uint32_t kFinNT = 256;
+constexpr uint32_t kFinNT = 256;   // estimation workgroups
+constexpr uint32_t kSelNT = 1024;  // top-K selection workgroup (one per signal)
 constexpr uint32_t kResNT = 256;
 constexpr uint32_t kResSamples = 64;   // residual samples per workgroup (its waves split the tones)
 constexpr uint32_t kSubNT = 256;

@@ -432,7 +432,7 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
 // With the subtraction round, round 0 keeps its K largest in the workspace
 // (rec_f, rec_v, count in ctr[2]) instead of the outputs; round 1 writes the
 // outputs.
-__global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t round) {
+__global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t round) {
     extern __shared__ f4v lds_raw[];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t bc[4];
@@ -456,9 +456,9 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
         const uint32_t lane = threadIdx.x & 63u;
         for (int pass = 0; pass < 8; ++pass) {
             const int shift = 56 - 8 * pass;
-            for (int i = threadIdx.x; i < 256; i += kFinNT) hist[i] = 0;
+            for (int i = threadIdx.x; i < 256; i += kSelNT) hist[i] = 0;
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
+            for (uint32_t i = threadIdx.x; i < n; i += kSelNT) {
                 const uint64_t key = gld(keys + i);
                 if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
             }
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
     }
     if (threadIdx.x == 0) bc[2] = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kFinNT) {
+    for (uint32_t i = threadIdx.x; i < n; i += kSelNT) {
         const uint64_t key = gld(keys + i);
         if (key <= thr) {
             const uint32_t pos = atomicAdd(&bc[2], 1u);
@@ -523,14 +523,14 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
     const uint32_t cnt = min(bc[2], K);
     uint32_t Q = 1;   // sort size: power of two >= cnt (<= P)
     while (Q < cnt) Q <<= 1;
-    for (uint32_t i = cnt + threadIdx.x; i < Q; i += kFinNT) {
+    for (uint32_t i = cnt + threadIdx.x; i < Q; i += kSelNT) {
         s_f[i] = 0xFFFFFFFFu;
         s_v[i] = make_float2(0.f, 0.f);
     }
     __syncthreads();
     for (uint32_t k = 2; k <= Q; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < Q; i += kFinNT) {
+            for (uint32_t i = threadIdx.x; i < Q; i += kSelNT) {
                 const uint32_t l = i ^ j;
                 if (l > i) {
                     const bool up = (i & k) == 0;
@@ -548,14 +548,14 @@ __global__ __launch_bounds__(kFinNT) void finalize_kernel(Launch a, uint32_t rou
         }
     }
     if (d.iterate && round == 0) {
-        for (uint32_t k = threadIdx.x; k < K; k += kFinNT) {
+        for (uint32_t k = threadIdx.x; k < K; k += kSelNT) {
             gst(d.rec_f + k, k < cnt ? s_f[k] : 0xFFFFFFFFu);
             gst(d.rec_v + k, k < cnt ? s_v[k] : make_float2(0.f, 0.f));
         }
         if (threadIdx.x == 0) gst(d.ctr + 2, cnt);
         return;
     }
-    for (uint32_t k = threadIdx.x; k < K; k += kFinNT) {
+    for (uint32_t k = threadIdx.x; k < K; k += kSelNT) {
         if (k < cnt) {
             gst(io.out_idx + k, (int64_t)s_f[k]);
             gst(io.out_val + k, s_v[k]);
@@ -799,7 +799,7 @@ hipError_t launch_estimate(const Launch& a, uint32_t lmax, uint32_t units, uint3
 }
 
 hipError_t launch_finalize(const Launch& a, uint32_t units, uint32_t lds, uint32_t round, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(units), dim3(kFinNT), lds, s, a, round);
+    hipLaunchKernelGGL(finalize_kernel, dim3(units), dim3(kSelNT), lds, s, a, round);
     return hipGetLastError();
 }
 
