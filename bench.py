@@ -81,7 +81,7 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     srv = S.Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_inflight=args.serve_inflight,
                    n_streams=args.serve_streams)
     fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
-    fflags |= S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" else 0
+    fflags |= S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" and 4096 <= B <= 16384 else 0
     h = srv.prepare(S.PlanParams(N, K, B, L, args.w_over_b * B, seed=PLAN_SEED, strip_cols=args.strip_cols,
                                  flags=fflags))
     n = max(1, int(args.serve_rate * args.serve_seconds))
@@ -566,7 +566,11 @@ def uneven_measure(S, torch, dev, args) -> dict:
 
 
 def main() -> int:
+    global N, K, B, L
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--shape", default="22,100,16384,9",
+                    help="log2 N, K, B, L of the step's workload (default: the metric's configuration; other "
+                         "shapes are for profiling the same path)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=5)
@@ -611,6 +615,9 @@ def main() -> int:
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
                     help="autotuner JSON table for the uneven batch ('' = the untuned rule; missing classes are tuned)")
     args = ap.parse_args()
+    ln, K, B, L = (int(v) for v in args.shape.split(","))
+    N = 1 << ln
+    metric_shape = (N, K, B, L) == (1 << 22, 100, 16384, 9)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding of this path is a design note, not a build", file=sys.stderr)
@@ -635,7 +642,7 @@ def main() -> int:
     fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
     plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols,
                   flags=fflags | (S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0) |
-                  (S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" else 0))
+                  (S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" and 4096 <= B <= 16384 else 0))
     desc = plan.desc
     batch = S.Batch([plan] * M, branches=args.branches)
     idx = torch.empty((M, K), dtype=torch.int64, device=dev)
@@ -643,7 +650,7 @@ def main() -> int:
     res = torch.empty((M, 2), dtype=torch.float64, device=dev)
     idxs, vals, ress = [idx[i] for i in range(M)], [val[i] for i in range(M)], [res[i] for i in range(M)]
     torch.cuda.synchronize()
-    print(f"# setup {time.perf_counter() - t_setup:.1f}s: {M} signals of N=2^22 resident, "
+    print(f"# setup {time.perf_counter() - t_setup:.1f}s: {M} signals of N=2^{ln} resident, "
           f"fold_mode={desc['fold_mode']} strip_cols={desc['strip_cols']}", file=sys.stderr, flush=True)
 
     # steps in flight: consecutive steps alternate over `inflight` batches (own workspaces and
@@ -750,7 +757,7 @@ def main() -> int:
 
     alg = alg_bytes_per_signal(W) * M
     achieved = alg / fold_avg_s / 1e9
-    traffic = committed_traffic(M)
+    traffic = committed_traffic(M) if metric_shape else None   # the counters cover the metric's shape
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "fold_strip_pf_kernel (bucketization)", "alg_bytes_per_launch": alg,
@@ -780,7 +787,7 @@ def main() -> int:
                 errs.append(float(np.max(np.abs(val_h[n][ok] - r.val[ok]) / np.abs(r.val[ok]))))
             n += 1
         cpu = {"value": round(n / tcpu, 4), "unit": "signals/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n} of the {M} benchmark signals (N=2^22, K=100), FP64 NumPy oracle, "
+               "sample": f"{n} of the {M} benchmark signals (N=2^{ln}, K={K}), FP64 NumPy oracle, "
                          f"single thread, {tcpu:.1f}s"}
         parity = {"signals": n, "support_equal": sup_eq,
                   "max_rel_value_err_fp32_vs_fp64": max(errs) if errs else None}
@@ -798,7 +805,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"sFFT N=2^22 K=100 SNR20dB B=16384 L=9 w={W}, batch of resident signals",
+        "config": {"workload": f"sFFT N=2^{ln} K={K} SNR20dB B={B} L={L} w={W}, batch of resident signals",
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
                    "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "steps_in_flight": nf,
