@@ -97,6 +97,9 @@ constexpr uint32_t kNumXcd = 8;  // MI355X: 8 accelerator complex dies, workgrou
 constexpr uint32_t kVoteNT = 256;
 constexpr uint32_t kVotePerThread = 16;
 constexpr uint32_t kVoteUnit = kVoteNT * kVotePerThread;  // candidates per vote workgroup
+// LDS words for the selected-bucket slots one vote workgroup enumerates (N/B = 2^log2M
+// candidates per slot), a multiple of 4 so the staged bitmaps after them stay 16-byte aligned
+__host__ __device__ constexpr uint32_t vote_slot_words(uint32_t log2M) { return ((kVoteUnit >> log2M) + 1u + 3u) & ~3u; }
 constexpr uint32_t kFoldNT = 256;
 constexpr uint32_t kFftNT = 256;
 constexpr uint32_t kFinNT = 256;   // estimation workgroups

@@ -45,9 +45,10 @@ __device__ __forceinline__ void append_wave(const uint32_t (&fv)[P], uint32_t em
 // In the subtraction round (round 1) the frequencies recovered by the first
 // round are not candidates again.
 template <int LMAX>
+// Dynamic LDS: the chunk's selected-bucket slots (vote_slot_words(log2 N/B) words), then
+// (staged) the L selected-bucket bitmaps.
 __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged, uint32_t round) {
-    extern __shared__ uint32_t sbits[];
-    __shared__ uint32_t s_slot[kVoteUnit / 2 + 1];   // selected buckets of this chunk (N/B >= 2)
+    extern __shared__ uint32_t sdyn[];
     __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
     uint32_t sig, unit;
     resolve(a, sig, unit);
@@ -65,6 +66,8 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     const uint32_t slot0 = start >> log2M;
     const uint32_t nslots = ((end - 1u) >> log2M) - slot0 + 1u;
     const uint32_t sinv0 = d.sigma_inv[r0];
+    uint32_t* s_slot = sdyn;
+    uint32_t* sbits = sdyn + vote_slot_words(log2M);
     const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
     for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
     uint32_t sg[LMAX];   // sigma_r, uniform: scalar loads
@@ -769,9 +772,8 @@ __global__ __launch_bounds__(kResNT) void residual_sum_kernel(Launch a) {
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t round,
-                       hipStream_t s) {
-    const uint32_t staged = lds_bytes ? 1u : 0u;
+hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t staged,
+                       uint32_t round, hipStream_t s) {
     switch (lmax) {
         case 4: hipLaunchKernelGGL(vote_kernel<4>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
         case 8: hipLaunchKernelGGL(vote_kernel<8>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
@@ -811,9 +813,18 @@ hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds, hipStr
 // largest subtraction LDS: K = 4096 (P = 4096), B = 16384
 constexpr int kSubLdsMax = kMaxK * 8 + kMaxK * 4 + kMaxK * 4 + kMaxFftLds * 2;
 
+// largest vote dynamic LDS: the slots at N/B = 2 plus 64 KB of staged bitmaps
+constexpr int kVoteLdsMax = (int)vote_slot_words(1) * 4 + 65536;
+
 hipError_t set_estimate_attributes() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&subtract_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kSubLdsMax);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&subtract_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kSubLdsMax);
+    const void* votes[4] = {reinterpret_cast<const void*>(&vote_kernel<4>), reinterpret_cast<const void*>(&vote_kernel<8>),
+                            reinterpret_cast<const void*>(&vote_kernel<16>),
+                            reinterpret_cast<const void*>(&vote_kernel<32>)};
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        e = hipFuncSetAttribute(votes[i], hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsMax);
+    return e;
 }
 
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {

@@ -203,6 +203,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     const uint32_t wpl = (R.B + 31) / 32;
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
     R.vote_lds = vbytes <= 65536u ? vbytes : 0u;
+    R.vote_dyn_lds = vote_slot_words(R.log2M) * 4u + R.vote_lds;
     // B-point FFT: in one workgroup's LDS up to kMaxFftLds, else two passes
     // (B = B1 * B2, tiles of 16 sequences per workgroup) and a selection workgroup per loop
     R.fft_mode = (R.B > (uint32_t)kMaxFftLds || (p.flags & SFFT_FLAG_FFT_TWO_PASS)) ? 1u : 0u;

@@ -78,8 +78,8 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
                 auto in_group = [&](const Resolved& R) {
                     return active(R) && !R.phase && (R.vote_lds > 0) == (staged == 1) && R.lmax == lm;
                 };
-                const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_lds; });
-                add_step(kStepVote, staged | (lm << 8) | (round << 16), staged ? lds : 0,
+                const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_dyn_lds; });
+                add_step(kStepVote, staged | (lm << 8) | (round << 16), lds,
                          [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
             }
         add_step(kStepDecode, round, 0, [&](const Resolved& R) { return active(R) && R.phase ? R.vote_units : 0u; });
@@ -109,7 +109,9 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
         switch (st.kind) {
             case kStepFold: e = launch_fold(a, st.param, st.units, st.lds, s); break;
             case kStepFft: e = launch_fft_select(a, st.param, st.units, s); break;
-            case kStepVote: e = launch_vote(a, (st.param >> 8) & 255u, st.units, st.lds, st.param >> 16, s); break;
+            case kStepVote:
+                e = launch_vote(a, (st.param >> 8) & 255u, st.units, st.lds, st.param & 1u, st.param >> 16, s);
+                break;
             case kStepDecode: e = launch_decode(a, st.units, st.param, s); break;
             case kStepEst: e = launch_estimate(a, st.param & 255u, st.units, st.param >> 8, s); break;
             case kStepFin: e = launch_finalize(a, st.units, st.lds, st.param, s); break;
