@@ -33,6 +33,7 @@ CASES = [  # N, K, B, L, w, snr, seed, est_loops, est_B, est_w, flags
     (1 << 18, 40, 1024, 16, 8192, 20.0, 4, 16, 2048, 0, 0),   # 32 loops in all
     (1 << 16, 20, 256, 5, 2048, 10.0, 5, 4, 1024, 0, 0x10),   # mean combiner
     (1 << 20, 50, 1024, 7, 8192, 20.0, 6, 2, 4096, 0, 0),     # C2 shape
+    (1 << 20, 50, 4096, 5, 32768, 20.0, 7, 3, 8192, 0, 0x80), # location loops through the two-pass FFT
 ]
 
 
