@@ -126,7 +126,7 @@ public:
     int query(int s) override {
         std::lock_guard<std::mutex> lk(mu_);
         if (!slot_[s].busy) return 1;
-        if (Clock::now() < slot_[s].until) return 0;
+        if (hold.load() || Clock::now() < slot_[s].until) return 0;
         slot_[s].busy = false;
         slot_[s].ranges.clear();
         slot_[s].n = 0;
@@ -134,6 +134,7 @@ public:
     }
 
     std::atomic<size_t> uploads{0}, waves{0}, max_wave{0}, max_inflight_seen{0};
+    std::atomic<bool> hold{false};   // while set, no wave completes
 
 private:
     struct Slot {
@@ -190,6 +191,16 @@ static void test_allocator() {
     CHECK(a.in_use() == 0 && a.free_ranges() == 1 && a.largest_free() == cap);
 }
 
+// Polls pred every 100 us for up to 20 s.
+template <class F>
+static bool wait_until(F pred) {
+    for (int i = 0; i < 200000; ++i) {
+        if (pred()) return true;
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    return false;
+}
+
 struct Env {
     std::map<uint32_t, size_t> tab, ws;
 };
@@ -205,14 +216,19 @@ static void test_batching_and_overlap() {
     core.add_plan(2, e.tab[2]);
     std::vector<uint64_t> t;
     uint64_t k = 0;
+    // waves stay in flight until released, so the later arrivals meet the first wave running
+    // (no dependence on how fast the scheduler thread runs)
+    ex.hold = true;
     CHECK(core.submit(1, e.ws[1], Io{0, 1}, &k) == kCoreOk);
     t.push_back(k);
-    std::this_thread::sleep_for(std::chrono::microseconds(500));  // first wave is running
+    CHECK(wait_until([&] { return ex.waves.load() >= 1; }));   // first wave is running
     for (int i = 0; i < 40; ++i) {
         const uint32_t p = 1 + i % 2;
         CHECK(core.submit(p, e.ws[p], Io{0, (int)p}, &k) == kCoreOk);
         t.push_back(k);
     }
+    CHECK(wait_until([&] { return ex.waves.load() >= 2; }));   // a second wave beside it
+    ex.hold = false;
     for (uint64_t x : t) {
         double lat = -1;
         int st = 1;
