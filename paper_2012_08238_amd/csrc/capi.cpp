@@ -147,7 +147,7 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
     if (R.phase)
         HIP_TRY(launch_decode(a, R.vote_units, 0, s), "phase decode launch");
     else
-        HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_dyn_lds, R.vote_lds > 0, 0, s), "vote launch");
+        HIP_TRY(launch_vote(a, vote_key(R.L), R.vote_units, R.vote_dyn_lds, R.vote_lds > 0, 0, s), "vote launch");
     HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 0, s), "estimate launch");
     HIP_TRY(launch_finalize(a, 1, R.fin_lds, 0, s), "top-K launch");
     if (R.iterate) {
@@ -156,7 +156,7 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
         if (R.phase)
             HIP_TRY(launch_decode(a, R.vote_units, 1, s), "second phase decode launch");
         else
-            HIP_TRY(launch_vote(a, R.lmax, R.vote_units, R.vote_dyn_lds, R.vote_lds > 0, 1, s), "second vote launch");
+            HIP_TRY(launch_vote(a, vote_key(R.L), R.vote_units, R.vote_dyn_lds, R.vote_lds > 0, 1, s), "second vote launch");
         HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 1, s), "second estimate launch");
         HIP_TRY(launch_finalize(a, 1, R.fin_lds, 1, s), "second top-K launch");
     }

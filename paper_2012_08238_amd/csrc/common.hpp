@@ -97,9 +97,16 @@ constexpr uint32_t kNumXcd = 8;  // MI355X: 8 accelerator complex dies, workgrou
 constexpr uint32_t kVoteNT = 256;
 constexpr uint32_t kVotePerThread = 16;
 constexpr uint32_t kVoteUnit = kVoteNT * kVotePerThread;  // candidates per vote workgroup
+// Vote grid cap: at most this many workgroups (a few per compute unit of the 256), each
+// looping over its share of the chunks, so that a vote launch does not take every compute
+// unit's LDS and wave slots from the bucketization running beside it on another stream.
+constexpr uint32_t kVoteMaxGrid = 4u * 256u;
 // LDS words for the selected-bucket slots one vote workgroup enumerates (N/B = 2^log2M
 // candidates per slot), a multiple of 4 so the staged bitmaps after them stay 16-byte aligned
 __host__ __device__ constexpr uint32_t vote_slot_words(uint32_t log2M) { return ((kVoteUnit >> log2M) + 1u + 3u) & ~3u; }
+// Vote kernel instance of a plan with L location loops: L itself up to 16, else 32.
+__host__ __device__ constexpr uint32_t vote_key(uint32_t L) { return L <= 16u ? L : 32u; }
+constexpr uint32_t kVoteKeys = 17;   // distinct vote_key values
 constexpr uint32_t kFoldNT = 256;
 constexpr uint32_t kFftNT = 256;
 constexpr uint32_t kFinNT = 256;   // estimation workgroups

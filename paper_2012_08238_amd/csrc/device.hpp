@@ -61,8 +61,8 @@ __device__ __forceinline__ uint32_t xcd_unit(uint32_t blk, uint32_t grid) {
     return x * base + min(x, rem) + i;
 }
 
-__device__ __forceinline__ void resolve(const Launch& a, uint32_t& sig, uint32_t& unit) {
-    const uint32_t blk = a.xcd_order ? xcd_unit(blockIdx.x, gridDim.x) : blockIdx.x;
+// (signal, unit) of launch-wide unit blk
+__device__ __forceinline__ void resolve_blk(const Launch& a, uint32_t blk, uint32_t& sig, uint32_t& unit) {
     if (a.nsig == 0) {
         sig = 0;
         unit = blk;
@@ -76,6 +76,10 @@ __device__ __forceinline__ void resolve(const Launch& a, uint32_t& sig, uint32_t
     }
     sig = lo;
     unit = blk - pre[lo];
+}
+
+__device__ __forceinline__ void resolve(const Launch& a, uint32_t& sig, uint32_t& unit) {
+    resolve_blk(a, a.xcd_order ? xcd_unit(blockIdx.x, gridDim.x) : blockIdx.x, sig, unit);
 }
 
 __device__ __forceinline__ const __attribute__((address_space(4))) SigDesc& desc_of(const Launch& a, uint32_t sig) {

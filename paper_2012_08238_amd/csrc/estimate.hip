@@ -44,17 +44,28 @@ __device__ __forceinline__ void append_wave(const uint32_t (&fv)[P], uint32_t em
 // for it (later loops skip it), so I' has no duplicates; votes are bitmap tests.
 // In the subtraction round (round 1) the frequencies recovered by the first
 // round are not candidates again.
-template <int LMAX>
-// Dynamic LDS: the chunk's selected-bucket slots (vote_slot_words(log2 N/B) words), then
-// (staged) the L selected-bucket bitmaps.
-__global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged, uint32_t round) {
-    extern __shared__ uint32_t sdyn[];
-    __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
-    uint32_t sig, unit;
-    resolve(a, sig, unit);
+//
+// Loop r hashes f = sigma_r0^{-1} p to bucket ((c_r p + N/2B) mod N) >> log2(N/B)
+// with c_r = sigma_r sigma_r0^{-1} (mod N, a workgroup constant). A thread takes
+// kVotePerThread consecutive positions p of one selected bucket (when N/B allows),
+// so each loop's hash argument advances by the constant c_r per candidate (an add
+// instead of a multiply) and the bucket is a bit-field of it. Instances: VL = L for
+// L <= 16 (every test unconditional); VL = 32 covers 17..32 with the surplus tests
+// masked. STAGED: the L selected-bucket bitmaps are copied to LDS first.
+// One chunk of kVoteUnit candidates (unit `unit` of signal `sig`). sdyn: the chunk's
+// selected-bucket slots (vote_slot_words(log2 N/B) words), then (staged) the L
+// selected-bucket bitmaps, which (like the comb residues) are copied only when `restage`
+// (the workgroup's previous chunk was another signal's).
+template <int VL, bool STAGED>
+__device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32_t unit, uint32_t round, bool restage,
+                                           uint32_t* sdyn, uint32_t* s_comb) {
+    constexpr bool kExact = VL <= 16;
+    constexpr uint32_t kLog2PT = 4;
+    static_assert((1u << kLog2PT) == kVotePerThread, "candidates per thread");
     const auto& d = desc_of(a, sig);
     const uint32_t wpl = (d.B + 31u) >> 5;
-    const uint32_t L = d.L, T = d.T, M = d.M, log2M = d.log2M, maskN = d.maskN, B = d.B, dK = d.dK;
+    const uint32_t L = kExact ? (uint32_t)VL : d.L;
+    const uint32_t T = d.T, M = d.M, log2M = d.log2M, maskN = d.maskN, log2B = d.log2B, dK = d.dK;
     const uint32_t* jbits = d.jbits;
     // this workgroup: candidates [start, end) of enumerated loop r0, i.e. the
     // permuted positions of selected-bucket slots slot0 .. slot0 + nslots - 1
@@ -65,16 +76,20 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
     const uint32_t end = min(start + kVoteUnit, per_loop);
     const uint32_t slot0 = start >> log2M;
     const uint32_t nslots = ((end - 1u) >> log2M) - slot0 + 1u;
-    const uint32_t sinv0 = d.sigma_inv[r0];
+    const uint32_t sinv0 = ((CU32)d.sigma_inv)[r0];
     uint32_t* s_slot = sdyn;
     uint32_t* sbits = sdyn + vote_slot_words(log2M);
     const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
     for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
-    uint32_t sg[LMAX];   // sigma_r, uniform: scalar loads
+    uint32_t cr[VL], boff[VL];   // c_r and loop r's bitmap offset: uniform
 #pragma unroll
-    for (int r = 0; r < LMAX; ++r) sg[r] = (uint32_t)r < L ? ((CU32)d.sigma)[r] : 0u;
+    for (int r = 0; r < VL; ++r) {
+        const uint32_t rr = kExact ? (uint32_t)r : min((uint32_t)r, L - 1u);
+        cr[r] = ((CU32)d.sigma)[rr] * sinv0;
+        boff[r] = rr * wpl;
+    }
     const uint32_t ncomb = d.comb_loops, cmask = (1u << d.comb_log2b) - 1u;
-    if (ncomb) {
+    if (ncomb && restage) {
         const uint32_t cw = max(1u, (cmask + 1u) >> 5);
         for (uint32_t i = threadIdx.x; i < cw; i += kVoteNT) {
             uint32_t v = 0;
@@ -82,8 +97,7 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
             s_comb[i] = v;
         }
     }
-    const uint32_t* bits = jbits;
-    if (staged) {
+    if (STAGED && restage) {
         // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte units)
         typedef uint32_t u4v __attribute__((ext_vector_type(4)));
         const uint32_t nw4 = (L * wpl + 3u) >> 2;
@@ -99,48 +113,111 @@ __global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t staged
                 if (i < nw4) dst[i] = t[e];
             }
         }
-        bits = sbits;
     }
     __syncthreads();
+    // bit r of the result: loop r selected the bucket of hash argument qv, i.e. bits
+    // [log2M, log2M + log2B) of qv: its bitmap word (bits above log2M + 5) and the bit in it
+    const uint32_t wb_off = log2M + 5u, wb_w = (log2B > 5u ? log2B : 5u) - 5u, hb_w = log2B < 5u ? log2B : 5u;
+    auto test = [&](int r, uint32_t qv) -> uint32_t {
+        const uint32_t word = __builtin_amdgcn_ubfe(qv, wb_off, wb_w);
+        const uint32_t hb = __builtin_amdgcn_ubfe(qv, log2M, hb_w);
+        uint32_t wd;
+        if constexpr (STAGED) wd = sbits[boff[r] + word];
+        else wd = gld(jbits + boff[r] + word);
+        return (kExact || (uint32_t)r < L ? __builtin_amdgcn_ubfe(wd, hb, 1u) : 0u) << r;
+    };
     uint32_t* ctr = d.ctr;
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
-    const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;   // first-round frequencies (ascending)
+    const uint32_t half = M >> 1;
+    const uint32_t before_r0 = (1u << r0) - 1u;
+    // >= T votes, counted once: from the first loop that voted (loop r0 always did)
+    auto voted = [&](uint32_t votes) -> uint32_t {
+        return ((votes & before_r0) == 0u && (uint32_t)__popc(votes) >= T) ? 1u : 0u;
+    };
     uint32_t fv[kVotePerThread];
     uint32_t emask = 0;   // bit qq: candidate qq of this thread passes
+    if (log2M >= kLog2PT) {
+        // candidates ci0 .. ci0 + kVotePerThread - 1: consecutive positions of one bucket
+        // (the chunk bounds are multiples of kVotePerThread here)
+        const uint32_t ci0 = start + (threadIdx.x << kLog2PT);
+        if (ci0 < end) {
+            const uint32_t h = s_slot[(ci0 >> log2M) - slot0];
+            const uint32_t p0 = (h << log2M) - half + (ci0 & (M - 1u));   // mod 2^32: N divides it
+            uint32_t q[VL];
 #pragma unroll
-    for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-        const uint32_t ci = start + qq * kVoteNT + threadIdx.x;   // candidate index within loop r0
-        bool emit = false;
-        uint32_t f = 0;
-        if (ci < end) {
-            const uint32_t h = s_slot[(ci >> log2M) - slot0];
-            const uint32_t p = ((h << log2M) - (M >> 1) + (ci & (M - 1u))) & maskN;
-            f = (sinv0 * p) & maskN;
-            // all L bitmap tests issued together (no serial chain); bit r of `votes`
-            // is set when loop r selected the bucket of f (loop r0 always did; testing it
-            // too keeps the unrolled tests free of a per-loop predicate)
-            uint32_t votes = 0;
+            for (int r = 0; r < VL; ++r) q[r] = cr[r] * p0 + half;
+            uint32_t f = sinv0 * p0;
 #pragma unroll
-            for (int r = 0; r < LMAX; ++r) {
-                if ((uint32_t)r < L) {
-                    const uint32_t pr = (sg[r] * f) & maskN;
-                    const uint32_t hr = ((pr + (M >> 1)) >> log2M) & (B - 1u);
-                    votes |= ((bits[(uint32_t)r * wpl + (hr >> 5)] >> (hr & 31u)) & 1u) << r;
+            for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+                uint32_t votes = 0;
+#pragma unroll
+                for (int r = 0; r < VL; ++r) {
+                    votes |= test(r, q[r]);
+                    q[r] += cr[r];
                 }
+                fv[qq] = f & maskN;
+                emask |= voted(votes) << qq;
+                f += sinv0;
             }
-            // counted once: from the first loop that voted for f
-            emit = (votes & ((1u << r0) - 1u)) == 0u && (uint32_t)__popc(votes) >= T;
-            if (ncomb) {
-                const uint32_t res = f & cmask;
-                emit = emit && ((s_comb[res >> 5] >> (res & 31u)) & 1u);
-            }
-            if (emit && n1) emit = !in_sorted(d.rec_f, n1, f);
+        } else {
+#pragma unroll
+            for (uint32_t qq = 0; qq < kVotePerThread; ++qq) fv[qq] = 0u;
         }
-        fv[qq] = f;
-        emask |= (emit ? 1u : 0u) << qq;
+    } else {
+        // fewer positions per bucket than candidates per thread: each candidate on its own
+#pragma unroll
+        for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+            const uint32_t ci = start + qq * kVoteNT + threadIdx.x;   // candidate index within loop r0
+            fv[qq] = 0u;
+            if (ci < end) {
+                const uint32_t h = s_slot[(ci >> log2M) - slot0];
+                const uint32_t p = (h << log2M) - half + (ci & (M - 1u));
+                uint32_t votes = 0;
+#pragma unroll
+                for (int r = 0; r < VL; ++r) votes |= test(r, cr[r] * p + half);
+                fv[qq] = (sinv0 * p) & maskN;
+                emask |= voted(votes) << qq;
+            }
+        }
+    }
+    // the comb prefilter's residues and the first round's frequencies, on the passing ones only
+    const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;   // first-round frequencies (ascending)
+    if (ncomb || n1) {
+#pragma unroll
+        for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+            if ((emask >> qq) & 1u) {
+                const uint32_t f = fv[qq];
+                bool keep = true;
+                if (ncomb) {
+                    const uint32_t res = f & cmask;
+                    keep = (s_comb[res >> 5] >> (res & 31u)) & 1u;
+                }
+                if (keep && n1) keep = !in_sorted(d.rec_f, n1, f);
+                if (!keep) emask &= ~(1u << qq);
+            }
+        }
     }
     append_wave<kVotePerThread>(fv, emask, ctr, cand, cap);
+}
+
+// The grid may be smaller than the launch's `units` chunks (it is capped so that the vote
+// leaves room on every compute unit for other streams' work); each workgroup then takes
+// a contiguous share of the chunks, mostly of one signal, whose tables it copies once.
+template <int VL, bool STAGED>
+__global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t round, uint32_t units) {
+    extern __shared__ uint32_t sdyn[];
+    __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
+    const uint32_t b0 = (uint32_t)(((uint64_t)blockIdx.x * units) / gridDim.x);
+    const uint32_t b1 = (uint32_t)(((uint64_t)(blockIdx.x + 1u) * units) / gridDim.x);
+    uint32_t prev = 0xffffffffu;
+    for (uint32_t blk = b0; blk < b1; ++blk) {
+        uint32_t sig, unit;
+        resolve_blk(a, blk, sig, unit);
+        if (blk != b0) __syncthreads();   // the previous chunk's LDS reads are done
+        vote_chunk<VL, STAGED>(a, sig, unit, round, sig != prev, sdyn, s_comb);
+        prev = sig;
+    }
 }
 
 // ---------------------------------------------------------------- phase-encoding location
@@ -772,16 +849,42 @@ __global__ __launch_bounds__(kResNT) void residual_sum_kernel(Launch a) {
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t staged,
-                       uint32_t round, hipStream_t s) {
-    switch (lmax) {
-        case 4: hipLaunchKernelGGL(vote_kernel<4>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
-        case 8: hipLaunchKernelGGL(vote_kernel<8>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
-        case 16: hipLaunchKernelGGL(vote_kernel<16>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
-        case 32: hipLaunchKernelGGL(vote_kernel<32>, dim3(units), dim3(kVoteNT), lds_bytes, s, a, staged, round); break;
-        default: return hipErrorInvalidValue;
-    }
+template <int VL>
+hipError_t launch_vote_vl(const Launch& a, uint32_t units, uint32_t lds_bytes, uint32_t staged, uint32_t round,
+                          hipStream_t s) {
+    const uint32_t grid = min(units, kVoteMaxGrid);
+    if (staged) hipLaunchKernelGGL((vote_kernel<VL, true>), dim3(grid), dim3(kVoteNT), lds_bytes, s, a, round, units);
+    else hipLaunchKernelGGL((vote_kernel<VL, false>), dim3(grid), dim3(kVoteNT), lds_bytes, s, a, round, units);
     return hipGetLastError();
+}
+
+template <int... VLs>
+struct VoteTable {
+    static hipError_t launch(uint32_t key, const Launch& a, uint32_t units, uint32_t lds_bytes, uint32_t staged,
+                             uint32_t round, hipStream_t s) {
+        hipError_t e = hipErrorInvalidValue;
+        ((key == (uint32_t)VLs ? (e = launch_vote_vl<VLs>(a, units, lds_bytes, staged, round, s), 0) : 0), ...);
+        return e;
+    }
+    static hipError_t set_lds(uint32_t bytes) {
+        hipError_t e = hipSuccess;
+        ((e = e == hipSuccess ? hipFuncSetAttribute(reinterpret_cast<const void*>(&vote_kernel<VLs, true>),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes)
+                              : e),
+         ...);
+        ((e = e == hipSuccess ? hipFuncSetAttribute(reinterpret_cast<const void*>(&vote_kernel<VLs, false>),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes)
+                              : e),
+         ...);
+        return e;
+    }
+};
+// one instance per vote_key value
+typedef VoteTable<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 32> Votes;
+
+hipError_t launch_vote(const Launch& a, uint32_t key, uint32_t units, uint32_t lds_bytes, uint32_t staged,
+                       uint32_t round, hipStream_t s) {
+    return Votes::launch(key, a, units, lds_bytes, staged, round, s);
 }
 
 hipError_t launch_decode(const Launch& a, uint32_t units, uint32_t round, hipStream_t s) {
@@ -819,11 +922,7 @@ constexpr int kVoteLdsMax = (int)vote_slot_words(1) * 4 + 65536;
 hipError_t set_estimate_attributes() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&subtract_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kSubLdsMax);
-    const void* votes[4] = {reinterpret_cast<const void*>(&vote_kernel<4>), reinterpret_cast<const void*>(&vote_kernel<8>),
-                            reinterpret_cast<const void*>(&vote_kernel<16>),
-                            reinterpret_cast<const void*>(&vote_kernel<32>)};
-    for (int i = 0; i < 4 && e == hipSuccess; ++i)
-        e = hipFuncSetAttribute(votes[i], hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsMax);
+    if (e == hipSuccess) e = Votes::set_lds(kVoteLdsMax);
     return e;
 }
 

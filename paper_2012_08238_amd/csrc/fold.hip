@@ -5,6 +5,11 @@
 namespace sfft {
 
 // ---------------------------------------------------------------- bucketization
+// Every bucketization kernel raises its waves' issue priority: it streams the signals
+// from HBM, and when later stages of other batches run beside it on the same compute
+// units (other streams) the SIMD arbiter then issues its loads first, which keeps HBM busy.
+__device__ __forceinline__ void fold_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Strip form. View x as an (N/B) x B row-major matrix: time sample a = row*B + col.
 // For loop r the window index of sample a is i = sigma^{-1}(a - tau) mod N and its
 // bucket is i mod B, which depends on col only (B | N). Each workgroup streams a
@@ -13,6 +18,7 @@ namespace sfft {
 // that land in the column: they sit at rows (q + sigma*m) mod (N/B) of it.
 template <int PER>
 __global__ __launch_bounds__(kFoldNT) void fold_strip_kernel(Launch a) {
+    fold_priority();
     extern __shared__ f4v lds4[];
     uint32_t sig, unit;
     resolve(a, sig, unit);
@@ -86,6 +92,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_kernel(Launch a) {
 // summed in tap order at the end: same taps, same order as the other forms.
 template <int PER, int IPT, int G4, int H>
 __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
+    fold_priority();
     extern __shared__ f4v lds4[];
     uint32_t sig, unit;
     resolve(a, sig, unit);
@@ -194,6 +201,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
 // directly (four loads in flight). Same taps in the same order as the strip
 // form, so both give bitwise-identical buckets.
 __global__ __launch_bounds__(kFoldNT) void fold_gather_kernel(Launch a) {
+    fold_priority();
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);

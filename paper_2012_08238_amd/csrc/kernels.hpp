@@ -19,10 +19,10 @@ hipError_t launch_comb(const Launch& a, uint32_t log2b, uint32_t units, hipStrea
 // 1 = second pass (L * B1/16), 2 = selection (L); every signal of the launch has this B
 hipError_t launch_fft_large(const Launch& a, uint32_t log2B, uint32_t pass, uint32_t units, hipStream_t s);
 // lds_bytes = Resolved::vote_dyn_lds (max over the launch): the slot words, then (staged: the
-// bitmaps are copied to LDS) L * ceil(B/32) * 4 bytes; lmax in {4, 8, 16, 32} >= L of every
+// bitmaps are copied to LDS) L * ceil(B/32) * 4 bytes; key = vote_key(L), the same for every
 // signal of the launch; round 1: the vote of the subtraction round (the first round's
 // frequencies are excluded)
-hipError_t launch_vote(const Launch& a, uint32_t lmax, uint32_t units, uint32_t lds_bytes, uint32_t staged,
+hipError_t launch_vote(const Launch& a, uint32_t key, uint32_t units, uint32_t lds_bytes, uint32_t staged,
                        uint32_t round, hipStream_t s);
 // phase-encoding location: kDecUnit selected buckets per workgroup; round 1 excludes the first round's
 // frequencies

@@ -18,10 +18,10 @@ constexpr uint32_t kLmaxCount = 4;     // lmax in {4, 8, 16, 32}
 size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // two-pass fft: 3 per size; comb prefilter: one per comb size (2^1 .. 2^14);
-    // per round: vote 2 x kLmaxCount, phase decode 1, estimate kLmaxCount, top-K 1;
+    // per round: vote 2 x kVoteKeys, phase decode 1, estimate kLmaxCount, top-K 1;
     // subtraction 1, reselection kFftLog2Max; residual and its sum 2
     const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kLargeLog2Min + 1) + kFftLog2Max +
-                            2 * (3 * kLmaxCount + 2) + 1 + kFftLog2Max + 2;
+                            2 * (2 * kVoteKeys + kLmaxCount + 2) + 1 + kFftLog2Max + 2;
     return launches * (n + 1);
 }
 
@@ -74,12 +74,13 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
                 add_step(kStepReselect, lb, 0, [&](const Resolved& R) { return R.iterate && R.log2B == lb ? R.L : 0u; });
         }
         for (uint32_t staged = 0; staged < 2; ++staged)
-            for (uint32_t lm = 4; lm <= 32; lm <<= 1) {
+            for (uint32_t vk = 1; vk <= 32; ++vk) {
+                if (vote_key(vk) != vk) continue;
                 auto in_group = [&](const Resolved& R) {
-                    return active(R) && !R.phase && (R.vote_lds > 0) == (staged == 1) && R.lmax == lm;
+                    return active(R) && !R.phase && (R.vote_lds > 0) == (staged == 1) && vote_key(R.L) == vk;
                 };
                 const uint32_t lds = max_of(in_group, [](const Resolved& R) { return R.vote_dyn_lds; });
-                add_step(kStepVote, staged | (lm << 8) | (round << 16), lds,
+                add_step(kStepVote, staged | (vk << 8) | (round << 16), lds,
                          [&](const Resolved& R) { return in_group(R) ? R.vote_units : 0u; });
             }
         add_step(kStepDecode, round, 0, [&](const Resolved& R) { return active(R) && R.phase ? R.vote_units : 0u; });
