@@ -581,7 +581,7 @@ def main() -> int:
     ap.add_argument("--strip-cols", type=int, default=0, help="bucketization tile width (0 = plan default)")
     ap.add_argument("--w-over-b", type=int, default=8, help="window length w as a multiple of B")
     ap.add_argument("--fold", choices=["auto", "strip", "gather"], default="auto", help="bucketization form")
-    ap.add_argument("--fft", choices=["two-pass", "one-workgroup"], default="two-pass",
+    ap.add_argument("--fft", choices=["two-pass", "one-workgroup"], default="one-workgroup",
                     help="B-point FFT form of the step's plan (two passes of small workgroups share compute units "
                          "with the next step's bucketization)")
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")

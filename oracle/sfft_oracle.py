@@ -57,35 +57,50 @@ def splitmix64(seed: int, n: int) -> list[int]:
     return out
 
 
+RESID_RUN = 8   # residual-check positions come in runs of this many consecutive samples
+
+
+def resid_draws(n_resid: int) -> int:
+    """Stream outputs the residual positions take: one per run."""
+    return -(-n_resid // RESID_RUN)
+
+
 def draw_permutations(N: int, L: int, seed: int, n_resid: int = 0):
     """Random scaling sigma (odd, so invertible mod N = 2^m) and shift tau per
     bucketization, drawn in the order sigma_0, tau_0, sigma_1, tau_1, ...;
-    then ``n_resid`` residual-check time positions t_j from the same stream.
+    then the ``n_resid`` residual-check time positions from the same stream, in
+    runs: draw j gives the run start s_j = (draw & (N-1)) rounded down to a
+    multiple of RESID_RUN, and the positions are s_j, s_j + 1, ..., the first
+    n_resid of them in run order.
 
     The voting framework uses random frequency scaling per bucketization
     (voting-framework section); the random shift makes the phase of Eq.(9)
-    random as well.
+    random as well. The paper fixes no positions for the formula-method check
+    (Eq.(2)); runs of consecutive samples are one valid choice.
     """
-    draws = splitmix64(seed, 2 * L + n_resid)
+    nr = resid_draws(n_resid)
+    draws = splitmix64(seed, 2 * L + nr)
     sigma = np.array([(draws[2 * r] & (N - 1)) | 1 for r in range(L)], dtype=np.int64)
     tau = np.array([draws[2 * r + 1] & (N - 1) for r in range(L)], dtype=np.int64)
-    tpos = np.array([draws[2 * L + j] & (N - 1) for j in range(n_resid)], dtype=np.int64)
+    starts = [(draws[2 * L + j] & (N - 1)) & ~(RESID_RUN - 1) for j in range(nr)]
+    tpos = np.array([starts[j // RESID_RUN] + j % RESID_RUN for j in range(n_resid)], dtype=np.int64)
     return sigma, tau, tpos
 
 
 def draw_comb_shifts(N: int, L: int, seed: int, n_resid: int, n_comb: int) -> np.ndarray:
     """Time shifts of the comb (spike-train) prefilter loops: the next ``n_comb``
     outputs of the same SplitMix64 stream, after the 2L permutation draws and
-    the residual positions."""
-    draws = splitmix64(seed, 2 * L + n_resid + n_comb)
-    return np.array([draws[2 * L + n_resid + c] & (N - 1) for c in range(n_comb)], dtype=np.int64)
+    the residual positions' draws."""
+    base = 2 * L + resid_draws(n_resid)
+    draws = splitmix64(seed, base + n_comb)
+    return np.array([draws[base + c] & (N - 1) for c in range(n_comb)], dtype=np.int64)
 
 
 def draw_est_permutations(N: int, L: int, seed: int, n_resid: int, n_comb: int, L_est: int):
     """Scalings and shifts of the estimation-only loops: the next 2 L_est outputs
     of the same SplitMix64 stream (sigma, tau alternating), after the permutation
     draws, the residual positions and the comb shifts."""
-    base = 2 * L + n_resid + n_comb
+    base = 2 * L + resid_draws(n_resid) + n_comb
     draws = splitmix64(seed, base + 2 * L_est)
     sigma = np.array([(draws[base + 2 * r] & (N - 1)) | 1 for r in range(L_est)], dtype=np.int64)
     tau = np.array([draws[base + 2 * r + 1] & (N - 1) for r in range(L_est)], dtype=np.int64)

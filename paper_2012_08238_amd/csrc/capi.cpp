@@ -100,6 +100,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.vote_units = R.vote_units;
     d.vote_upl = R.vote_upl;
     d.resid_blocks = R.resid_blocks;
+    d.resid_log2kl = R.resid_log2kl;
     d.est_units = R.est_units;
     d.lmax = R.lmax;
     d.combine = (R.flags & SFFT_FLAG_MEAN_ESTIMATE) ? 1u : 0u;

@@ -61,6 +61,7 @@ struct SigDesc {
     uint32_t vote_units;        // vote workgroups
     uint32_t vote_upl;          // vote workgroups per enumerated loop (chunks of kVoteUnit candidates)
     uint32_t resid_blocks;      // residual workgroups
+    uint32_t resid_log2kl;      // residual: lanes per run (the outputs split 2^resid_log2kl ways)
     uint32_t est_units;         // estimation workgroups (striding over the candidates)
     uint32_t lmax;              // power of two >= L used by the median network
     uint32_t combine;           // 0: coordinate-wise median over the loops, 1: mean
@@ -112,7 +113,7 @@ constexpr uint32_t kFftNT = 256;
 constexpr uint32_t kFinNT = 256;   // estimation workgroups
 constexpr uint32_t kSelNT = 1024;  // top-K selection workgroup (one per signal)
 constexpr uint32_t kResNT = 256;
-constexpr uint32_t kResSamples = 64;   // residual samples per workgroup (its waves split the tones)
+constexpr uint32_t kResRun = 8;        // residual positions per run (consecutive samples, one 64-byte line)
 constexpr uint32_t kSubNT = 256;
 constexpr uint32_t kDecPerThread = 4;                     // decoded buckets per thread
 constexpr uint32_t kDecUnit = kVoteNT * kDecPerThread;    // decoded buckets per workgroup

@@ -740,22 +740,25 @@ __global__ __launch_bounds__(kSubNT) void subtract_kernel(Launch a) {
 
 // ---------------------------------------------------------------- FP64 residual
 // E_res = mean_t |x_t - sum_k v_k e^{+2 pi i (t f_k mod N)/N}|^2 and
-// E_in = mean_t |x_t|^2 over the S residual samples. A workgroup takes 64
-// samples; its four waves sum the model over every fourth output (wave w: k = w,
-// w+4, ...) for the same samples, and the four partial sums are added in wave
-// order. The outputs are staged in LDS (dynamic: K values, K frequencies); the
-// phase of the exact integer t f mod N is evaluated in FP64 (phase_of). Each
-// workgroup writes its two partial sums; residual_sum_kernel reduces them.
+// E_in = mean_t |x_t|^2 over the S residual positions, which come in runs of
+// kResRun consecutive samples. Lane (run, kl) of a wave sums the model over the
+// outputs k = kl, kl + KL, ... (KL = 2^resid_log2kl) for the kResRun samples of its
+// run: the phase of the exact integer t0 f mod N at the run start t0 (phase_of, FP64),
+// then one complex multiply by e^{+2 pi i f/N} per further sample. The KL lanes of a
+// run are added by a fixed shuffle tree; the run's lane kl = 0 forms the two energy
+// sums of its samples; lanes, then waves, are added in a fixed order, and each
+// workgroup writes its two partial sums; residual_sum_kernel reduces them. Padding
+// outputs (index -1) are staged as f = 0, v = 0 and add exact zeros.
 __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
     constexpr uint32_t NW = kResNT / 64;
-    __shared__ double2 s_part[NW][kResSamples];
+    __shared__ double2 s_red[NW];
     __shared__ double2 s_rou[kRouMax];
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
     const IoDesc io = io_of(a, sig);
-    const uint32_t K = d.K, maskN = d.maskN;
+    const uint32_t K = d.K, maskN = d.maskN, log2kl = d.resid_log2kl;
     const uint32_t rsh = d.log2N - d.tb;
     const double step = d.step;
     float2* s_v = reinterpret_cast<float2*>(lds_raw);
@@ -763,50 +766,76 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     stage_rou<kResNT>(s_rou, d.rou, d.tb);
     for (uint32_t k = threadIdx.x; k < K; k += kResNT) {
         const int64_t f = gld(io.out_idx + k);
-        s_f[k] = f < 0 ? 0xFFFFFFFFu : (uint32_t)f;
-        s_v[k] = gld(io.out_val + k);
+        const bool pad = f < 0;
+        s_f[k] = pad ? 0u : (uint32_t)f;
+        s_v[k] = pad ? make_float2(0.f, 0.f) : gld(io.out_val + k);
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t j = unit * kResSamples + lane;
-    const bool valid = j < d.S;
-    const uint32_t t = valid ? gld(d.tpos + j) : 0u;
-    double mr = 0.0, mi = 0.0;
-#pragma unroll 2
-    for (uint32_t k = wv; k < K; k += NW) {
+    const uint32_t KL = 1u << log2kl, kl = lane & (KL - 1u);
+    const uint32_t run = (unit * NW + wv) * (64u >> log2kl) + (lane >> log2kl);
+    const uint32_t j0 = run * kResRun;
+    const bool valid = j0 < d.S;
+    const uint32_t t0 = valid ? gld(d.tpos + j0) : 0u;
+    double mr[kResRun], mi[kResRun];
+#pragma unroll
+    for (uint32_t i = 0; i < kResRun; ++i) mr[i] = mi[i] = 0.0;
+    for (uint32_t k = kl; k < K; k += KL) {
         const uint32_t f = s_f[k];
-        if (f == 0xFFFFFFFFu) continue;   // padding (uniform across the wave)
-        const double2 p = phase_of(s_rou, (t * f) & maskN, rsh, step);
-        const float2 v = s_v[k];
-        mr += (double)v.x * p.x - (double)v.y * p.y;
-        mi += (double)v.x * p.y + (double)v.y * p.x;
-    }
-    s_part[wv][lane] = make_double2(mr, mi);
-    __syncthreads();
-    if (wv == 0) {
-        double ea = 0.0, eb = 0.0;
-        if (valid) {
-            double m_r = 0.0, m_i = 0.0;
+        const double vr = (double)s_v[k].x, vi = (double)s_v[k].y;
+        double2 p = phase_of(s_rou, (t0 * f) & maskN, rsh, step);   // e^{+2 pi i t0 f/N}
+        const double2 st = phase_of(s_rou, f, rsh, step);          // e^{+2 pi i f/N}
 #pragma unroll
-            for (uint32_t w = 0; w < NW; ++w) {
-                m_r += s_part[w][lane].x;
-                m_i += s_part[w][lane].y;
+        for (uint32_t i = 0; i < kResRun; ++i) {
+            mr[i] = fma(vr, p.x, fma(-vi, p.y, mr[i]));
+            mi[i] = fma(vr, p.y, fma(vi, p.x, mi[i]));
+            if (i + 1 < kResRun) {
+                const double px = p.x * st.x - p.y * st.y;
+                p.y = p.x * st.y + p.y * st.x;
+                p.x = px;
             }
-            const float2 xv = gld(io.x + t);
-            const double xr = xv.x, xi = xv.y;
-            const double er = xr - m_r, ei = xi - m_i;
-            ea = er * er + ei * ei;
-            eb = xr * xr + xi * xi;
         }
+    }
+    for (uint32_t off = KL >> 1; off > 0; off >>= 1) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            ea += __shfl_down(ea, off, 64);
-            eb += __shfl_down(eb, off, 64);
+        for (uint32_t i = 0; i < kResRun; ++i) {
+            mr[i] += __shfl_xor(mr[i], (int)off, 64);
+            mi[i] += __shfl_xor(mi[i], (int)off, 64);
         }
-        if (lane == 0) {
-            gst(d.rpart + 2 * unit, ea);
-            gst(d.rpart + 2 * unit + 1, eb);
+    }
+    double ea = 0.0, eb = 0.0;
+    if (valid && kl == 0) {
+        const uint32_t cnt = min(kResRun, d.S - j0);
+        const f4v* xs = reinterpret_cast<const f4v*>(io.x + t0);   // t0 is a multiple of kResRun: 64-byte aligned
+        f4v xv[kResRun / 2];
+#pragma unroll
+        for (uint32_t q = 0; q < kResRun / 2; ++q) xv[q] = gld(xs + q);
+#pragma unroll
+        for (uint32_t i = 0; i < kResRun; ++i) {
+            if (i < cnt) {
+                const double xr = xv[i >> 1][(i & 1u) * 2u], xi = xv[i >> 1][(i & 1u) * 2u + 1u];
+                const double er = xr - mr[i], ei = xi - mi[i];
+                ea += er * er + ei * ei;
+                eb += xr * xr + xi * xi;
+            }
         }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ea += __shfl_down(ea, off, 64);
+        eb += __shfl_down(eb, off, 64);
+    }
+    if (lane == 0) s_red[wv] = make_double2(ea, eb);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (uint32_t w = 0; w < NW; ++w) {
+            ta += s_red[w].x;
+            tb += s_red[w].y;
+        }
+        gst(d.rpart + 2 * unit, ta);
+        gst(d.rpart + 2 * unit + 1, tb);
     }
 }
 

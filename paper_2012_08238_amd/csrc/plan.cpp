@@ -117,7 +117,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         R.tau[r] = (uint32_t)(rng.next() & (R.N - 1));
     }
     R.tpos.resize(R.S);
-    for (uint32_t j = 0; j < R.S; ++j) R.tpos[j] = (uint32_t)(rng.next() & (R.N - 1));
+    for (uint32_t j = 0; j < R.S; j += kResRun) {   // runs of kResRun consecutive positions, one draw each
+        const uint32_t s0 = (uint32_t)(rng.next() & (R.N - 1)) & ~(kResRun - 1u);
+        for (uint32_t i = 0; i < kResRun && j + i < R.S; ++i) R.tpos[j + i] = s0 + i;
+    }
     // comb prefilter shifts: the next draws of the same stream
     R.comb_loops = (uint32_t)p.comb_loops;
     R.comb_b = R.comb_loops ? (uint32_t)p.comb_b : 0u;
@@ -212,7 +215,13 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         R.fft_p1_units = R.L * ((1u << lb2) / 16u);
         R.fft_p2_units = R.L * ((1u << lb1) / 16u);
     }
-    R.resid_blocks = (R.S + kResSamples - 1) / kResSamples;
+    // residual: a wave's lanes are (run, output subset) pairs, 2^resid_log2kl subsets per run
+    R.resid_log2kl = R.K >= 512 ? 4u : 3u;
+    {
+        const uint32_t runs = (R.S + kResRun - 1) / kResRun;
+        const uint32_t runs_per_wg = (kResNT / 64u) * (64u >> R.resid_log2kl);
+        R.resid_blocks = (runs + runs_per_wg - 1) / runs_per_wg;
+    }
     uint32_t P = 1;
     while (P < R.K) P <<= 1;
     R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies

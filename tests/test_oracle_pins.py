@@ -29,6 +29,23 @@ def check_splitmix64_vector():
         4593380528125082431, 16408922859458223821]
 
 
+def check_resid_positions():
+    # Residual positions in runs of 8 consecutive samples, one stream output per run
+    # start (rounded down to a multiple of 8), then the comb shifts: checked against
+    # the published SplitMix64 outputs for seed 1234567.
+    out = [6457827717110365317, 3203168211198807973, 9817491932198370423]
+    N = 1 << 20
+    for n_resid in (16, 13):
+        _, _, t = O.draw_permutations(N, 0, 1234567, n_resid)
+        s0, s1 = (out[0] & (N - 1)) & ~7, (out[1] & (N - 1)) & ~7
+        want = [s0 + i for i in range(8)] + [s1 + i for i in range(8)]
+        assert t.tolist() == want[:n_resid]
+        assert O.draw_comb_shifts(N, 0, 1234567, n_resid, 1).tolist() == [out[2] & (N - 1)]
+    _, _, t = O.draw_permutations(N, 3, 99, 4096)
+    assert np.all((t >= 0) & (t < N)) and np.all(t[::8] % 8 == 0)
+    assert np.all(t.reshape(-1, 8) - t[::8, None] == np.arange(8))
+
+
 def check_dft_scale():
     rng = np.random.default_rng(0)
     for N in (8, 64, 256):
