@@ -99,6 +99,7 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.strips = R.B / R.C;
     d.vote_units = R.vote_units;
     d.vote_upl = R.vote_upl;
+    d.vote_split = R.vote_split;
     d.resid_blocks = R.resid_blocks;
     d.resid_log2kl = R.resid_log2kl;
     d.est_units = R.est_units;

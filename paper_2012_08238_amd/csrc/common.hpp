@@ -60,6 +60,7 @@ struct SigDesc {
     uint32_t C, log2C, strips;  // strip bucketization tile: C columns x M rows
     uint32_t vote_units;        // vote workgroups
     uint32_t vote_upl;          // vote workgroups per enumerated loop (chunks of kVoteUnit candidates)
+    uint32_t vote_split;        // 1: votes tested in two phases (few selected buckets, T = L/2 + 1)
     uint32_t resid_blocks;      // residual workgroups
     uint32_t resid_log2kl;      // residual: lanes per run (the outputs split 2^resid_log2kl ways)
     uint32_t est_units;         // estimation workgroups (striding over the candidates)

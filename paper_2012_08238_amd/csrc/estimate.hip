@@ -144,21 +144,59 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
         if (ci0 < end) {
             const uint32_t h = s_slot[(ci0 >> log2M) - slot0];
             const uint32_t p0 = (h << log2M) - half + (ci0 & (M - 1u));   // mod 2^32: N divides it
-            uint32_t q[VL];
-#pragma unroll
-            for (int r = 0; r < VL; ++r) q[r] = cr[r] * p0 + half;
             uint32_t f = sinv0 * p0;
+            if (kExact && VL >= 4 && d.vote_split) {
+                // Few selected buckets (dK/B small) and T = L/2 + 1: the first P1 = L - T + 2
+                // loops (r0 and every loop before it among them) are tested for all
+                // candidates; one with fewer than 2 votes there cannot reach T (the other
+                // L - P1 = T - 2 loops add at most T - 2), so only the rest test those loops.
+                constexpr int P1 = VL - VL / 2 + 1;
+                uint32_t q[P1];
 #pragma unroll
-            for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-                uint32_t votes = 0;
+                for (int r = 0; r < P1; ++r) q[r] = cr[r] * p0 + half;
+                uint32_t smask = 0;   // bit qq: candidate qq needs the other loops
+                uint64_t cnt1 = 0;    // 4 bits per candidate: its votes among the first P1 loops
 #pragma unroll
-                for (int r = 0; r < VL; ++r) {
-                    votes |= test(r, q[r]);
-                    q[r] += cr[r];
+                for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+                    uint32_t votes = 0;
+#pragma unroll
+                    for (int r = 0; r < P1; ++r) {
+                        votes |= test(r, q[r]);
+                        q[r] += cr[r];
+                    }
+                    fv[qq] = f & maskN;
+                    f += sinv0;
+                    const uint32_t c1 = (uint32_t)__popc(votes);
+                    const bool first = (votes & before_r0) == 0u;
+                    emask |= (first && c1 >= T ? 1u : 0u) << qq;
+                    smask |= (first && c1 >= 2u && c1 < T ? 1u : 0u) << qq;
+                    cnt1 |= (uint64_t)c1 << (4u * qq);
                 }
-                fv[qq] = f & maskN;
-                emask |= voted(votes) << qq;
-                f += sinv0;
+                while (smask) {
+                    const uint32_t qq = (uint32_t)__builtin_ctz(smask);
+                    smask &= smask - 1u;
+                    const uint32_t p = p0 + qq;
+                    uint32_t v2 = 0;
+#pragma unroll
+                    for (int r = P1; r < VL; ++r) v2 |= test(r, cr[r] * p + half);
+                    if (((uint32_t)(cnt1 >> (4u * qq)) & 15u) + (uint32_t)__popc(v2) >= T) emask |= 1u << qq;
+                }
+            } else {
+                uint32_t q[VL];
+#pragma unroll
+                for (int r = 0; r < VL; ++r) q[r] = cr[r] * p0 + half;
+#pragma unroll
+                for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+                    uint32_t votes = 0;
+#pragma unroll
+                    for (int r = 0; r < VL; ++r) {
+                        votes |= test(r, q[r]);
+                        q[r] += cr[r];
+                    }
+                    fv[qq] = f & maskN;
+                    emask |= voted(votes) << qq;
+                    f += sinv0;
+                }
             }
         } else {
 #pragma unroll

@@ -36,6 +36,7 @@ struct Resolved {
     // units per stage
     uint32_t fold_units, vote_units, vote_upl, resid_blocks, vote_lds, strip_lds, resid_lds, fin_lds;
     uint32_t resid_log2kl;      // residual: lanes per run, log2
+    uint32_t vote_split;        // votes in two phases (dK/B <= 1/32, T = L/2 + 1, 4 <= L <= 16)
     uint32_t vote_dyn_lds;      // vote dynamic LDS: slot words + staged bitmaps (vote_lds, 0 = not staged)
     uint32_t est_units;
     uint32_t L_est() const { return est ? est->L : 0u; }

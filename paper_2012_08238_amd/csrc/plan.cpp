@@ -203,6 +203,9 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     // vote workgroups: chunks of kVoteUnit candidates that never straddle two loops
     R.vote_upl = (R.dK * R.M + kVoteUnit - 1) / kVoteUnit;
     R.vote_units = phase ? (R.L / 2 * R.dK + kDecUnit - 1) / kDecUnit : (R.L - R.T + 1) * R.vote_upl;
+    // two-phase vote tests where few buckets are selected (a random candidate rarely gets a
+    // second vote among the first L - T + 2 loops) and the threshold is the default majority
+    R.vote_split = (!phase && R.L >= 4 && R.L <= 16 && R.T == R.L / 2 + 1 && (uint64_t)R.dK * 32u <= R.B) ? 1u : 0u;
     const uint32_t wpl = (R.B + 31) / 32;
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
     R.vote_lds = vbytes <= 65536u ? vbytes : 0u;

@@ -154,6 +154,8 @@ def test_impulse_probe_sampled_set(dev):
     dict(N=16, K=1, B=2, L=3, w=4, seed=8),                     # smallest N
     dict(N=1 << 12, K=6, B=64, L=7, w=512, seed=9, vote_threshold=1),   # T = 1: large I'
     dict(N=1 << 14, K=20, B=256, L=9, w=2048, seed=10, n_resid=1000),   # ragged residual tail
+    dict(N=1 << 14, K=20, B=256, L=9, w=2048, seed=12, n_resid=1003),   # last residual run partial
+    dict(N=1 << 12, K=4, B=64, L=5, w=512, seed=13, n_resid=5),         # fewer samples than one run
     dict(N=1 << 12, K=3, B=8, L=5, w=64, seed=11),              # B < 32 (one bitmap word)
 ])
 def test_edge_cases(dev, cfg):
@@ -166,6 +168,22 @@ def test_edge_cases(dev, cfg):
                 vote_threshold=cfg.get("vote_threshold", 0), n_resid=n_resid)
     compare(g, r, cfg["K"], cfg["B"], cfg["L"], cfg["w"], cfg["seed"])
     check_residual(g, sig.x, r.trace["tpos"])
+
+
+@pytest.mark.parametrize("L,T", [(4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (9, 6)])
+def test_vote_two_phase(dev, L, T):
+    """Few selected buckets (dK/B = 1/64) with the default majority: the vote tests the
+    first L - T + 2 loops for every candidate and the rest only for those that can still
+    reach T. Candidate sets, supports and values as the oracle; T = 6 of 9 (not the
+    default) takes the one-phase tests."""
+    N, K, B = 1 << 20, 16, 2048
+    assert 2 * K * 32 <= B
+    sig = make_signal(N, K, 20.0, seed=900 + L)
+    g = _run(dev, sig.x, K=K, B=B, L=L, w=8 * B, seed=L, vote_threshold=T)
+    r = _oracle(sig.x, K, B, L, 8 * B, L, vote_threshold=T)
+    compare(g, r, K, B, L, 8 * B, L)
+    check_residual(g, sig.x, r.trace["tpos"])
+    assert set(g["idx"].tolist()) == set(sig.freqs.tolist())
 
 
 def test_zero_signal(dev):
