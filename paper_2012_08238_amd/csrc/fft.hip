@@ -114,12 +114,16 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* tlo, co
         if (j < NBF) {
             const int k = j & (Ns - 1);
             if (Ns > 1) {
+                // W^{r m1} for r = 1..R-1: W^{m1} from the two tables, the other powers by
+                // squarings and products (at most log2 R + 2 roundings deep) instead of two
+                // table reads each
+                const int m1 = k << TSHIFT;
+                float2 w[R];
+                w[1] = cmul(thi[m1 >> Cfg::LOG2TL], tlo[m1 & (Cfg::TL - 1)]);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    const int m = (r * k) << TSHIFT;
-                    const float2 w = cmul(thi[m >> Cfg::LOG2TL], tlo[m & (Cfg::TL - 1)]);
-                    v[q][r] = cmul(v[q][r], w);
-                }
+                for (int r = 2; r < R; ++r) w[r] = (r & 1) ? cmul(w[r - 1], w[1]) : cmul(w[r / 2], w[r / 2]);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
             }
             SmallDft<R>::run(v[q]);
             const int base = (j - k) * R + k;
