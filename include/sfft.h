@@ -105,14 +105,16 @@ typedef struct {
     int64_t w;              /* flat window length (time support), even */
     uint64_t seed;          /* SplitMix64 seed of sigma_r, tau_r and the residual samples */
     int32_t vote_threshold; /* T; 0 selects the strict majority floor(L/2)+1 */
-    int32_t n_resid;        /* S residual time samples; 0 selects 4096 */
+    int32_t n_resid;        /* S residual time samples; 0 selects 4096. They come in runs of 8
+                             * consecutive positions, one stream draw per run (its start rounded
+                             * down to a multiple of 8); the first S positions in run order */
     double gauss_c;         /* window length / (2 * Gaussian std); 0 selects the Fig. 1 ratio 4.861870431316438 */
     uint32_t flags;         /* SFFT_FLAG_* */
     int32_t strip_cols;     /* tile width of the strip bucketization (power of two); 0 = automatic */
     const uint32_t* sigma;  /* optional host uint32[L]: explicit odd scalings (NULL = draw from seed) */
     const uint32_t* tau;    /* optional host uint32[L]: explicit shifts; required iff sigma is given */
     /* Comb prefilter (the spike-train bucketization of the sFFT2.0 row, Eq.(15)-(16)):
-     * comb_loops in [0, 8] (0 = off) shifts tau_c drawn after the residual samples,
+     * comb_loops in [0, 8] (0 = off) shifts tau_c drawn after the residual runs' draws,
      * each taking the comb_b samples x[tau_c + j N/comb_b]; the comb_keep (0 = d*K)
      * largest of their comb_b-point DFT mark residues mod comb_b, and only
      * frequencies whose residue is marked by some shift can be located.
@@ -168,7 +170,7 @@ sfft_status sfft_params_init(sfft_params* p, int64_t N, int32_t K, int32_t B, in
 
 /* Build a plan on the current HIP device: validates, draws sigma_r (odd) and
  * tau_r from SplitMix64(seed) in the order sigma_0, tau_0, sigma_1, ...,
- * followed by the S residual positions; inverts sigma_r mod N; builds the flat
+ * followed by one draw per run of 8 residual positions; inverts sigma_r mod N; builds the flat
  * window (Eq.(12) x Eq.(13), FP64), the gain table
  * Gtab[o] = sum_n g_n e^{+2 pi i n o/N}, o in [-N/2B, N/2B) (FP64; Eq.(14)),
  * FFT twiddles and FP64 residual phase tables; uploads them and allocates one
