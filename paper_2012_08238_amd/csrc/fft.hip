@@ -150,13 +150,15 @@ __device__ __forceinline__ void fft_passes(float2* lds, const float2* tlo, const
 // LDS histogram. The first digit (shared by most keys) is counted with one
 // atomic per distinct digit per wave. Returns the value and how many keys equal
 // to it are among the k largest.
-template <int NT, int KPT>
+// With PASSES < 4 only the top 8 PASSES bits are decided: theta is then the k-th
+// largest key with its lower bits cleared, a lower bound of it.
+template <int NT, int KPT, int PASSES = 4>
 __device__ __forceinline__ void block_kth_largest(const uint32_t* key, const bool* kv, uint32_t k, uint32_t* hist,
                                                   uint32_t* bcast, uint32_t& theta, uint32_t& rank) {
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t prefix = 0, pmask = 0, kk = k;
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < PASSES; ++pass) {
         const int shift = 24 - 8 * pass;
         for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
         __syncthreads();
@@ -296,7 +298,8 @@ __device__ __forceinline__ void select_top(const float2* data, uint32_t dK, uint
 #pragma unroll
             for (int c = 0; c < CH; ++c) tmax[0] = max(tmax[0], key[c]);
             uint32_t theta0, rank0;
-            block_kth_largest<NT, 1>(tmax, tv, dK, hist, bcast, theta0, rank0);
+            // (its top 16 bits suffice: any lower bound of it keeps every selected key)
+            block_kth_largest<NT, 1, 2>(tmax, tv, dK, hist, bcast, theta0, rank0);
             uint32_t cnt = 0;
 #pragma unroll
             for (int c = 0; c < CH; ++c) cnt += (valid && key[c] >= theta0) ? 1u : 0u;
