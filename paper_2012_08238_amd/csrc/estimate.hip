@@ -81,12 +81,15 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
     uint32_t* sbits = sdyn + vote_slot_words(log2M);
     const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
     for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
-    uint32_t cr[VL], boff[VL];   // c_r and loop r's bitmap offset: uniform
+    // loop slots: slot 0 is r0 (it voted for every candidate it enumerates, so it is not
+    // tested), slots 1..r0 the loops before it, then the loops after it in order
+    uint32_t cr[VL], boff[VL];   // c_r and the bitmap offset of each slot's loop: uniform
 #pragma unroll
-    for (int r = 0; r < VL; ++r) {
-        const uint32_t rr = kExact ? (uint32_t)r : min((uint32_t)r, L - 1u);
-        cr[r] = ((CU32)d.sigma)[rr] * sinv0;
-        boff[r] = rr * wpl;
+    for (int j = 0; j < VL; ++j) {
+        const uint32_t r = j == 0 ? r0 : ((uint32_t)j <= r0 ? (uint32_t)j - 1u : (uint32_t)j);
+        const uint32_t rr = kExact ? r : min(r, L - 1u);
+        cr[j] = ((CU32)d.sigma)[rr] * sinv0;
+        boff[j] = rr * wpl;
     }
     const uint32_t ncomb = d.comb_loops, cmask = (1u << d.comb_log2b) - 1u;
     if (ncomb && restage) {
@@ -115,7 +118,7 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
         }
     }
     __syncthreads();
-    // bit r of the result: loop r selected the bucket of hash argument qv, i.e. bits
+    // bit j of the result: slot j's loop selected the bucket of hash argument qv, i.e. bits
     // [log2M, log2M + log2B) of qv: its bitmap word (bits above log2M + 5) and the bit in it
     const uint32_t wb_off = log2M + 5u, wb_w = (log2B > 5u ? log2B : 5u) - 5u, hb_w = log2B < 5u ? log2B : 5u;
     auto test = [&](int r, uint32_t qv) -> uint32_t {
@@ -130,8 +133,8 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
     const uint32_t half = M >> 1;
-    const uint32_t before_r0 = (1u << r0) - 1u;
-    // >= T votes, counted once: from the first loop that voted (loop r0 always did)
+    const uint32_t before_r0 = ((1u << r0) - 1u) << 1;   // slots of the loops before r0
+    // >= T votes, counted once: from the first loop that voted (loop r0, slot 0, always did)
     auto voted = [&](uint32_t votes) -> uint32_t {
         return ((votes & before_r0) == 0u && (uint32_t)__popc(votes) >= T) ? 1u : 0u;
     };
@@ -150,17 +153,17 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
                 // loops (r0 and every loop before it among them) are tested for all
                 // candidates; one with fewer than 2 votes there cannot reach T (the other
                 // L - P1 = T - 2 loops add at most T - 2), so only the rest test those loops.
-                constexpr int P1 = VL - VL / 2 + 1;
+                constexpr int P1 = VL - VL / 2 + 1;   // slots 0 .. P1-1: loops 0 .. P1-1
                 uint32_t q[P1];
 #pragma unroll
-                for (int r = 0; r < P1; ++r) q[r] = cr[r] * p0 + half;
+                for (int r = 1; r < P1; ++r) q[r] = cr[r] * p0 + half;
                 uint32_t smask = 0;   // bit qq: candidate qq needs the other loops
                 uint64_t cnt1 = 0;    // 4 bits per candidate: its votes among the first P1 loops
 #pragma unroll
                 for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-                    uint32_t votes = 0;
+                    uint32_t votes = 1u;
 #pragma unroll
-                    for (int r = 0; r < P1; ++r) {
+                    for (int r = 1; r < P1; ++r) {
                         votes |= test(r, q[r]);
                         q[r] += cr[r];
                     }
@@ -184,12 +187,12 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
             } else {
                 uint32_t q[VL];
 #pragma unroll
-                for (int r = 0; r < VL; ++r) q[r] = cr[r] * p0 + half;
+                for (int r = 1; r < VL; ++r) q[r] = cr[r] * p0 + half;
 #pragma unroll
                 for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-                    uint32_t votes = 0;
+                    uint32_t votes = 1u;
 #pragma unroll
-                    for (int r = 0; r < VL; ++r) {
+                    for (int r = 1; r < VL; ++r) {
                         votes |= test(r, q[r]);
                         q[r] += cr[r];
                     }
@@ -211,9 +214,9 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
             if (ci < end) {
                 const uint32_t h = s_slot[(ci >> log2M) - slot0];
                 const uint32_t p = (h << log2M) - half + (ci & (M - 1u));
-                uint32_t votes = 0;
+                uint32_t votes = 1u;
 #pragma unroll
-                for (int r = 0; r < VL; ++r) votes |= test(r, cr[r] * p + half);
+                for (int r = 1; r < VL; ++r) votes |= test(r, cr[r] * p + half);
                 fv[qq] = (sinv0 * p) & maskN;
                 emask |= voted(votes) << qq;
             }
