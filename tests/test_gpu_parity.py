@@ -156,6 +156,9 @@ def test_impulse_probe_sampled_set(dev):
     dict(N=1 << 14, K=20, B=256, L=9, w=2048, seed=10, n_resid=1000),   # ragged residual tail
     dict(N=1 << 14, K=20, B=256, L=9, w=2048, seed=12, n_resid=1003),   # last residual run partial
     dict(N=1 << 12, K=4, B=64, L=5, w=512, seed=13, n_resid=5),         # fewer samples than one run
+    dict(N=1 << 16, K=10, B=512, L=20, w=4096, seed=14),        # L > 16: the vote's generic instance
+    dict(N=1 << 16, K=10, B=512, L=32, w=4096, seed=15),        # the most loops
+    dict(N=1 << 14, K=6, B=256, L=1, w=2048, seed=16),          # one loop: T = 1, every enumerated frequency
     dict(N=1 << 12, K=3, B=8, L=5, w=64, seed=11),              # B < 32 (one bitmap word)
 ])
 def test_edge_cases(dev, cfg):
