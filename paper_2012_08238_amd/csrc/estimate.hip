@@ -789,7 +789,8 @@ __global__ __launch_bounds__(kSubNT) void subtract_kernel(Launch a) {
 // run are added by a fixed shuffle tree; the run's lane kl = 0 forms the two energy
 // sums of its samples; lanes, then waves, are added in a fixed order, and each
 // workgroup writes its two partial sums; residual_sum_kernel reduces them. Padding
-// outputs (index -1) are staged as f = 0, v = 0 and add exact zeros.
+// outputs (index -1) are staged as f = 0, v = 0 and add exact zeros. The per-sample
+// factors e^{+2 pi i f/N} are evaluated once per workgroup into LDS.
 __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
     constexpr uint32_t NW = kResNT / 64;
@@ -802,7 +803,8 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
     const uint32_t K = d.K, maskN = d.maskN, log2kl = d.resid_log2kl;
     const uint32_t rsh = d.log2N - d.tb;
     const double step = d.step;
-    float2* s_v = reinterpret_cast<float2*>(lds_raw);
+    double2* s_st = reinterpret_cast<double2*>(lds_raw);
+    float2* s_v = reinterpret_cast<float2*>(s_st + K);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + K);
     stage_rou<kResNT>(s_rou, d.rou, d.tb);
     for (uint32_t k = threadIdx.x; k < K; k += kResNT) {
@@ -811,6 +813,8 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
         s_f[k] = pad ? 0u : (uint32_t)f;
         s_v[k] = pad ? make_float2(0.f, 0.f) : gld(io.out_val + k);
     }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < K; k += kResNT) s_st[k] = phase_of(s_rou, s_f[k], rsh, step);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t KL = 1u << log2kl, kl = lane & (KL - 1u);
@@ -825,7 +829,7 @@ __global__ __launch_bounds__(kResNT) void residual_kernel(Launch a) {
         const uint32_t f = s_f[k];
         const double vr = (double)s_v[k].x, vi = (double)s_v[k].y;
         double2 p = phase_of(s_rou, (t0 * f) & maskN, rsh, step);   // e^{+2 pi i t0 f/N}
-        const double2 st = phase_of(s_rou, f, rsh, step);          // e^{+2 pi i f/N}
+        const double2 st = s_st[k];                                // e^{+2 pi i f/N}
 #pragma unroll
         for (uint32_t i = 0; i < kResRun; ++i) {
             mr[i] = fma(vr, p.x, fma(-vi, p.y, mr[i]));
@@ -993,6 +997,9 @@ hipError_t set_estimate_attributes() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&subtract_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kSubLdsMax);
     if (e == hipSuccess) e = Votes::set_lds(kVoteLdsMax);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kMaxK * 28);
     return e;
 }
 

@@ -227,7 +227,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     }
     uint32_t P = 1;
     while (P < R.K) P <<= 1;
-    R.resid_lds = R.K * 8u + R.K * 4u;   // staged outputs: values, frequencies
+    R.resid_lds = R.K * 16u + R.K * 8u + R.K * 4u;   // staged outputs: e^{+2 pi i f/N}, values, frequencies
     R.fin_lds = P * 8u + P * 4u;         // selected values, frequencies (sort size P)
     R.iterate = (p.flags & SFFT_FLAG_ITERATE) ? 1u : 0u;
     // estimation workgroups stride over the candidates, so their number only sets the
