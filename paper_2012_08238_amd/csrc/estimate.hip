@@ -52,6 +52,7 @@ __device__ __forceinline__ void append_wave(const uint32_t (&fv)[P], uint32_t em
 // instead of a multiply) and the bucket is a bit-field of it. Instances: VL = L for
 // L <= 16 (every test unconditional); VL = 32 covers 17..32 with the surplus tests
 // masked. STAGED: the L selected-bucket bitmaps are copied to LDS first.
+
 // One chunk of kVoteUnit candidates (unit `unit` of signal `sig`). sdyn: the chunk's
 // selected-bucket slots (vote_slot_words(log2 N/B) words), then (staged) the L
 // selected-bucket bitmaps, which (like the comb residues) are copied only when `restage`
@@ -101,7 +102,9 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
         }
     }
     if (STAGED && restage) {
-        // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte units)
+        // 16-byte loads, four in flight per thread (the LDS copy is sized to whole 16-byte
+        // units; the last unit may read up to 12 bytes past the bitmaps, inside the
+        // workspace's 256-byte aligned region, into LDS words that are never tested)
         typedef uint32_t u4v __attribute__((ext_vector_type(4)));
         const uint32_t nw4 = (L * wpl + 3u) >> 2;
         const u4v* src = reinterpret_cast<const u4v*>(jbits);
