@@ -993,8 +993,8 @@ hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds, hipStr
 // largest subtraction LDS: K = 4096 (P = 4096), B = 16384
 constexpr int kSubLdsMax = kMaxK * 8 + kMaxK * 4 + kMaxK * 4 + kMaxFftLds * 2;
 
-// largest vote dynamic LDS: the slots at N/B = 2 plus 64 KB of staged bitmaps
-constexpr int kVoteLdsMax = (int)vote_slot_words(1) * 4 + 65536;
+// largest vote dynamic LDS: the slots at N/B = 2 plus 96 KB of staged bitmaps
+constexpr int kVoteLdsMax = (int)vote_slot_words(1) * 4 + 98304;
 
 hipError_t set_estimate_attributes() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&subtract_kernel),

@@ -208,7 +208,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.vote_split = (!phase && R.L >= 4 && R.L <= 16 && R.T == R.L / 2 + 1 && (uint64_t)R.dK * 32u <= R.B) ? 1u : 0u;
     const uint32_t wpl = (R.B + 31) / 32;
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
-    R.vote_lds = vbytes <= 65536u ? vbytes : 0u;
+    R.vote_lds = vbytes <= 98304u ? vbytes : 0u;   // bitmaps staged in LDS up to 96 KB (B = 65536 at L <= 12)
     R.vote_dyn_lds = vote_slot_words(R.log2M) * 4u + R.vote_lds;
     // B-point FFT: in one workgroup's LDS up to kMaxFftLds, else two passes
     // (B = B1 * B2, tiles of 16 sequences per workgroup) and a selection workgroup per loop
