@@ -186,6 +186,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         C = (uint32_t)p.strip_cols;
     } else {
         C = std::min<uint32_t>(R.B, std::max<uint32_t>(2u, kStripLdsBytes / (8u * R.M)));
+        while (C > 32u && R.L * C > 4u * kFoldNT) C >>= 1;   // at most 4 (loop, column) items per thread
     }
     const bool strip_ok = C >= 2 && (uint64_t)R.M * C * 8ull <= 131072ull;
     if (p.flags & SFFT_FLAG_FOLD_STRIP) {
