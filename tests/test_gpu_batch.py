@@ -14,6 +14,8 @@ CONFIGS = [  # (N, K, B, L, w, seed, snr)
     (1 << 20, 50, 1024, 7, 8192, 3, 20.0),      # gather form
     (1 << 22, 100, 16384, 9, 131072, 4, 20.0),  # strip form, the benchmark shape
     (1 << 12, 3, 8, 4, 64, 5, -5.0),
+    (1 << 16, 10, 512, 20, 4096, 6, 15.0),      # L > 16: one vote launch for both of these,
+    (1 << 15, 8, 256, 32, 2048, 7, 15.0),       # each signal with its own L
 ]
 
 
