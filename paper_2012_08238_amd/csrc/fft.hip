@@ -58,7 +58,8 @@ struct SmallDft {
         for (int k = 0; k < R / 2; ++k) {
             const int t = k * (16 / R);
             const float2 w = make_float2(kC16[t], -kS16[t]);
-            const float2 ow = (k == 0) ? o[k] : cmul(o[k], w);
+            // W = -i (t = 4) is a swap and a sign: no multiplications by zero
+            const float2 ow = (k == 0) ? o[k] : (t == 4 ? mul_mi(o[k]) : cmul(o[k], w));
             v[k] = make_float2(e[k].x + ow.x, e[k].y + ow.y);
             v[k + R / 2] = make_float2(e[k].x - ow.x, e[k].y - ow.y);
         }
