@@ -249,7 +249,9 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
 // leaves room on every compute unit for other streams' work); each workgroup then takes
 // a contiguous share of the chunks, mostly of one signal, whose tables it copies once.
 template <int VL, bool STAGED>
-__global__ __launch_bounds__(kVoteNT) void vote_kernel(Launch a, uint32_t round, uint32_t units) {
+// Staged instances are held to 80 VGPRs (six waves per SIMD): four vote waves per SIMD then
+// leave room for a bucketization wave of another stream beside them.
+__global__ __launch_bounds__(kVoteNT, STAGED ? 6 : 1) void vote_kernel(Launch a, uint32_t round, uint32_t units) {
     extern __shared__ uint32_t sdyn[];
     __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
     const uint32_t b0 = (uint32_t)(((uint64_t)blockIdx.x * units) / gridDim.x);
