@@ -203,20 +203,20 @@ def gain_table(g: np.ndarray, N: int, B: int) -> np.ndarray:
     return out
 
 
+def gain_full(g: np.ndarray, N: int) -> np.ndarray:
+    """The flat window's complete response Gw(o) = sum_n g_n e^{+2 pi i n o / N} at
+    every offset o, as an array indexed by o mod N: N times the library inverse FFT
+    of the window zero-padded to length N. Gtab (gain_table) is its restriction
+    to |o| <= N/2B."""
+    w = g.shape[0]
+    padded = np.zeros(N, dtype=np.complex128)
+    padded[:w] = g
+    return np.fft.ifft(padded) * N
+
+
 # ---------------------------------------------------------------------------
 # Bucket hash (flat-filter example: bucket = round(f / (N/B)), 64/128 -> 1).
 # ---------------------------------------------------------------------------
-def gain_wide(g: np.ndarray, N: int, B: int) -> np.ndarray:
-    """Gain at the offsets of a bucket and its two neighbours: Gw[o + 3N/2B] =
-    sum_n g_n e^{+2 pi i n o / N} for o in [-3N/2B, 3N/2B) (exact FP64 sum)."""
-    M = N // B
-    n = np.arange(g.shape[0], dtype=np.int64)
-    out = np.empty(3 * M, dtype=np.complex128)
-    for k, o in enumerate(range(-3 * M // 2, 3 * M // 2)):
-        out[k] = np.sum(g * np.exp(2j * np.pi * ((o * n) % N) / N))
-    return out
-
-
 def bucket_of(p, N: int, B: int):
     """Bucket of permuted frequency p: round-half-up of p/(N/B), taken mod B
     (the top half-bucket wraps to bucket 0)."""
@@ -409,21 +409,20 @@ def loop_estimates(I, uhat_list, sigma, tau, G, N: int, B: int) -> np.ndarray:
 # Iterative framework: subtract the recovered coefficients before recovering
 # again (frameworks section, iterative framework).
 # ---------------------------------------------------------------------------
-def subtract_recovered(uhat_r: np.ndarray, f_list, v_list, sigma_r: int, tau_r: int, Gw: np.ndarray,
+def subtract_recovered(uhat_r: np.ndarray, f_list, v_list, sigma_r: int, tau_r: int, Gfull: np.ndarray,
                        N: int, B: int) -> np.ndarray:
-    """Loop r's bucket values with the recovered coefficients removed: each (f, v)
-    contributes v e^{+2 pi i tau f/N} Gw(sigma f - h N/B) to bucket h; its own bucket
-    and the two neighbours are corrected (further out the flat window's response
-    is below 1e-6 for w >= 8B and is dropped)."""
+    """Loop r's bucket values with the recovered coefficients removed. A lone
+    coefficient v at frequency f puts v e^{+2 pi i tau f/N} Gw(sigma f - h N/B) into
+    every bucket h (Eq.(9) for the permuted spectrum, the window's response
+    Gw = gain_full for the filter); that whole contribution is subtracted from
+    all B buckets, for each recovered (f, v)."""
     M = N // B
     u = np.array(uhat_r, dtype=np.complex128, copy=True)
+    centre = np.arange(B, dtype=np.int64) * M
     for f, v in zip(np.asarray(f_list, dtype=np.int64), np.asarray(v_list, dtype=np.complex128)):
         p = (int(sigma_r) * int(f)) % N
-        h0 = int(bucket_of(p, N, B))
-        o = int(offset_in_bucket(p, N, B))
         ph = np.exp(2j * np.pi * ((int(tau_r) * int(f)) % N) / N)
-        for j in (-1, 0, 1):
-            u[(h0 + j) % B] -= v * ph * Gw[o - j * M + 3 * M // 2]
+        u -= v * ph * Gfull[(p - centre) % N]
     return u
 
 
@@ -605,8 +604,8 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
     if iterate:
         keep1 = idx >= 0
         K1, V1 = idx[keep1], val[keep1]
-        Gw = gain_wide(g, N, B)
-        ures = [subtract_recovered(uhat[r], K1, V1, int(sigma[r]), int(tau[r]), Gw, N, B) for r in range(L)]
+        Gf = gain_full(g, N)
+        ures = [subtract_recovered(uhat[r], K1, V1, int(sigma[r]), int(tau[r]), Gf, N, B) for r in range(L)]
         sel2 = [select_buckets(u, d * K) for u in ures]
         J2 = [s[0] for s in sel2]
         decodes2 = None

@@ -330,36 +330,63 @@ def check_comb_keeps_support():
         assert set(b.trace["I"].tolist()) <= set(a.trace["I"].tolist())
 
 
-def check_gain_wide():
-    # against the library FFT of the zero-padded window, over the bucket and its neighbours
-    for N, B, w in ((1 << 10, 16, 128), (1 << 12, 64, 512)):
+def check_gain_full():
+    # the complete response against the definition summed directly in FP64, at offsets
+    # near the bucket and far out (both signs, the wrap at N/2), and its restriction to
+    # one bucket width against the gain table
+    for N, B, w in ((1 << 10, 16, 128), (1 << 12, 64, 512), (1 << 12, 64, 96), (256, 16, 32)):
         g = O.flat_window(w, B)
-        Gw = O.gain_wide(g, N, B)
-        gp = np.zeros(N)
-        gp[:w] = g
-        full = np.fft.ifft(gp) * N
+        full = O.gain_full(g, N)
+        n = np.arange(w)
         M = N // B
-        o = np.arange(-3 * M // 2, 3 * M // 2)
-        assert np.max(np.abs(Gw - full[o % N])) < 1e-12 * np.max(np.abs(Gw))
-        assert np.max(np.abs(Gw[M:2 * M] - O.gain_table(g, N, B))) < 1e-12 * np.max(np.abs(Gw))
+        for o in (0, 1, -1, M // 2, -M // 2, 3 * M // 2 + 1, -5 * M, N // 2 - 1, -N // 2, 7 * M + 3):
+            direct = np.sum(g * np.exp(2j * np.pi * ((n * o) % N) / N))
+            assert abs(full[o % N] - direct) < 1e-12 * np.sum(np.abs(g))
+        o = np.arange(-M // 2, M // 2)
+        assert np.max(np.abs(full[o % N] - O.gain_table(g, N, B))) < 1e-12 * np.max(np.abs(full))
+
+
+def _tones_in_time(N, freqs, vals):
+    t = np.arange(N, dtype=np.int64)
+    x = np.zeros(N, dtype=np.complex128)
+    for f, v in zip(freqs, vals):
+        x += v * np.exp(2j * np.pi * ((t * int(f)) % N) / N)
+    return x
+
+
+def check_subtract_rebucketize():
+    # Bucketization is linear in x, so removing the recovered coefficients from the
+    # buckets must equal bucketizing x with those tones removed in time (a tone of
+    # coefficient v is v e^{+2 pi i t f/N} under the 1/N forward scale of Eq.(2)).
+    # Every bucket is compared, at windows whose response reaches far beyond the
+    # neighbouring buckets (w = 2B, 1.5B, 4B) and at w = 8B, w = N, B = 8.
+    rng = np.random.default_rng(31)
+    for N, B, w in ((1 << 12, 64, 128), (1 << 12, 64, 96), (1 << 14, 128, 512), (1 << 12, 64, 512),
+                    (1 << 10, 32, 1 << 10), (1 << 12, 8, 64)):
+        g = O.flat_window(w, B)
+        Gf = O.gain_full(g, N)
+        x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        freqs = rng.choice(N, 6, replace=False)
+        vals = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+        for sigma, tau in ((int(rng.integers(N // 2)) * 2 + 1, int(rng.integers(N))), (1, 0), (N - 1, N - 1)):
+            uh = O.bucketize(x, g, sigma, tau, B)
+            got = O.subtract_recovered(uh, freqs, vals, sigma, tau, Gf, N, B)
+            want = O.bucketize(x - _tones_in_time(N, freqs, vals), g, sigma, tau, B)
+            assert np.max(np.abs(got - want)) < 1e-11 * max(1.0, np.max(np.abs(uh)))
 
 
 def check_subtract_tone():
-    # a lone tone's buckets minus its own contribution leave (almost) nothing in its
-    # bucket and both neighbours; w = 8B puts the rest of the response below 1e-6
-    N, B, w = 1 << 12, 64, 512
-    g = O.flat_window(w, B)
-    Gw = O.gain_wide(g, N, B)
-    for f, c, sigma, tau in ((100, 0.3 - 0.7j, 5, 9), (4095, 1.0, 1001, 4000), (2048 + 31, 1j, 3, 1)):
-        xh = np.zeros(N, dtype=np.complex128)
-        xh[f] = c
-        x = np.fft.ifft(xh) * N
-        uh = O.bucketize(x, g, sigma, tau, B)
-        res = O.subtract_recovered(uh, [f], [c], sigma, tau, Gw, N, B)
-        h0 = int(O.bucket_of((sigma * f) % N, N, B))
-        for j in (-1, 0, 1):
-            assert abs(res[(h0 + j) % B]) < 1e-6 * abs(c)
-        assert np.max(np.abs(res)) < 1e-5 * abs(c)
+    # a lone tone minus its own recovered coefficient leaves nothing in any bucket,
+    # whatever the window (here w = 2B, whose response spans many buckets)
+    N, B = 1 << 12, 64
+    for w in (128, 512):
+        g = O.flat_window(w, B)
+        Gf = O.gain_full(g, N)
+        for f, c, sigma, tau in ((100, 0.3 - 0.7j, 5, 9), (4095, 1.0, 1001, 4000), (2048 + 31, 1j, 3, 1)):
+            x = _tones_in_time(N, [f], [c])
+            uh = O.bucketize(x, g, sigma, tau, B)
+            res = O.subtract_recovered(uh, [f], [c], sigma, tau, Gf, N, B)
+            assert np.max(np.abs(res)) < 1e-12 * abs(c)
     # one noiseless tone: the correction round keeps it exact
     sig = make_signal(1 << 12, 1, None, seed=9)
     r = O.sfft(sig.x, 1, 64, 5, 512, seed=2, iterate=True)
@@ -602,7 +629,7 @@ def test_iteration_resolves_collisions():
 
 
 # --------------------------------------------------------------------------- planted mistakes
-_GOOD = {n: getattr(O, n) for n in ("gain_table", "loop_estimates")}
+_GOOD = {n: getattr(O, n) for n in ("gain_table", "loop_estimates", "subtract_recovered")}
 
 
 def _bucket_half_down(p, N, B):
@@ -661,6 +688,24 @@ def _pairs_same_shift(sigma, tau, N):
     return sigma, tau
 
 
+def _subtract_neighbours_only(uhat_r, f_list, v_list, sigma_r, tau_r, Gfull, N, B):
+    # the bucket of sigma f and its two neighbours only
+    M = N // B
+    u = np.array(uhat_r, dtype=np.complex128, copy=True)
+    for f, v in zip(np.asarray(f_list, dtype=np.int64), np.asarray(v_list, dtype=np.complex128)):
+        p = (int(sigma_r) * int(f)) % N
+        h0 = int(O.bucket_of(p, N, B))
+        ph = np.exp(2j * np.pi * ((int(tau_r) * int(f)) % N) / N)
+        for j in (-1, 0, 1):
+            h = (h0 + j) % B
+            u[h] -= v * ph * Gfull[(p - h * M) % N]
+    return u
+
+
+def _subtract_conjugate_phase(uhat_r, f_list, v_list, sigma_r, tau_r, Gfull, N, B):
+    return _GOOD["subtract_recovered"](uhat_r, f_list, v_list, sigma_r, -int(tau_r) % N, Gfull, N, B)
+
+
 MUTANTS = [
     ("bucket_of", _bucket_half_down),
     ("gain_table", _gain_wrong_sign),
@@ -671,6 +716,8 @@ MUTANTS = [
     ("decode_phase", _decode_wrong_sign),
     ("decode_phase", _decode_truncates),
     ("pair_permutations", _pairs_same_shift),
+    ("subtract_recovered", _subtract_neighbours_only),
+    ("subtract_recovered", _subtract_conjugate_phase),
 ]
 
 
