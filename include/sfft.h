@@ -69,8 +69,13 @@ typedef enum {
                                          energy-concentration method) instead of the coordinate-wise median */
 #define SFFT_FLAG_ITERATE 0x20u       /* one round of the iterative framework (frameworks section): the K
                                          recovered coefficients (f, v) are subtracted from every loop's
-                                         buckets, v e^{+2 pi i tau f/N} Gw(sigma f - h N/B) from the bucket h
-                                         of sigma f and its two neighbours (Gw = sum_n g_n e^{+2 pi i n o/N});
+                                         buckets, v e^{+2 pi i tau f/N} Gw(sigma f - h N/B) from each bucket h
+                                         (Gw = sum_n g_n e^{+2 pi i n o/N}, Eq.(9)): from every bucket, or
+                                         from the bucket of sigma f and the R on either side when a bound
+                                         on |Gw| beyond them is <= 1e-6 of the centre gain (smallest R >= 1;
+                                         sfft_plan_desc.sub_reach_*). A window whose response needs more
+                                         than 129 buckets (or a gain table of more than 2^22 entries) gives
+                                         SFFT_E_UNSUPPORTED;
                                          the residual buckets are selected and voted again (frequencies
                                          already recovered excluded), new candidates are estimated from the
                                          residual buckets, each recovered value is corrected by the combined
@@ -144,6 +149,12 @@ typedef struct {
     size_t table_bytes;     /* resident device tables */
     size_t workspace_bytes; /* one execution's device workspace */
     double sampled_fraction_expected; /* 1-(1-w/N)^L (Table 2, sFFT1.0 sampling, log N -> L) */
+    /* SFFT_FLAG_ITERATE: each recovered coefficient of bucket h0 is subtracted from the buckets
+     * h0 - sub_reach_lo .. h0 + sub_reach_hi (all B of them when the two add up to B - 1), and
+     * sub_tail_bound bounds the window response in every other bucket relative to the centre
+     * gain (<= 1e-6; 0 when no bucket is left out). All three are 0 without the flag. */
+    int32_t sub_reach_lo, sub_reach_hi;
+    double sub_tail_bound;
 } sfft_plan_desc;
 
 /* Host copies of one execution's intermediates (all pointers host, caller-owned,
@@ -187,6 +198,10 @@ sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_
 
 /* Resolved description of the plan. */
 sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out);
+
+/* Host only, no device: the description that sfft_plan_ex(p) would give (the same
+ * validation and status; table and workspace sizes as that plan would allocate them). */
+sfft_status sfft_params_describe(const sfft_params* p, sfft_plan_desc* out);
 
 /* Host-only build of the plan's FP64 tables without any device (for checking
  * the host logic): sigma, sigma_inv, tau uint32[L + est_loops]; tpos uint32[S];

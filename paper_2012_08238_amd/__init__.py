@@ -18,7 +18,7 @@ from ._capi import (SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, SFFT_FLAG_XCD_O
                     SfftError, check,
                     load)
 
-__all__ = ["PlanParams", "Plan", "Batch", "Server", "host_tables", "load", "SfftError",
+__all__ = ["PlanParams", "Plan", "Batch", "Server", "host_tables", "params_describe", "load", "SfftError",
            "SFFT_FLAG_FOLD_GATHER", "SFFT_FLAG_FOLD_STRIP", "SFFT_FLAG_XCD_ORDER", "SFFT_FLAG_NO_RESIDUAL",
            "SFFT_FLAG_MEAN_ESTIMATE", "SFFT_FLAG_ITERATE", "SFFT_FLAG_PHASE_LOCATION",
            "SFFT_FLAG_FFT_TWO_PASS"]
@@ -84,6 +84,15 @@ def _stream_handle(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream)
+
+
+def params_describe(params: PlanParams) -> dict:
+    """The description sfft_plan_ex would give these parameters, without a device."""
+    p, keep = params.to_c()
+    d = _capi.PlanDesc()
+    check(load().sfft_params_describe(C.byref(p), C.byref(d)), "sfft_params_describe")
+    del keep
+    return {f: getattr(d, f) for f, _ in _capi.PlanDesc._fields_}
 
 
 def host_tables(params: PlanParams) -> dict:

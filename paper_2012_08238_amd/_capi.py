@@ -39,7 +39,8 @@ class PlanDesc(C.Structure):
                 ("L", C.c_int32), ("d", C.c_int32), ("T", C.c_int32), ("n_resid", C.c_int32),
                 ("fold_mode", C.c_int32), ("strip_cols", C.c_int32), ("cand_cap", C.c_int64),
                 ("table_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
-                ("sampled_fraction_expected", C.c_double)]
+                ("sampled_fraction_expected", C.c_double),
+                ("sub_reach_lo", C.c_int32), ("sub_reach_hi", C.c_int32), ("sub_tail_bound", C.c_double)]
 
 
 class Trace(C.Structure):
@@ -67,6 +68,7 @@ SIGNATURES = [
     ("sfft_destroy", C.c_int, [C.c_void_p]),
     ("sfft_plan_get_perms", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sfft_plan_describe", C.c_int, [C.c_void_p, C.POINTER(PlanDesc)]),
+    ("sfft_params_describe", C.c_int, [C.POINTER(Params), C.POINTER(PlanDesc)]),
     ("sfft_host_tables", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p]),
     ("sfft_execute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

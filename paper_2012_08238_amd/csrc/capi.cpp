@@ -72,6 +72,8 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.rec_f = reinterpret_cast<uint32_t*>(ws + w.rec_f);
     d.rec_v = reinterpret_cast<float2*>(ws + w.rec_v);
     d.iterate = R.iterate;
+    d.sub_rl = R.sub_rl;
+    d.sub_rh = R.sub_rh;
     d.phase = R.phase;
     d.comb_loops = R.comb_loops;
     d.comb_log2b = R.comb_log2b;
@@ -349,9 +351,7 @@ sfft_status sfft_plan_get_perms(sfft_plan_t p, uint32_t* sigma, uint32_t* sigma_
     return SFFT_OK;
 }
 
-sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out) {
-    if (!p || !out) return set_error(SFFT_E_INVALID, "null argument");
-    const Resolved& R = p->R;
+static void fill_desc(const Resolved& R, size_t tab_bytes, size_t ws_bytes, sfft_plan_desc* out) {
     out->N = R.N;
     out->w = R.w;
     out->K = (int32_t)R.K;
@@ -363,9 +363,32 @@ sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out) {
     out->fold_mode = (int32_t)R.mode;
     out->strip_cols = (int32_t)R.C;
     out->cand_cap = R.cap;
-    out->table_bytes = p->tab_bytes;
-    out->workspace_bytes = p->ws_bytes;
+    out->table_bytes = tab_bytes;
+    out->workspace_bytes = ws_bytes;
     out->sampled_fraction_expected = 1.0 - pow(1.0 - (double)R.w / (double)R.N, (double)R.L);
+    out->sub_reach_lo = (int32_t)R.sub_rl;
+    out->sub_reach_hi = (int32_t)R.sub_rh;
+    out->sub_tail_bound = R.sub_bound;
+}
+
+sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out) {
+    if (!p || !out) return set_error(SFFT_E_INVALID, "null argument");
+    fill_desc(p->R, p->tab_bytes, p->ws_bytes, out);
+    return SFFT_OK;
+}
+
+sfft_status sfft_params_describe(const sfft_params* p, sfft_plan_desc* out) {
+    if (!p || !out) return set_error(SFFT_E_INVALID, "null argument");
+    Resolved R;
+    std::string err;
+    const sfft_status st = resolve_params(*p, &R, &err);
+    if (st != SFFT_OK) return set_error(st, err);
+    size_t tab = table_layout(R).total, ws = workspace_layout(R).total;
+    if (R.est) {   // the estimation-only loops' tables and workspace follow, 256-byte aligned
+        tab = ((tab + 255) & ~size_t(255)) + table_layout(*R.est).total;
+        ws = ((ws + 255) & ~size_t(255)) + workspace_layout(*R.est).total;
+    }
+    fill_desc(R, tab, ws, out);
     return SFFT_OK;
 }
 

@@ -29,7 +29,8 @@ struct SigDesc {
     const double2* rou;         // [2^tb] e^{2 pi i j / 2^tb}, FP64
     const uint32_t* comb_tau;   // [comb_loops] time shifts of the comb prefilter
     const float2* ctw;          // [Bc] e^{-2 pi i m/Bc}
-    const float2* gw;           // [3M] gain at offsets o in [-3M/2, 3M/2): gw[o + 3M/2] (iteration only)
+    const float2* gw;           // [(sub_rl+sub_rh+1) M] gain at offsets o in [-c, (sub_rl+sub_rh+1) M - c),
+                                // c = sub_rh M + M/2: gw[o + c] (iteration only)
     // workspace
     float2* uhat;               // [L][B] bucket values in column order (bucket of column col is
                                 // sigma^{-1}(col - tau) mod B), then their B-point DFT in bucket order
@@ -70,6 +71,7 @@ struct SigDesc {
     uint32_t comb_log2b;        // log2 Bc
     uint32_t comb_keep;         // residues kept per comb loop
     uint32_t iterate;           // 1: one subtraction round after the first recovery
+    uint32_t sub_rl, sub_rh;    // subtraction reach in buckets below / above a coefficient's own
     uint32_t phase;             // 1: location by phase encoding over loop pairs (2j, 2j+1)
     const SigDesc* eloops;      // estimation-only loops of the same signal (own B, window, tables), or null
     uint32_t L_est;             // their number

@@ -696,8 +696,9 @@ __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t rou
 // Iterative framework (frameworks section), subtraction step for loop r: a
 // recovered coefficient (f, v) with p = sigma_r f mod N in bucket h0 at offset
 // o = p - h0 N/B contributes v e^{+2 pi i (tau_r f mod N)/N} Gw(o - j N/B) to bucket
-// h0 + j (Eq.(9) with the flat window's gain); j = -1, 0, 1 are removed, further
-// buckets lie in the window's stopband. Each touched bucket is rewritten by one
+// h0 + j (Eq.(9) with the flat window's gain). It is removed from the buckets
+// j = -sub_rl .. sub_rh, the plan's reach: every bucket, or as many as leave less
+// than 1e-6 of the centre gain in the others. Each touched bucket is rewritten by one
 // thread that subtracts its contributions in a fixed order (coefficients sorted
 // by (h0, index)), so the result is independent of scheduling. Unit 0 also
 // clears the candidate counter for the second vote. One workgroup per
@@ -764,15 +765,17 @@ __global__ __launch_bounds__(kSubNT) void subtract_kernel(Launch a) {
     __syncthreads();
     float2* u = d.uhat + (size_t)r * B;
     const float2* gw = d.gw;
-    const int32_t c0 = (int32_t)(3u * M / 2u);
+    const int32_t rl = (int32_t)d.sub_rl, rh = (int32_t)d.sub_rh;
+    const int32_t c0 = rh * (int32_t)M + (int32_t)(M >> 1);   // gw index of offset 0
     for (uint32_t b = threadIdx.x; b < B; b += kSubNT) {
-        // runs of the buckets b-1 (contributing with j = +1), b (j = 0), b+1 (j = -1)
-        const uint32_t hs[3] = {(b - 1u) & (B - 1u), b, (b + 1u) & (B - 1u)};
-        if (s_first[hs[0]] == 0xFFFFu && s_first[hs[1]] == 0xFFFFu && s_first[hs[2]] == 0xFFFFu) continue;
+        // the coefficients of bucket hh = b - j reach bucket b, j = -rl .. rh, in that order
+        bool any = false;
+        for (int32_t j = -rl; j <= rh; ++j) any |= s_first[(b - (uint32_t)j) & (B - 1u)] != 0xFFFFu;
+        if (!any) continue;
         float2 acc = gld(u + b);
-        for (int q = 0; q < 3; ++q) {
-            const uint32_t hh = hs[q];
-            const int32_t sh = (q - 1) * (int32_t)M + c0;   // gw index = o - j M + 3M/2, j = 1 - q
+        for (int32_t j = -rl; j <= rh; ++j) {
+            const uint32_t hh = (b - (uint32_t)j) & (B - 1u);
+            const int32_t sh = c0 - j * (int32_t)M;   // gw index = o - j M + c0
             for (uint32_t i = s_first[hh]; i < n1 && (s_key[i] >> 12) == hh; ++i) {
                 const uint32_t k = s_key[i] & 4095u;
                 const float2 c = cmul(s_vph[k], gld(gw + (s_off[k] + sh)));

@@ -24,6 +24,8 @@ struct Resolved {
     uint32_t fft_mode;          // 0 one-workgroup FFT (B <= 16384), 1 two-pass FFT
     uint32_t comb_b, comb_log2b, comb_loops, comb_keep, comb_words;  // comb prefilter
     uint32_t iterate, sub_lds;  // one subtraction round (iterative framework); its LDS bytes
+    uint32_t sub_rl, sub_rh;    // subtraction reach: a coefficient is removed from buckets h0 - sub_rl .. h0 + sub_rh
+    double sub_bound;           // bound on what it leaves beyond them, relative to the centre gain
     uint32_t phase;             // location by phase encoding over loop pairs
     uint32_t est_only;          // a plan's estimation-only loops (bucketization + FFT only)
     std::shared_ptr<const struct Resolved> est;  // the estimation-only loops of this plan, or null
@@ -47,14 +49,15 @@ struct Resolved {
 struct HostTables {
     std::vector<double> window;                 // g_n, n < w
     std::vector<std::complex<double>> gain;     // Gtab[o], o = -M/2 .. M/2-1
-    std::vector<std::complex<double>> gain_wide;  // [3M] gain at o = -3M/2 .. 3M/2-1 (iteration only)
+    std::vector<std::complex<double>> gain_wide;  // [(sub_rl+sub_rh+1) M] gain at o = -(sub_rh M + M/2) ..
+                                                  // (sub_rl M + M/2) - 1 (iteration only)
     std::vector<float> gT;                      // [B][Mw4]
     std::vector<float> invG;                    // [M] (re, im) pairs of 1/Gtab
     std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
     std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N}, two bit fields
     std::vector<double> rou;                    // (re, im) pairs of e^{2 pi i j / 2^tb}
     std::vector<float> ctw;                     // [comb_b] (re, im) pairs of e^{-2 pi i m/comb_b}
-    std::vector<float> gw;                      // [3M] (re, im) pairs of gain_wide (iteration only)
+    std::vector<float> gw;                      // (re, im) pairs of gain_wide (iteration only)
 };
 
 constexpr double kDefaultGaussC = 4.861870431316438;  // 516 / (2 * 16 * sqrt(11)), Fig. 1 example

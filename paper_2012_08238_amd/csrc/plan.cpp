@@ -13,7 +13,78 @@ namespace sfft {
 
 namespace {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+constexpr double kSubTail = 1e-6;           // largest response left beyond the subtraction reach
+constexpr uint32_t kSubMaxBuckets = 129;    // buckets a coefficient is removed from, at most
+constexpr uint64_t kSubMaxGain = 1u << 22;  // entries of the subtraction gain table, at most
+
+// Bounds on the flat window's response Gw(o) = sum_{n<w} g_n e^{+2 pi i n o/N}, from the
+// window's definition: g_n = e^{-t^2/2s^2} sin(pi t/B)/(pi t), t = n - w/2, s = w/(2 c).
+// The same formula over every integer t has, by Poisson summation, the response
+// e^{+pi i w o/N} sum_k F(o/N - k) with F the continuous spectrum of the product: the
+// boxcar of width 1/B convolved with the Gaussian's spectrum,
+//   F(nu) = (erf(sqrt2 pi s (nu + 1/2B)) - erf(sqrt2 pi s (nu - 1/2B))) / 2 >= 0,
+// largest at 0 and decreasing in |nu|. The samples cut off at t < -w/2 and t >= w/2 change
+// the response by at most Tc = sum over those t of |g|, which is below
+//   (4 / (pi w)) (e^{-c^2/2} + s sqrt(pi/2) erfc(c/sqrt2))
+// (each one-sided sum of the decreasing e^{-t^2/2s^2}/(pi t), t >= w/2, is at most its first
+// term plus the integral from w/2). So |Gw(0)| >= F(0) - Tc and, for |o| in
+// [(R + 1/2) N/B, N/2], |Gw(o)| <= F((R + 1/2)/B) + 2 sum_{m>=0} F(1/2 + m) + Tc.
+double window_F(double nu, double s, double B) {
+    const double a = 1.4142135623730951 * 3.14159265358979323846 * s;
+    nu = fabs(nu);
+    const double lo = nu - 0.5 / B, hi = nu + 0.5 / B;
+    if (lo > 0) return 0.5 * (erfc(a * lo) - erfc(a * hi));
+    return 0.5 * (erf(a * hi) - erf(a * lo));
+}
+
+double window_cut(double w, double c) {
+    const double s = w / (2.0 * c);
+    return 4.0 / (3.14159265358979323846 * w) *
+           (exp(-0.5 * c * c) + s * 1.2533141373155003 * erfc(c / 1.4142135623730951));
+}
+
+// Largest response beyond R buckets on either side, relative to the centre gain
+// (a bound; +inf when the centre bound is not positive).
+double response_tail(uint32_t R, const Resolved& P) {
+    const double B = (double)P.B, s = (double)P.w / (2.0 * P.gauss_c);
+    const double cut = window_cut((double)P.w, P.gauss_c);
+    const double centre = window_F(0.0, s, B) - cut;
+    if (!(centre > 0)) return INFINITY;
+    double alias = 0.0;
+    for (int m = 0; m < 64; ++m) alias += window_F(0.5 + m, s, B);
+    return (window_F(((double)R + 0.5) / B, s, B) + 2.0 * alias + cut) / centre;
+}
 }  // namespace
+
+// Reach of the subtraction round: the smallest R >= 1 whose tail bound is at most kSubTail
+// (buckets h0 - R .. h0 + R), or every bucket (h0 - B/2 + 1 .. h0 + B/2) once 2R + 1 would
+// exceed B. SFFT_E_UNSUPPORTED when that needs more than kSubMaxBuckets buckets or a gain
+// table of more than kSubMaxGain entries.
+static sfft_status subtraction_reach(Resolved* R, std::string* err) {
+    for (uint32_t r = 1;; ++r) {
+        if (2 * r + 1 > R->B) {   // every bucket: nothing is left out
+            R->sub_rl = R->B / 2 - 1;
+            R->sub_rh = R->B / 2;
+            R->sub_bound = 0.0;
+            break;
+        }
+        const double t = response_tail(r, *R);
+        if (t <= kSubTail) {
+            R->sub_rl = R->sub_rh = r;
+            R->sub_bound = t;
+            break;
+        }
+        if (2 * r + 1 > kSubMaxBuckets) break;
+    }
+    const uint64_t nb = (uint64_t)R->sub_rl + R->sub_rh + 1;
+    if (R->sub_rh == 0 || nb > kSubMaxBuckets || nb * R->M > kSubMaxGain) {
+        *err = "the subtraction round needs the window's response beyond 64 buckets (or a gain table of more "
+               "than 2^22 entries) below 1e-6 of its centre: widen w or raise gauss_c";
+        return SFFT_E_UNSUPPORTED;
+    }
+    return SFFT_OK;
+}
 
 sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err) {
     Resolved R{};
@@ -249,6 +320,10 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.est_units = (uint32_t)std::max(1.0, std::min(32.0, std::ceil(expect / (4.0 * kFinNT))));
     // subtraction round: phased values [K], sort keys [P], offsets [K], run starts [B] (16 bit)
     R.sub_lds = R.iterate ? ((R.K * 8u + P * 4u + R.K * 4u + R.B * 2u + 15u) & ~15u) : 0u;
+    if (R.iterate) {
+        const sfft_status st = subtraction_reach(&R, err);
+        if (st != SFFT_OK) return st;
+    }
     R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;
     R.fold_variant = fold_variant(R.mode, R.strip_lds, R.L << R.log2C, R.Mw4 / 4);
     *out = std::move(R);
@@ -291,15 +366,17 @@ void build_tables(const Resolved& R, HostTables* t) {
         t->rou[2 * j + 1] = sin(a);
     }
     // gain table Gtab[o] = sum_n g_n e^{+2 pi i (n o mod N)/N}, exact FP64 sum, at
-    // o = -M/2 .. M/2-1; with the subtraction round at o = -3M/2 .. 3M/2-1 (the
-    // offsets of a bucket's two neighbours too), whose middle M entries are Gtab
-    const uint32_t G = R.iterate ? 3 * M : M;
+    // o = -M/2 .. M/2-1; with the subtraction round at the offsets of every bucket in
+    // its reach too, o = -(sub_rh M + M/2) .. (sub_rl M + M/2) - 1, of which the M
+    // entries from sub_rh M on are Gtab
+    const uint32_t G = R.iterate ? (R.sub_rl + R.sub_rh + 1) * M : M;
+    const uint32_t gc = R.iterate ? R.sub_rh * M + M / 2 : M / 2;   // index of o = 0
     std::vector<std::complex<double>>& gout = R.iterate ? t->gain_wide : t->gain;
     gout.assign(G, std::complex<double>(0.0, 0.0));
     const uint32_t lomask = nlo - 1;
     auto work = [&](uint32_t k0, uint32_t k1) {
         for (uint32_t k = k0; k < k1; ++k) {
-            const int64_t o = (int64_t)k - (int64_t)(G / 2);
+            const int64_t o = (int64_t)k - (int64_t)gc;
             const uint32_t step = (uint32_t)((o % (int64_t)N + (int64_t)N) % (int64_t)N);
             double re = 0.0, im = 0.0;
             uint32_t m = 0;  // n * o mod N, advanced by step
@@ -326,9 +403,10 @@ void build_tables(const Resolved& R, HostTables* t) {
     }
     for (auto& x : th) x.join();
     if (R.iterate) {
-        t->gain.assign(t->gain_wide.begin() + M, t->gain_wide.begin() + 2 * M);
-        t->gw.resize(6 * (size_t)M);
-        for (uint32_t k = 0; k < 3 * M; ++k) {
+        const size_t g0 = (size_t)R.sub_rh * M;
+        t->gain.assign(t->gain_wide.begin() + g0, t->gain_wide.begin() + g0 + M);
+        t->gw.resize(2 * (size_t)G);
+        for (uint32_t k = 0; k < G; ++k) {
             t->gw[2 * k] = (float)t->gain_wide[k].real();
             t->gw[2 * k + 1] = (float)t->gain_wide[k].imag();
         }
@@ -406,7 +484,7 @@ TabLayout table_layout(const Resolved& R) {
     l.rou = take((size_t)16 << R.tb);
     l.ctau = take((size_t)R.comb_loops * 4);
     l.ctw = take((size_t)R.comb_b * 8);
-    l.gw = take(R.iterate ? (size_t)3 * R.M * 8 : 16);
+    l.gw = take(R.iterate ? (size_t)(R.sub_rl + R.sub_rh + 1) * R.M * 8 : 16);
     l.total = off;
     return l;
 }

@@ -124,11 +124,63 @@ def test_iterate_validation_and_gain():
     with pytest.raises(S.SfftError) as e:
         S.host_tables(S.PlanParams(N=1 << 20, K=100, B=1 << 15, L=5, w=1 << 17, flags=S.SFFT_FLAG_ITERATE))
     assert e.value.status == _capi.SFFT_E_UNSUPPORTED
-    # the round widens the gain table to three bucket widths; its middle is the plain table, bitwise
-    kw = dict(N=1 << 14, K=10, B=128, L=5, w=512, n_resid=8)
-    a = S.host_tables(S.PlanParams(**kw))
-    b = S.host_tables(S.PlanParams(flags=S.SFFT_FLAG_ITERATE, **kw))
-    assert np.array_equal(a["gain"], b["gain"])
+    # the round widens the gain table to the buckets of its reach; the plain table within it
+    # is the same, bitwise, at w = 4B (reach 2), 8B (reach 1) and w = B (every bucket)
+    for N, B, w in ((1 << 14, 128, 512), (1 << 14, 128, 1024), (1 << 12, 64, 64)):
+        kw = dict(N=N, K=10, B=B, L=5, w=w, n_resid=8)
+        a = S.host_tables(S.PlanParams(**kw))
+        b = S.host_tables(S.PlanParams(flags=S.SFFT_FLAG_ITERATE, **kw))
+        assert np.array_equal(a["gain"], b["gain"])
+
+
+def _outside_reach(N, B, lo, hi):
+    # offsets o = o0 - j N/B (o0 in [-N/2B, N/2B), j in [-lo, hi]) reach buckets of the
+    # reach; True for the offsets (mod N) that none of them produces
+    M = N // B
+    covered = np.zeros(N, bool)
+    covered[np.arange(-(hi * M + M // 2), lo * M + M // 2) % N] = True
+    return ~covered
+
+
+@pytest.mark.parametrize("N,B,w,c_g", [
+    (1 << 14, 128, 1024, 0), (1 << 14, 128, 512, 0), (1 << 14, 128, 256, 0), (1 << 14, 128, 192, 0),
+    (1 << 12, 64, 96, 0), (1 << 18, 512, 4096, 0), (1 << 16, 1024, 2048, 0), (1 << 12, 8, 64, 0),
+    (1 << 14, 256, 3072, 6.0), (1 << 14, 128, 1024, 4.0), (256, 16, 32, 0), (1 << 12, 64, 64, 0),
+    (1 << 10, 16, 64, 2.0)])
+def test_subtraction_reach_bounds_the_response(N, B, w, c_g):
+    """The subtraction round's reach (the buckets a recovered coefficient is removed from):
+    the oracle's complete window response (library inverse FFT of the padded window) beyond
+    it stays within the plan's bound, which is at most 1e-6 of the centre gain; or the reach
+    is every bucket."""
+    d = S.params_describe(S.PlanParams(N, 2, B, 5, w, gauss_c=c_g, flags=S.SFFT_FLAG_ITERATE))
+    lo, hi, bound = d["sub_reach_lo"], d["sub_reach_hi"], d["sub_tail_bound"]
+    Gf = O.gain_full(O.flat_window(w, B, c_g) if c_g else O.flat_window(w, B), N)
+    if lo + hi + 1 == B:
+        assert (lo, hi, bound) == (B // 2 - 1, B // 2, 0.0)
+        assert not _outside_reach(N, B, lo, hi).any()
+        return
+    assert 1 <= lo == hi and 2 * hi + 1 < B and 0 < bound <= 1e-6
+    tail = np.max(np.abs(Gf[_outside_reach(N, B, lo, hi)])) / abs(Gf[0])
+    assert tail <= bound
+    # the reach also leaves out nothing the method needs: one bucket less leaves more than
+    # the bound (the window's response is still falling off there)
+    if hi > 1:
+        assert np.max(np.abs(Gf[_outside_reach(N, B, hi - 1, hi - 1)])) / abs(Gf[0]) > bound
+
+
+def test_subtraction_reach_values_and_refusal():
+    it = S.SFFT_FLAG_ITERATE
+    reach = lambda N, B, w: S.params_describe(S.PlanParams(N, 2, B, 5, w, flags=it))["sub_reach_hi"]  # noqa: E731
+    # the response falls off over about 8/(w/B) buckets at the default Gaussian ratio
+    assert [reach(1 << 16, 256, a * 256) for a in (16, 8, 4, 2)] == [1, 1, 2, 4]
+    assert S.params_describe(S.PlanParams(1 << 14, 10, 128, 5, 512))["sub_reach_hi"] == 0   # no round
+    # a window whose response stays above 1e-6 over more than 129 buckets: refused
+    with pytest.raises(S.SfftError) as e:
+        S.params_describe(S.PlanParams(1 << 20, 10, 1024, 5, 512, flags=it))
+    assert e.value.status == _capi.SFFT_E_UNSUPPORTED
+    with pytest.raises(S.SfftError) as e:
+        S.params_describe(S.PlanParams(1 << 20, 10, 1024, 5, 8192, gauss_c=2.0, flags=it))
+    assert e.value.status == _capi.SFFT_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("N,K,B,L,w,seed", [
