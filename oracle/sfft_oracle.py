@@ -619,17 +619,21 @@ def sfft(x, K: int, B: int, L: int, w: int, seed: int = 0, d: int = 2,
         I2 = np.nonzero(voted2)[0].astype(np.int64)
         e2 = loop_estimates(I2, ures, sigma, tau, G, N, B)
         eK = loop_estimates(K1, ures, sigma, tau, G, N, B)
+        use2 = None
         if phase:
             # new frequencies from the pairs that decode them in the residual; the
             # recovered values (single-ton estimates) are kept
-            v2 = combine_masked(e2, decoding_loops(I2, ures, J2, sigma, N, B), combine)
+            use2 = decoding_loops(I2, ures, J2, sigma, N, B)
+            v2 = combine_masked(e2, use2, combine)
             vK = V1
         else:
             v2 = comb(e2) if I2.shape[0] else np.zeros(0, dtype=np.complex128)
             vK = V1 + (comb(eK) if K1.shape[0] else 0)
+        Iall, vall = np.concatenate([I2, K1]), np.concatenate([v2, vK])
         it = dict(idx1=idx, val1=val, final_margin1=fmargin, ures=ures, J2=J2,
-                  select_margin2=[s[1] for s in sel2], I2=I2, e2=e2, eK=eK, decodes2=decodes2)
-        idx, val, fmargin = finalize(np.concatenate([I2, K1]), np.concatenate([v2, vK]), K)
+                  select_margin2=[s[1] for s in sel2], I2=I2, e2=e2, eK=eK, decodes2=decodes2,
+                  I_all2=Iall, v_all2=vall, use2=use2)
+        idx, val, fmargin = finalize(Iall, vall, K)
     e_res, e_in = residual_energy(x, idx, val, tpos) if len(tpos) else (0.0, 0.0)
     trace = dict(sigma=sigma, tau=tau, sigma_inv=sigma_inv, g=g, G=G, uhat=uhat,
                  J=J, select_margin=[s[1] for s in sel], counts=counts, I=I,

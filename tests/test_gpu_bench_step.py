@@ -1,6 +1,7 @@
 """The benchmark's timed step, in its own launch configuration: 64 resident signals
-of N=2^22, K=100, SNR 20 dB through one batch graph per step (B=16384, L=9, w=8B,
-two-pass B-point FFT), three steps in flight on three streams. Every batch output
+of N=2^22, K=100, SNR 20 dB through one batch graph per step (B=16384, L=9, w=8B),
+three steps in flight on three streams; with the benchmark's default one-workgroup
+B-point FFT and with the two-pass form it offers. Every batch output
 is bitwise the signal's single execution; sampled signals are compared with the
 FP64 oracle (spectra, selections, candidates, support, values, residual) and every
 signal's support with its planted tones."""
@@ -8,7 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
-from test_gpu_parity import _oracle, check_residual, compare
+from parity import compare
+from test_gpu_parity import _oracle, check_residual
 
 pytestmark = pytest.mark.gpu
 
@@ -17,7 +19,8 @@ W = 8 * B
 SAMPLED = (0, 37, 63)
 
 
-def test_benchmark_step_configuration(dev):
+@pytest.mark.parametrize("fft", ["one-workgroup", "two-pass"])
+def test_benchmark_step_configuration(dev, fft):
     import torch
     import paper_2012_08238_amd as S
     xs, truth = [], []
@@ -25,7 +28,7 @@ def test_benchmark_step_configuration(dev):
         x, f, _ = make_signal_torch(N, K, 20.0, derive_seed(0, i), dev)
         xs.append(x)
         truth.append(np.sort(f))
-    plan = S.Plan(N, K, B, L, W, seed=SEED, flags=S.SFFT_FLAG_FFT_TWO_PASS)
+    plan = S.Plan(N, K, B, L, W, seed=SEED, flags=S.SFFT_FLAG_FFT_TWO_PASS if fft == "two-pass" else 0)
     batches, outs, streams = [], [], []
     for j in range(INFLIGHT):
         batches.append(S.Batch([plan] * M, branches=1))
@@ -60,6 +63,7 @@ def test_benchmark_step_configuration(dev):
                  trace=plan.trace(), perms=plan.perms(), desc=plan.desc)
         x64 = xs[i].cpu().numpy().astype(np.complex128)
         r = _oracle(x64, K, B, L, W, SEED)
-        compare(g, r, K, B, L, W, SEED)
+        p = compare(g, r, K, B, L, W, SEED)
+        assert p.certain == K and p.values == K, p
         check_residual(g, x64, r.trace["tpos"])
     plan.close()

@@ -7,7 +7,8 @@ import pytest
 
 import oracle.sfft_oracle as O
 from paper_2012_08238_amd.signals import make_signal
-from test_gpu_parity import SEL_MARGIN, check_residual, compare
+from parity import compare
+from test_gpu_parity import SEL_MARGIN, check_residual
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +71,7 @@ def test_comb_parity(dev, cfg):
     r = O.sfft(sig.x.astype(np.complex64).astype(np.complex128), cfg["K"], cfg["B"], cfg["L"], cfg["w"],
                seed=cfg["seed"], comb_b=cfg["comb_b"], comb_loops=cfg["comb_loops"], comb_keep=keep)
     exact = _check_comb(g, r, sig.x, cfg["comb_b"], keep)
-    compare(g, r, cfg["K"], cfg["B"], cfg["L"], cfg["w"], cfg["seed"], cand_exact=exact)
+    compare(g, r, cfg["K"], cfg["B"], cfg["L"], cfg["w"], cfg["seed"], cand_exact=exact, comb_b=cfg["comb_b"])
     check_residual(g, sig.x, r.trace["tpos"])
 
 

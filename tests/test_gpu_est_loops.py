@@ -6,7 +6,8 @@ import pytest
 
 import oracle.sfft_oracle as O
 from paper_2012_08238_amd.signals import make_signal
-from test_gpu_parity import check_residual, compare
+from parity import compare
+from test_gpu_parity import check_residual
 
 pytestmark = pytest.mark.gpu
 

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from paper_2012_08238_amd.signals import make_signal
-from test_gpu_parity import _oracle, _run, check_residual, compare
+from parity import compare
+from test_gpu_parity import _oracle, _run, check_residual
 
 pytestmark = pytest.mark.gpu
 

@@ -1,8 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Both sides get the same complex64 signal. Integer work must match exactly:
-permutations, the sampled index set, selected buckets (where the oracle's
-selection margin is not a near-tie), candidate sets, recovered supports.
+permutations, the sampled index set, selected buckets, candidate sets and
+recovered supports, wherever the oracle's decision is not a near-tie at FP32
+precision; near-ties are checked for validity and counted (parity.compare).
 Floating point: bucket spectra within 1e-5 of the loop's largest bucket,
 values within |v - v_ref| <= 1e-4 |v_ref|, FP64 residual within 1e-9.
 """
@@ -11,13 +12,11 @@ import pytest
 
 import oracle.sfft_oracle as O
 from paper_2012_08238_amd.signals import impulse, make_signal
+from parity import VAL_RTOL, compare  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
-VAL_RTOL = 1e-4           # values, relative
-UHAT_TOL = 1e-5           # bucket spectra, relative to the loop's max |uhat|
-SEL_MARGIN = 1e-4         # compare J_r only when the oracle's dK-boundary gap exceeds this
-FINAL_MARGIN = 1e-3       # compare supports only when the oracle's K-boundary gap exceeds this
+SEL_MARGIN = 1e-4         # a comb prefilter's selection is compared where its boundary gap exceeds this
 
 
 def _run(dev, x64, **plan_kw):
@@ -40,51 +39,6 @@ def _oracle(x64, K, B, L, w, seed, d=2, vote_threshold=0, n_resid=4096, combine=
                   n_resid=n_resid, combine=combine)
 
 
-def compare(g, r, K, B, L, w, seed, check_values=True, cand_exact=True):
-    """cand_exact=False when a prefilter's selection was a rounding-level tie (the
-    candidate sets may then differ by frequencies whose estimates are ~0)."""
-    N = r.trace["counts"].shape[0]
-    sigma, sigma_inv, tau = g["perms"]
-    assert np.array_equal(sigma, r.trace["sigma"].astype(np.uint32))
-    assert np.array_equal(tau, r.trace["tau"].astype(np.uint32))
-    assert np.array_equal(sigma_inv, r.trace["sigma_inv"].astype(np.uint32))
-    uh = g["trace"]["uhat"]
-    all_sel_equal = True
-    for rr in range(L):
-        ref = r.trace["uhat"][rr]
-        scale = max(np.max(np.abs(ref)), 1e-30)
-        assert np.max(np.abs(uh[rr] - ref)) <= UHAT_TOL * scale, f"loop {rr} bucket spectra"
-        jl = np.sort(g["trace"]["jlist"][rr])
-        bits = g["trace"]["jbits"][rr]
-        from_bits = np.nonzero([(bits[h >> 5] >> (h & 31)) & 1 for h in range(B)])[0]
-        assert np.array_equal(from_bits, jl), "bitmap and list disagree"
-        assert len(np.unique(jl)) == jl.shape[0]
-        if r.trace["select_margin"][rr] > SEL_MARGIN:
-            assert np.array_equal(jl, r.trace["J"][rr]), f"loop {rr} selected buckets"
-        else:
-            all_sel_equal = all_sel_equal and np.array_equal(jl, r.trace["J"][rr])
-    cand = np.sort(g["trace"]["cand"].astype(np.int64))
-    assert len(np.unique(cand)) == cand.shape[0], "duplicate candidates"
-    if all_sel_equal and cand_exact:
-        assert np.array_equal(cand, np.sort(r.trace["I"])), "candidate set"
-    idx = g["idx"]
-    if all_sel_equal and r.trace["final_margin"] > FINAL_MARGIN:
-        assert np.array_equal(idx, r.idx), "recovered support"
-        if check_values:
-            ok = idx >= 0
-            ref = r.val[ok]
-            err = np.abs(g["val"][ok] - ref)
-            mag = np.abs(ref)
-            # median cancellation guard: tiny |v_ref| relative to the loop estimates
-            e = r.trace["e"]
-            pos = {f: k for k, f in enumerate(r.trace["I"].tolist())}
-            m_f = np.array([np.median(np.abs(e[:, pos[f]])) for f in idx[ok]])
-            well = mag >= 1e-3 * m_f
-            assert np.all(err[well] <= VAL_RTOL * mag[well]), f"values: max rel {np.max(err[well] / mag[well])}"
-            assert np.all(g["val"][~ok] == 0)
-    return all_sel_equal
-
-
 def check_residual(g, x64, tpos):
     er, ein = O.residual_energy(x64.astype(np.complex64).astype(np.complex128), g["idx"], g["val"], tpos)
     res = g["resid"]
@@ -99,7 +53,12 @@ def test_c1_exact_sparse(dev, seed):
     sig = make_signal(1 << 14, 10, None, seed=100 + seed)
     g = _run(dev, sig.x, K=10, B=128, L=5, w=512, seed=seed)
     r = _oracle(sig.x, 10, 128, 5, 512, seed)
-    compare(g, r, 10, 128, 5, 512, seed)
+    p = compare(g, r, 10, 128, 5, 512, seed)
+    # every one of the K slots is a certain entry or a valid choice from the tie band
+    # (seeds 1 and 2: the 10th and 11th largest are true unit tones 4e-9 apart), and
+    # every returned value is compared
+    assert p.certain + p.band == 10 and p.values == 10, p
+    assert p.certain == (1 if seed in (1, 2) else 10), p
     check_residual(g, sig.x, r.trace["tpos"])
 
 

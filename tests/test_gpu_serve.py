@@ -1,6 +1,7 @@
 """Serving loop on the GPU: every request's result is bitwise the one its
 parameter set gives alone, whether it ran alone or in a mix of other sizes,
-under a tight memory budget with table eviction, and with waves overlapping."""
+under a tight memory budget with table eviction, and with waves overlapping;
+served results of C5's sizes (up to N = 2^24) against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -95,26 +96,79 @@ def test_serve_mix_matches_alone(dev):
 
 
 def test_serve_waves_overlap(dev):
+    """Requests submitted while earlier waves run go out as further waves on the other
+    streams: at least two waves are on the device at once, and every result is bitwise
+    its single execution."""
     import torch
     import paper_2012_08238_amd as S
     c = MIX[5]
-    cfgs = [c] * 6
-    xs = _signals(dev, cfgs, 950)
-    refs = _alone(S, dev, cfgs, xs)
-    srv = S.Server(hbm_budget_bytes=1 << 30, max_inflight=8, n_streams=4)
+    n = 24
+    xs = _signals(dev, [c] * 6, 950)
+    refs = _alone(S, dev, [c] * 6, xs)
+    srv = S.Server(hbm_budget_bytes=2 << 30, max_inflight=n, n_streams=4)
     h = srv.prepare(_params(S, c))
-    outs = [_outputs(dev, c) for _ in cfgs]
+    outs = [_outputs(dev, c) for _ in range(n)]
     torch.cuda.synchronize()
-    tickets = []
-    for i in range(6):
-        tickets.append(srv.submit(h, xs[i], *outs[i]))
+    tickets = [srv.submit(h, xs[i % 6], *outs[i]) for i in range(n)]
     for t in tickets:
         assert srv.wait(t)[1] == 0
-    for i in range(6):
-        _same(outs[i], refs[i], c)
+    for i in range(n):
+        _same(outs[i], refs[i % 6], c)
     s = srv.stats()
-    assert s["completed"] == 6
+    assert s["completed"] == n
+    assert s["max_waves_in_flight"] >= 2, s
     srv.close()
+
+
+# C5's sizes with the serving loop's parameter rule (B next to sqrt(N K), w = 8B, L = 9):
+# (N, K, SNR dB, seed); N = 2^24 at both ends of K (two-pass and one-workgroup FFT)
+C5_MIX = [(1 << 24, 1000, 20.0, 1), (1 << 24, 20, 5.0, 2), (1 << 18, 300, 0.0, 3),
+          (1 << 20, 700, 30.0, 4), (1 << 22, 64, 12.0, 5)]
+
+
+def test_served_results_match_oracle(dev):
+    """Requests of C5's sizes (N = 2^18 .. 2^24) served in a mix, each twice: every
+    served result is bitwise its plan executed alone, and is compared with the FP64
+    oracle through the parity protocol (the alone execution supplies the trace of
+    the same computation)."""
+    import dataclasses
+
+    import torch
+    import oracle.sfft_oracle as O
+    import paper_2012_08238_amd as S
+    from paper_2012_08238_amd import autotune as A
+    from parity import compare
+    from test_gpu_parity import check_residual
+    prms = [dataclasses.replace(A.rule_params(N, K, seed=sd), n_resid=1000) for N, K, _, sd in C5_MIX]
+    sigs = [make_signal(N, K, snr, seed=1500 + sd) for N, K, snr, sd in C5_MIX]
+    xs = [torch.from_numpy(sg.x.astype(np.complex64)).to(dev) for sg in sigs]
+    order = [0, 2, 1, 4, 3, 1, 0, 3, 2, 4]
+    srv = S.Server(hbm_budget_bytes=6 << 30, max_inflight=16, n_streams=3)
+    outs = [(torch.full((prms[j].K,), -7, dtype=torch.int64, device=dev),
+             torch.zeros(prms[j].K, dtype=torch.complex64, device=dev),
+             torch.zeros(2, dtype=torch.float64, device=dev)) for j in order]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(prms[j], xs[j], *o) for j, o in zip(order, outs)]
+    for t in tickets:
+        assert srv.wait(t)[1] == 0
+    assert srv.stats()["completed"] == len(order)
+    srv.close()
+    for j, (prm, sg, x) in enumerate(zip(prms, sigs, xs)):
+        plan = S.Plan.from_params(prm)
+        ai, av, ar = plan(x, residual=True)
+        torch.cuda.synchronize()
+        for k in [k for k, jj in enumerate(order) if jj == j]:
+            assert torch.equal(outs[k][0], ai) and torch.equal(outs[k][1].view(torch.float32), av.view(torch.float32))
+            assert torch.equal(outs[k][2], ar)
+        k = order.index(j)
+        g = dict(idx=outs[k][0].cpu().numpy(), val=outs[k][1].cpu().numpy().astype(np.complex128),
+                 resid=outs[k][2].cpu().numpy(), trace=plan.trace(), perms=plan.perms())
+        plan.close()
+        x64 = sg.x.astype(np.complex64).astype(np.complex128)
+        r = O.sfft(x64, prm.K, prm.B, prm.L, prm.w, seed=prm.seed, n_resid=1000)
+        p = compare(g, r, prm.K, prm.B, prm.L)
+        assert p.values >= 1, p
+        check_residual(g, sg.x, r.trace["tpos"])
 
 
 def test_serve_tight_budget_evicts(dev):

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from paper_2012_08238_amd.signals import derive_seed, make_signal_torch, uneven_batch_specs
-from test_gpu_parity import _oracle, compare
+from parity import compare
+from test_gpu_parity import _oracle
 
 pytestmark = pytest.mark.gpu
 
