@@ -225,6 +225,19 @@ sfft_status sfft_execute(sfft_plan_t p, const void* x_dev, int64_t* out_idx, voi
 sfft_status sfft_execute_ex(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val,
                             double* out_resid, sfft_stream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): sfft_execute_ex with the same arguments and results,
+ * bitwise, that calls no allocating routine. Its workspace is one 64 MiB array per GPU
+ * (held until the process ends; its address is taken when the first plan is created on
+ * that GPU) instead of the plan's own workspace. Every call on a GPU shares that array
+ * and leaves its contents behind: calls that overlap on one GPU (any plans, any streams)
+ * race, so the caller orders them on one stream or waits between them. A plan whose
+ * workspace (sfft_plan_desc.workspace_bytes) exceeds 64 MiB returns SFFT_E_UNSUPPORTED;
+ * SFFT_E_DEVICE if the array's address could not be taken. sfft_plan_read_trace keeps
+ * reading the plan's own workspace (the last sfft_execute/_ex). */
+sfft_status sfft_execute_noalloc(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val,
+                                 double* out_resid, sfft_stream_t stream);
+
 /* Synchronously copy the intermediates of the plan's last execution to host
  * buffers (waits for that execution). For parity checking. */
 sfft_status sfft_plan_read_trace(sfft_plan_t p, sfft_trace* t);

@@ -73,6 +73,7 @@ SIGNATURES = [
                                    C.c_void_p, C.c_void_p]),
     ("sfft_execute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sfft_execute_ex", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("sfft_execute_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sfft_plan_read_trace", C.c_int, [C.c_void_p, C.POINTER(Trace)]),
     ("sfft_batch_create", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32]),
     ("sfft_batch_create_ex", C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_int32]),

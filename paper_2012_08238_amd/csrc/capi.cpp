@@ -182,7 +182,12 @@ struct sfft_plan_s {
     char* d_tab = nullptr;       // tables of the plan, then (at tab_e) of its estimation-only loops
     char* d_ws = nullptr;        // workspace, idem (at ws_e)
     size_t tab_e = 0, ws_e = 0;
-    SigDesc* d_desc = nullptr;   // [1 + has estimation-only loops]
+    SigDesc* d_desc = nullptr;   // [2 nd]: nd = 1 + has estimation-only loops descriptors on the plan's
+                                 // workspace, then nd on the device's scratch array (if it fits)
+    int nd = 1;
+    bool scratch_ok = false;     // the workspace fits the scratch array and its address is known
+    std::string scratch_err;
+    sfft_status scratch_st = SFFT_E_UNSUPPORTED;
     size_t tab_bytes = 0, ws_bytes = 0;
     hipEvent_t done = nullptr;
     hipStream_t last_stream = nullptr;
@@ -235,19 +240,37 @@ sfft_status plan_create(const sfft_params& p, sfft_plan_t* out) {
     pl->ws_bytes = ws_total;
     if (hipMalloc(&pl->d_tab, h.size()) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device tables"));
     if (hipMalloc(&pl->d_ws, ws_total) != hipSuccess) return cleanup(set_error(SFFT_E_NOMEM, "device workspace"));
-    if (hipMalloc(&pl->d_desc, sizeof(SigDesc) * nd) != hipSuccess)
+    if (hipMalloc(&pl->d_desc, sizeof(SigDesc) * 2 * nd) != hipSuccess)
         return cleanup(set_error(SFFT_E_NOMEM, "device descriptor"));
+    pl->nd = nd;
     e = hipMemcpy(pl->d_tab, h.data(), h.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "table upload"));
     e = hipMemset(pl->d_ws, 0, ws_total);
     if (e != hipSuccess) return cleanup(hip_fail(e, "workspace clear"));
-    SigDesc d[2];
+    SigDesc d[4];
     d[0] = make_desc(Rr, pl->d_tab, pl->d_ws);
     if (Rr.est) {
         d[1] = make_desc(*Rr.est, pl->d_tab + pl->tab_e, pl->d_ws + pl->ws_e);
         link_est(&d[0], pl->d_desc + 1, Rr);
     }
-    e = hipMemcpy(pl->d_desc, d, sizeof(SigDesc) * nd, hipMemcpyHostToDevice);
+    // the same descriptors on this device's scratch array, for sfft_execute_noalloc
+    char* sp = nullptr;
+    const hipError_t se = scratch_address(pl->device, &sp);
+    if (se != hipSuccess) {
+        pl->scratch_err = std::string("scratch array address: ") + hipGetErrorString(se);
+        pl->scratch_st = SFFT_E_DEVICE;
+    } else if (ws_total > scratch_bytes()) {
+        pl->scratch_err = "the plan's workspace (" + std::to_string(ws_total) + " bytes) exceeds the scratch array (" +
+                          std::to_string(scratch_bytes()) + " bytes)";
+    } else {
+        pl->scratch_ok = true;
+        d[nd] = make_desc(Rr, pl->d_tab, sp);
+        if (Rr.est) {
+            d[nd + 1] = make_desc(*Rr.est, pl->d_tab + pl->tab_e, sp + pl->ws_e);
+            link_est(&d[nd], pl->d_desc + nd + 1, Rr);
+        }
+    }
+    e = hipMemcpy(pl->d_desc, d, sizeof(SigDesc) * (pl->scratch_ok ? 2 * nd : nd), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "descriptor upload"));
     e = hipEventCreateWithFlags(&pl->done, hipEventDisableTiming);
     if (e != hipSuccess) return cleanup(hip_fail(e, "event"));
@@ -278,6 +301,33 @@ sfft_status check_busy(sfft_plan_t p, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace sfft {
+
+sfft_status plan_execute(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val, double* out_resid,
+                         sfft_stream_t stream, bool scratch) {
+    if (!p || !x_dev || !out_idx || !out_val) return set_error(SFFT_E_INVALID, "null argument");
+    if (scratch && !p->scratch_ok) return set_error(p->scratch_st, p->scratch_err);
+    if (!aligned16(x_dev)) return set_error(SFFT_E_INVALID, "x_dev must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(out_val) & 7u) || (reinterpret_cast<uintptr_t>(out_idx) & 7u) ||
+        (reinterpret_cast<uintptr_t>(out_resid) & 7u))
+        return set_error(SFFT_E_INVALID, "outputs must be 8-byte aligned");
+    std::lock_guard<std::mutex> lk(p->mu);
+    HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    sfft_status st = check_busy(p, s);
+    if (st != SFFT_OK) return st;
+    HIP_TRY(hipGetLastError(), "earlier device work");
+    IoDesc io{reinterpret_cast<const float2*>(x_dev), out_idx, reinterpret_cast<float2*>(out_val), out_resid};
+    st = launch_single(p->R, p->d_desc + (scratch ? p->nd : 0), io, s);
+    if (st != SFFT_OK) return st;
+    HIP_TRY(hipEventRecord(p->done, s), "hipEventRecord");
+    p->last_stream = s;
+    p->launched = true;
+    return SFFT_OK;
+}
+
+}  // namespace sfft
 
 extern "C" {
 
@@ -414,26 +464,10 @@ sfft_status sfft_host_tables(const sfft_params* p, uint32_t* sigma, uint32_t* si
     return SFFT_OK;
 }
 
+
 sfft_status sfft_execute_ex(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val, double* out_resid,
                             sfft_stream_t stream) {
-    if (!p || !x_dev || !out_idx || !out_val) return set_error(SFFT_E_INVALID, "null argument");
-    if (!aligned16(x_dev)) return set_error(SFFT_E_INVALID, "x_dev must be 16-byte aligned");
-    if ((reinterpret_cast<uintptr_t>(out_val) & 7u) || (reinterpret_cast<uintptr_t>(out_idx) & 7u) ||
-        (reinterpret_cast<uintptr_t>(out_resid) & 7u))
-        return set_error(SFFT_E_INVALID, "outputs must be 8-byte aligned");
-    std::lock_guard<std::mutex> lk(p->mu);
-    HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    sfft_status st = check_busy(p, s);
-    if (st != SFFT_OK) return st;
-    HIP_TRY(hipGetLastError(), "earlier device work");
-    IoDesc io{reinterpret_cast<const float2*>(x_dev), out_idx, reinterpret_cast<float2*>(out_val), out_resid};
-    st = launch_single(p->R, p->d_desc, io, s);
-    if (st != SFFT_OK) return st;
-    HIP_TRY(hipEventRecord(p->done, s), "hipEventRecord");
-    p->last_stream = s;
-    p->launched = true;
-    return SFFT_OK;
+    return plan_execute(p, x_dev, out_idx, out_val, out_resid, stream, false);
 }
 
 sfft_status sfft_execute(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val, sfft_stream_t stream) {

@@ -27,5 +27,13 @@ const char* plan_tables(sfft_plan_t p);
 int plan_device(sfft_plan_t p);
 size_t plan_table_bytes(sfft_plan_t p);
 size_t plan_ws_bytes(sfft_plan_t p);
+// Asynchronous execution of a plan; scratch = true runs on the per-device scratch array
+// (sfft_execute_noalloc) instead of the plan's workspace.
+sfft_status plan_execute(sfft_plan_t p, const void* x_dev, int64_t* out_idx, void* out_val, double* out_resid,
+                         sfft_stream_t stream, bool scratch);
+// Per-device scratch array of sfft_execute_noalloc: its size, and its device address on
+// `device` (which must be current; looked up once per device, then cached).
+size_t scratch_bytes();
+hipError_t scratch_address(int device, char** out);
 
 }  // namespace sfft

@@ -1,0 +1,75 @@
+"""sfft_execute_noalloc (the entry point for callers that cannot allocate) through the
+C ABI: calls in a row on plans of decreasing size, each bitwise equal to
+sfft_execute_ex of the same plan and input; a plan whose workspace exceeds the
+scratch array is refused."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2012_08238_amd.signals import make_signal
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (N, K, B, L, w, extra plan arguments), largest first
+    (1 << 22, 100, 16384, 9, 131072, {}),                                  # the benchmark shape
+    (1 << 20, 50, 1024, 7, 8192, {}),                                      # C2
+    (1 << 18, 60, 512, 7, 4096, {"flags": 0x20}),                          # subtraction round
+    (1 << 16, 20, 256, 5, 2048, {"est_loops": 4, "est_B": 1024}),          # estimation-only loops
+    (1 << 14, 10, 128, 5, 512, {}),                                        # C1
+]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def test_noalloc_matches_execute(dev):
+    import torch
+    import paper_2012_08238_amd as S
+    lib = S.load()
+    plans, xs, refs = [], [], []
+    for i, (N, K, B, L, w, kw) in enumerate(CASES):
+        p = S.Plan(N, K, B, L, w, seed=i, n_resid=1000, **kw)
+        x = torch.from_numpy(make_signal(N, K, 20.0, seed=2000 + i).x.astype(np.complex64)).to(dev)
+        o = p.outputs(dev)
+        s = torch.cuda.current_stream().cuda_stream
+        assert lib.sfft_execute_ex(p.handle, _ptr(x), _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), C.c_void_p(s)) == 0
+        plans.append(p)
+        xs.append(x)
+        refs.append(o)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        outs = []
+        for p, x in zip(plans, xs):   # one call after another on the one stream, decreasing sizes
+            o = p.outputs(dev)
+            for t in o:
+                t.fill_(7)
+            s = torch.cuda.current_stream().cuda_stream
+            st = lib.sfft_execute_noalloc(p.handle, _ptr(x), _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), C.c_void_p(s))
+            assert st == 0, (st, lib.sfft_last_error())
+            outs.append(o)
+        torch.cuda.synchronize()
+        for j, (o, ref) in enumerate(zip(outs, refs)):
+            assert torch.equal(o[0], ref[0]), f"pass {rep} case {j}: indices"
+            assert torch.equal(o[1].view(torch.float32), ref[1].view(torch.float32)), f"pass {rep} case {j}: values"
+            assert torch.equal(o[2], ref[2]), f"pass {rep} case {j}: residual"
+            assert int((o[0] >= 0).sum()) == CASES[j][1]
+    for p in plans:
+        p.close()
+
+
+def test_noalloc_refuses_a_workspace_beyond_the_array(dev):
+    import torch
+    import paper_2012_08238_amd as S
+    from paper_2012_08238_amd import _capi
+    lib = S.load()
+    # (L - T + 1) d K N/B = 5 * 2000 * 2048 candidates: an 80 MB candidate list alone
+    p = S.Plan(1 << 22, 1000, 2048, 9, 16384, seed=1, n_resid=0)
+    assert p.desc["workspace_bytes"] > 64 << 20
+    x = torch.zeros(1 << 22, dtype=torch.complex64, device=dev)
+    o = p.outputs(dev)
+    st = lib.sfft_execute_noalloc(p.handle, _ptr(x), _ptr(o[0]), _ptr(o[1]), None, None)
+    assert st == _capi.SFFT_E_UNSUPPORTED
+    assert b"exceeds the scratch array" in lib.sfft_last_error()
+    p.close()
