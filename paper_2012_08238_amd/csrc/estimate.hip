@@ -420,14 +420,6 @@ __device__ __forceinline__ void stage_rou(double2* dst, const double2* src, uint
 }
 
 
-// Number of candidates of a signal: the vote's list, plus (round 1) the first
-// round's frequencies.
-__device__ __forceinline__ uint32_t candidate_count(const __attribute__((address_space(4))) SigDesc& d,
-                                                    uint32_t round, uint32_t& nc) {
-    nc = min(gld(d.ctr), d.cap);
-    return nc + (round ? min(gld(d.ctr + 2), d.K) : 0u);
-}
-
 // For each f in I': e_r = uhat_r[h_r(f)] * e^{-2 pi i (tau_r f mod N)/N} / Gtab[o_r(f)]
 // (the energy-concentration estimate of the one frequency assumed in the
 // bucket), x'_f = median_r Re e_r + i median_r Im e_r (or the mean over r); the
@@ -442,9 +434,6 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
-    uint32_t nc;
-    const uint32_t n = candidate_count(d, round, nc);
-    if (unit * kFinNT >= n) return;   // block-uniform: no candidate for this workgroup
     const uint32_t fftm = d.fft_mode;
     const uint32_t mean = d.combine;
     const uint32_t L = d.L, maskN = d.maskN, log2M = d.log2M, M = d.M, B = d.B, N = d.N;
@@ -454,16 +443,34 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
     const uint32_t Le = d.L_est, Lt = L + Le;
     const CDesc ed = Le ? (CDesc)d.eloops : (CDesc)a.descs + (a.nsig ? sig : 0u);
     const uint32_t Be = ed->B, Me = ed->M, log2Me = ed->log2M;
+    // the candidate count, the loop tables, the roots of unity and this thread's first
+    // candidate are loaded together: one round trip before the buckets' (the candidate
+    // is read at an index clamped into the list and used only if it exists)
+    const uint32_t c0 = gld(d.ctr), c2 = round ? gld(d.ctr + 2) : 0u;
+    uint32_t tsig = 0, ttau = 0, tsinv = 0;
     if (threadIdx.x < Lt) {
         const bool xe = threadIdx.x >= L;
         const uint32_t q = xe ? threadIdx.x - L : threadIdx.x;
-        s_sig[threadIdx.x] = gld((xe ? ed->sigma : d.sigma) + q);
-        s_tau[threadIdx.x] = gld((xe ? ed->tau : d.tau) + q);
-        s_sinv[threadIdx.x] = gld((xe ? ed->sigma_inv : d.sigma_inv) + q);
+        tsig = gld((xe ? ed->sigma : d.sigma) + q);
+        ttau = gld((xe ? ed->tau : d.tau) + q);
+        tsinv = gld((xe ? ed->sigma_inv : d.sigma_inv) + q);
     }
-    stage_rou<kFinNT>(s_rou, d.rou, d.tb);
-    __syncthreads();
+    static_assert(kRouMax <= kFinNT, "one root of unity per thread");
+    double2 trou = make_double2(0.0, 0.0);
+    if (threadIdx.x < (1u << d.tb)) trou = gld(d.rou + threadIdx.x);
     const uint32_t* cand = d.cand;
+    const uint32_t first = unit * kFinNT + threadIdx.x;
+    const uint32_t fpre = gld(cand + min(first, d.cap - 1u));
+    const uint32_t nc = min(c0, d.cap);
+    const uint32_t n = nc + (round ? min(c2, d.K) : 0u);
+    if (unit * kFinNT >= n) return;   // block-uniform: no candidate for this workgroup
+    if (threadIdx.x < Lt) {
+        s_sig[threadIdx.x] = tsig;
+        s_tau[threadIdx.x] = ttau;
+        s_sinv[threadIdx.x] = tsinv;
+    }
+    if (threadIdx.x < (1u << d.tb)) s_rou[threadIdx.x] = trou;
+    __syncthreads();
     const float2* invG = d.invG;
     const float2* uhat = d.uhat;
     const float2* tw = d.tw;
@@ -473,7 +480,7 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
     const uint32_t phase = d.phase;
     for (uint32_t i = unit * kFinNT + threadIdx.x; i < n; i += stride) {
         const bool rec = i >= nc;   // a first-round frequency (round 1)
-        const uint32_t f = rec ? gld(d.rec_f + (i - nc)) : gld(cand + i);
+        const uint32_t f = rec ? gld(d.rec_f + (i - nc)) : (i == first ? fpre : gld(cand + i));
         if (rec && phase) {
             // phase location keeps the recovered single-ton estimates
             const float2 v0 = gld(d.rec_v + (i - nc));
@@ -553,15 +560,22 @@ __global__ __launch_bounds__(kFinNT) void estimate_kernel(Launch a, uint32_t rou
 // The K smallest keys of the estimates (the K largest |x'_f|^2, ties -> lower f),
 // returned in ascending f and padded with (-1, 0). The K-th smallest key comes
 // from a radix select over 8-bit digits from the top, which stops as soon as
-// every key with the selected prefix is needed. One workgroup per signal.
-// Dynamic LDS: P values and P frequencies (P = 2^ceil(log2 K)).
+// every key with the selected prefix is needed; up to kFinKPT keys per thread are
+// held in registers across its passes. The selected entries are then ordered by f
+// with a counting sort: the range [min f, max f] is cut into kSelNT bins, each
+// entry goes to its bin's run, and its rank is the run's start plus the entries of
+// the run below it (frequencies are distinct). One workgroup per signal. Dynamic
+// LDS: P values and P frequencies (P = 2^ceil(log2 K)).
 // With the subtraction round, round 0 keeps its K largest in the workspace
 // (rec_f, rec_v, count in ctr[2]) instead of the outputs; round 1 writes the
 // outputs.
+constexpr int kFinKPT = 4;                 // keys per thread held in registers
+constexpr int kFinEPT = kMaxK / kSelNT;    // selected entries per thread (K <= kMaxK)
 __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t round) {
     extern __shared__ f4v lds_raw[];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t bc[4];
+    __shared__ uint32_t s_bin[kSelNT], s_fill[kSelNT], s_red[2 * (kSelNT / 64)], s_scan[kSelNT / 64];
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
@@ -570,11 +584,31 @@ __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t rou
     while (P < d.K) P <<= 1;
     float2* s_v = reinterpret_cast<float2*>(lds_raw);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_v + P);
-    uint32_t nc;
-    const uint32_t n = candidate_count(d, round, nc);
     const float2* est = d.est;
     const uint64_t* keys = d.keys;
     const uint32_t K = d.K;
+    // the candidate count and the first kFinKPT keys of each thread are loaded together
+    // (keys read at indices clamped into the array; those at or beyond the count unused)
+    const uint32_t c0 = gld(d.ctr), c2 = round ? gld(d.ctr + 2) : 0u;
+    const uint32_t nkeys = d.cap + (d.iterate ? K : 0u);
+    uint64_t kr[kFinKPT];
+#pragma unroll
+    for (int e = 0; e < kFinKPT; ++e) kr[e] = gld(keys + min(threadIdx.x + e * kSelNT, nkeys - 1u));
+    const uint32_t nc = min(c0, d.cap);
+    const uint32_t n = nc + (round ? min(c2, K) : 0u);
+    const bool inreg = n <= (uint32_t)kFinKPT * kSelNT;   // block-uniform
+    // fn(key, index) for every candidate key (registers or global memory)
+    auto for_keys = [&](auto&& fn) {
+        if (inreg) {
+#pragma unroll
+            for (int e = 0; e < kFinKPT; ++e) {
+                const uint32_t i = threadIdx.x + e * kSelNT;
+                if (i < n) fn(kr[e], i);
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < n; i += kSelNT) fn(gld(keys + i), i);
+        }
+    };
     uint64_t thr = ~0ull;
     if (n > K) {
         uint64_t prefix = 0, pmask = 0;
@@ -584,10 +618,9 @@ __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t rou
             const int shift = 56 - 8 * pass;
             for (int i = threadIdx.x; i < 256; i += kSelNT) hist[i] = 0;
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < n; i += kSelNT) {
-                const uint64_t key = gld(keys + i);
+            for_keys([&](uint64_t key, uint32_t) {
                 if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
-            }
+            });
             __syncthreads();
             if (threadIdx.x < 64) {
                 const int lo = 4 * (int)lane;   // lane 0 owns the smallest digits
@@ -635,8 +668,7 @@ __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t rou
     }
     if (threadIdx.x == 0) bc[2] = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kSelNT) {
-        const uint64_t key = gld(keys + i);
+    for_keys([&](uint64_t key, uint32_t i) {
         if (key <= thr) {
             const uint32_t pos = atomicAdd(&bc[2], 1u);
             if (pos < P) {
@@ -644,52 +676,103 @@ __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t rou
                 s_v[pos] = gld(est + i);
             }
         }
-    }
+    });
     __syncthreads();
     const uint32_t cnt = min(bc[2], K);
-    uint32_t Q = 1;   // sort size: power of two >= cnt (<= P)
-    while (Q < cnt) Q <<= 1;
-    for (uint32_t i = cnt + threadIdx.x; i < Q; i += kSelNT) {
-        s_f[i] = 0xFFFFFFFFu;
-        s_v[i] = make_float2(0.f, 0.f);
+    // this thread's entries (positions threadIdx.x + e kSelNT) and the range of f
+    uint32_t ef[kFinEPT];
+    float2 ev[kFinEPT];
+    uint32_t fmin = 0xFFFFFFFFu, fmax = 0u;
+#pragma unroll
+    for (int e = 0; e < kFinEPT; ++e) {
+        const uint32_t q = threadIdx.x + e * kSelNT;
+        ef[e] = 0u;
+        ev[e] = make_float2(0.f, 0.f);
+        if (q < cnt) {
+            ef[e] = s_f[q];
+            ev[e] = s_v[q];
+            fmin = min(fmin, ef[e]);
+            fmax = max(fmax, ef[e]);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        fmin = min(fmin, (uint32_t)__shfl_xor((int)fmin, off, 64));
+        fmax = max(fmax, (uint32_t)__shfl_xor((int)fmax, off, 64));
+    }
+    const uint32_t wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63u) == 0u) {
+        s_red[wid] = fmin;
+        s_red[kSelNT / 64 + wid] = fmax;
+    }
+    s_bin[threadIdx.x] = 0u;
+    s_fill[threadIdx.x] = 0u;
+    __syncthreads();
+    fmin = s_red[0];
+    fmax = s_red[kSelNT / 64];
+#pragma unroll
+    for (int w = 1; w < (int)(kSelNT / 64); ++w) {
+        fmin = min(fmin, s_red[w]);
+        fmax = max(fmax, s_red[kSelNT / 64 + w]);
+    }
+    // bin width: ceil((fmax - fmin + 1) / kSelNT) >= 1 (64-bit: the range can reach 2^32)
+    const uint32_t width =
+        cnt ? (uint32_t)(((uint64_t)fmax - fmin + (uint64_t)kSelNT) / (uint64_t)kSelNT) : 1u;
+    uint32_t eb[kFinEPT];
+#pragma unroll
+    for (int e = 0; e < kFinEPT; ++e) {
+        const uint32_t q = threadIdx.x + e * kSelNT;
+        eb[e] = 0u;
+        if (q < cnt) {
+            eb[e] = (ef[e] - fmin) / width;   // < kSelNT
+            atomicAdd(&s_bin[eb[e]], 1u);
+        }
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= Q; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < Q; i += kSelNT) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const bool up = (i & k) == 0;
-                    const uint32_t fi = s_f[i], fl = s_f[l];
-                    if ((fi > fl) == up) {
-                        s_f[i] = fl;
-                        s_f[l] = fi;
-                        const float2 t = s_v[i];
-                        s_v[i] = s_v[l];
-                        s_v[l] = t;
-                    }
-                }
+    uint32_t tot;
+    const uint32_t start = block_excl_scan<kSelNT>(s_bin[threadIdx.x], s_scan, tot);
+    __syncthreads();
+    s_bin[threadIdx.x] = start;   // run start of bin threadIdx.x
+    __syncthreads();
+    // every entry into its bin's run (any order within the run)
+    uint32_t ep[kFinEPT];
+#pragma unroll
+    for (int e = 0; e < kFinEPT; ++e) {
+        const uint32_t q = threadIdx.x + e * kSelNT;
+        ep[e] = 0u;
+        if (q < cnt) {
+            ep[e] = s_bin[eb[e]] + atomicAdd(&s_fill[eb[e]], 1u);
+            s_f[ep[e]] = ef[e];
+        }
+    }
+    __syncthreads();
+    const bool keep = d.iterate && round == 0;
+#pragma unroll
+    for (int e = 0; e < kFinEPT; ++e) {
+        const uint32_t q = threadIdx.x + e * kSelNT;
+        if (q < cnt) {
+            const uint32_t b = eb[e], r0 = s_bin[b], r1 = b + 1u < kSelNT ? s_bin[b + 1u] : cnt;
+            uint32_t rank = r0;
+            for (uint32_t t = r0; t < r1; ++t) rank += s_f[t] < ef[e] ? 1u : 0u;
+            if (keep) {
+                gst(d.rec_f + rank, ef[e]);
+                gst(d.rec_v + rank, ev[e]);
+            } else {
+                gst(io.out_idx + rank, (int64_t)ef[e]);
+                gst(io.out_val + rank, ev[e]);
             }
-            __syncthreads();
         }
     }
-    if (d.iterate && round == 0) {
-        for (uint32_t k = threadIdx.x; k < K; k += kSelNT) {
-            gst(d.rec_f + k, k < cnt ? s_f[k] : 0xFFFFFFFFu);
-            gst(d.rec_v + k, k < cnt ? s_v[k] : make_float2(0.f, 0.f));
-        }
-        if (threadIdx.x == 0) gst(d.ctr + 2, cnt);
-        return;
-    }
-    for (uint32_t k = threadIdx.x; k < K; k += kSelNT) {
-        if (k < cnt) {
-            gst(io.out_idx + k, (int64_t)s_f[k]);
-            gst(io.out_val + k, s_v[k]);
+    for (uint32_t k = cnt + threadIdx.x; k < K; k += kSelNT) {
+        if (keep) {
+            gst(d.rec_f + k, 0xFFFFFFFFu);
+            gst(d.rec_v + k, make_float2(0.f, 0.f));
         } else {
             gst(io.out_idx + k, (int64_t)-1);
             gst(io.out_val + k, make_float2(0.f, 0.f));
         }
     }
+    if (keep && threadIdx.x == 0) gst(d.ctr + 2, cnt);
 }
 
 // ---------------------------------------------------------------- subtraction round

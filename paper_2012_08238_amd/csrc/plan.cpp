@@ -303,7 +303,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     R.fin_lds = P * 8u + P * 4u;         // selected values, frequencies (sort size P)
     R.iterate = (p.flags & SFFT_FLAG_ITERATE) ? 1u : 0u;
     // estimation workgroups stride over the candidates, so their number only sets the
-    // parallelism: about four candidates per thread for the expected count, at most 32.
+    // parallelism: about one candidate per thread for the expected count, at most 32.
     // Voting: K plus the false frequencies, N P(Binom(L, dK/B) >= T) (each loop selects a
     // bucket of a random frequency with probability dK/B); phase location: the capacity.
     double expect = (double)R.cap;
@@ -317,7 +317,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         expect = std::min((double)R.cap, (double)R.K + (double)R.N * tail);
     }
     expect += (double)(R.K * R.iterate);
-    R.est_units = (uint32_t)std::max(1.0, std::min(32.0, std::ceil(expect / (4.0 * kFinNT))));
+    R.est_units = (uint32_t)std::max(1.0, std::min(32.0, std::ceil(expect / (double)kFinNT)));
     // subtraction round: phased values [K], sort keys [P], offsets [K], run starts [B] (16 bit)
     R.sub_lds = R.iterate ? ((R.K * 8u + P * 4u + R.K * 4u + R.B * 2u + 15u) & ~15u) : 0u;
     if (R.iterate) {
