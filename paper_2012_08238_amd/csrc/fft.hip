@@ -288,8 +288,122 @@ __device__ __forceinline__ void select_top(const float2* data, uint32_t dK, uint
 #pragma unroll
     for (int c = 0; c < CH; ++c) kv[c] = valid;
     bool done = false;
+    if constexpr (CH >= 4 && NT == 1024 && 2 * Cfg::PADN >= Cfg::NW + 64 + 4096 + 2 * (1024 + 32)) {
+        if (dK <= (uint32_t)NT) {   // block-uniform
+            // The candidates are the keys of the histogram bins (the top 12 bits of the
+            // energy: exponent and three mantissa bits) from the top down to the bin that
+            // holds the dK-th largest; when they are at most 1024, each one's rank among
+            // them (larger energy first, then lower bucket) is counted directly and the
+            // dK of rank below dK are selected. Otherwise the general path below.
+            constexpr int NBIN = 4096;
+            uint32_t* hb = bits + Cfg::NW + 64;   // histogram [NBIN]
+            // candidates [1024 + padding]: (energy key << log2 B) | (B - 1 - bucket), so that
+            // a larger value is a larger energy, or an equal one in a lower bucket
+            uint64_t* ccomp = reinterpret_cast<uint64_t*>(hb + NBIN);
+            __syncthreads();   // every thread has read its values from the data region reused below
+#pragma unroll
+            for (int q = 0; q < NBIN / NT; ++q) hb[threadIdx.x + q * NT] = 0u;
+            if (threadIdx.x == 0) bcast[2] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < CH; ++c) atomicAdd(&hb[key[c] >> 20], 1u);
+            __syncthreads();
+            // thread t owns bins NBIN-1-4t .. NBIN-4-4t (largest first)
+            uint32_t hc[NBIN / NT], hs = 0;
+#pragma unroll
+            for (int q = 0; q < NBIN / NT; ++q) {
+                hc[q] = hb[NBIN - 1 - (int)threadIdx.x * (NBIN / NT) - q];
+                hs += hc[q];
+            }
+            uint32_t tot;
+            uint32_t above = block_excl_scan<NT>(hs, scan, tot);   // keys in the bins above this thread's
+            if (above < dK && dK <= above + hs) {
+#pragma unroll
+                for (int q = 0; q < NBIN / NT; ++q) {
+                    if (above < dK && dK <= above + hc[q]) {
+                        bcast[0] = (uint32_t)(NBIN - 1 - (int)threadIdx.x * (NBIN / NT) - q) << 20;   // lower edge
+                        bcast[1] = above + hc[q];                                                   // candidates
+                    }
+                    above += hc[q];
+                }
+            }
+            __syncthreads();
+            const uint32_t t0 = bcast[0], ncand = bcast[1];
+            if (ncand <= 1024u) {   // block-uniform
+                // collect the candidates (any order: the ranks below do not depend on it)
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) cnt += key[c] >= t0 ? 1u : 0u;
+                const uint32_t incl = wave_incl_scan(cnt);
+                uint32_t wbase = 0;
+                if ((threadIdx.x & 63u) == 63u && incl) wbase = atomicAdd(&bcast[2], incl);
+                uint32_t pos = __shfl(wbase, 63, 64) + incl - cnt;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (key[c] >= t0) {
+                        const uint32_t h = threadIdx.x * CH + c;
+                        ccomp[pos] = ((uint64_t)key[c] << LOG2B) | (uint64_t)(B - 1 - h);
+                        ++pos;
+                    }
+                }
+                // PS threads (consecutive lanes) share a candidate when there are few; each reads
+                // every PS-th group of 8 candidates, the list padded with zeros (never larger)
+                const int PS = ncand <= 256u ? 4 : (ncand <= 512u ? 2 : 1);   // block-uniform
+                const uint32_t npad = (ncand + 8u * PS - 1u) / (8u * PS) * (8u * PS);
+                if (threadIdx.x < npad - ncand) ccomp[ncand + threadIdx.x] = 0ull;
+                for (int i = threadIdx.x; i < NW; i += NT) bits[i] = 0u;
+                __syncthreads();
+                // rank of candidate j: the candidates with a larger value
+                const uint32_t j = threadIdx.x / PS, part = threadIdx.x % PS;
+                uint32_t rank = 0;
+                uint64_t cj = 0;
+                if (j < ncand) {
+                    cj = ccomp[j];
+                    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+                    const u64x2* c2 = reinterpret_cast<const u64x2*>(ccomp);
+                    for (uint32_t g = part; g < npad / 8u; g += PS) {
+                        u64x2 v[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = c2[g * 4u + e];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) rank += (v[e].x > cj ? 1u : 0u) + (v[e].y > cj ? 1u : 0u);
+                    }
+                }
+                if (PS >= 2) rank += __shfl_xor(rank, 1, 64);
+                if (PS >= 4) rank += __shfl_xor(rank, 2, 64);
+                if (j < ncand && part == 0 && rank < dK) {
+                    const uint32_t hj = (uint32_t)(B - 1) - (uint32_t)(cj & (uint64_t)(B - 1));
+                    atomicOr(&bits[hj >> 5], 1u << (hj & 31));
+                }
+                __syncthreads();
+                // the bitmap, and the list in ascending bucket order
+                constexpr int WPT = NW >= NT ? NW / NT : 1;
+                uint32_t wv[WPT], c2 = 0;
+#pragma unroll
+                for (int q = 0; q < WPT; ++q) {
+                    const uint32_t wi = threadIdx.x * WPT + q;
+                    wv[q] = wi < (uint32_t)NW ? bits[wi] : 0u;
+                    c2 += (uint32_t)__popc(wv[q]);
+                    if (wi < (uint32_t)NW) gst(jb + wi, wv[q]);
+                }
+                uint32_t t2;
+                uint32_t p2 = block_excl_scan<NT>(c2, scan, t2);
+#pragma unroll
+                for (int q = 0; q < WPT; ++q) {
+                    uint32_t w = wv[q];
+                    while (w) {
+                        const uint32_t b = (uint32_t)__ffs((int)w) - 1u;
+                        w &= w - 1u;
+                        if (p2 < nl) gst(jl + p2, (threadIdx.x * WPT + q) * 32u + b);
+                        ++p2;
+                    }
+                }
+                done = true;
+            }
+        }
+    }
     if constexpr (CH >= 4 && Cfg::SELCAP >= NT) {
-        if (dK <= (uint32_t)NT) {
+        if (!done && dK <= (uint32_t)NT) {
             // Every one of the dK largest energies is >= theta0, the dK-th largest of
             // the per-thread maxima (at least dK threads hold a value >= theta0), so
             // only the keys >= theta0 can be selected. Collect them (in bucket
