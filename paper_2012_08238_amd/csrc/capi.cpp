@@ -47,7 +47,6 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.sigma = reinterpret_cast<const uint32_t*>(tab + t.sigma);
     d.sigma_inv = reinterpret_cast<const uint32_t*>(tab + t.sigma_inv);
     d.tau = reinterpret_cast<const uint32_t*>(tab + t.tau);
-    d.gT = reinterpret_cast<const float*>(tab + t.gT);
     d.invG = reinterpret_cast<const float2*>(tab + t.invG);
     d.tw = reinterpret_cast<const float2*>(tab + t.tw);
     d.tpos = reinterpret_cast<const uint32_t*>(tab + t.tpos);
@@ -90,6 +89,8 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.w = R.w;
     d.Mw = R.Mw;
     d.Mw4 = R.Mw4;
+    // s = w / (2 gauss_c): t^2 / 2s^2 = (t kappa)^2 ln 2 with kappa = 2 gauss_c / (w sqrt(2 ln 2))
+    d.wkappa = (float)(2.0 * R.gauss_c / ((double)R.w * 1.1774100225154747));
     d.K = R.K;
     d.dK = R.dK;
     d.T = R.T;

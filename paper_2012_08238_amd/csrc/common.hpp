@@ -22,7 +22,6 @@ struct SigDesc {
     const uint32_t* sigma;      // [L] odd scalings
     const uint32_t* sigma_inv;  // [L] inverses mod N
     const uint32_t* tau;        // [L] shifts
-    const float* gT;            // [B][Mw4] window, gT[b*Mw4+m] = g[b + m*B] (0 beyond w)
     const float2* invG;         // [M] 1/Gtab[o], o = -M/2 .. M/2-1
     const float2* tw;           // [B] e^{-2 pi i m/B}
     const uint32_t* tpos;       // [S] residual sample positions
@@ -52,6 +51,7 @@ struct SigDesc {
     uint32_t B, log2B;
     uint32_t M, log2M;          // M = N/B (bucket width in bins = rows of the strip view)
     uint32_t L, w, Mw, Mw4;     // Mw = ceil(w/B) window taps per bucket, Mw4 = Mw rounded up to 4
+    float wkappa;               // Gaussian factor of the window: e^{-t^2/2s^2} = 2^{-(t wkappa)^2}
     uint32_t K, dK, T, S, cap;
     uint32_t tb;                // root-of-unity table bits, min(8, log2N)
     double step;                // 2 pi / N

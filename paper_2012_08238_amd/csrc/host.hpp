@@ -51,7 +51,6 @@ struct HostTables {
     std::vector<std::complex<double>> gain;     // Gtab[o], o = -M/2 .. M/2-1
     std::vector<std::complex<double>> gain_wide;  // [(sub_rl+sub_rh+1) M] gain at o = -(sub_rh M + M/2) ..
                                                   // (sub_rl M + M/2) - 1 (iteration only)
-    std::vector<float> gT;                      // [B][Mw4]
     std::vector<float> invG;                    // [M] (re, im) pairs of 1/Gtab
     std::vector<float> tw;                      // [B] (re, im) pairs of e^{-2 pi i m/B}
     std::vector<double> rt_hi, rt_lo;           // (re, im) pairs of e^{+2 pi i m/N}, two bit fields
@@ -104,7 +103,7 @@ WsLayout workspace_layout(const Resolved& R);
 
 // Device table layout (byte offsets into one allocation).
 struct TabLayout {
-    size_t sigma, sigma_inv, tau, tpos, gT, invG, tw, rou, ctau, ctw, gw, total;
+    size_t sigma, sigma_inv, tau, tpos, invG, tw, rou, ctau, ctw, gw, total;
 };
 TabLayout table_layout(const Resolved& R);
 

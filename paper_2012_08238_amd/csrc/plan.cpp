@@ -411,13 +411,7 @@ void build_tables(const Resolved& R, HostTables* t) {
             t->gw[2 * k + 1] = (float)t->gain_wide[k].imag();
         }
     }
-    // device tables
-    t->gT.assign((size_t)B * R.Mw4, 0.0f);
-    for (uint32_t b = 0; b < B; ++b)
-        for (uint32_t m = 0; m < R.Mw; ++m) {
-            const uint64_t i = (uint64_t)b + (uint64_t)m * B;
-            if (i < w) t->gT[(size_t)b * R.Mw4 + m] = (float)t->window[i];
-        }
+    // device tables (the window taps themselves are computed by the bucketization kernels)
     t->invG.resize(2 * (size_t)M);
     for (uint32_t k = 0; k < M; ++k) {
         const std::complex<double> inv = 1.0 / t->gain[k];
@@ -478,7 +472,6 @@ TabLayout table_layout(const Resolved& R) {
     l.sigma_inv = take((size_t)R.L * 4);
     l.tau = take((size_t)R.L * 4);
     l.tpos = take((size_t)R.S * 4);
-    l.gT = take((size_t)R.B * R.Mw4 * 4);
     l.invG = take((size_t)R.M * 8);
     l.tw = take((size_t)R.B * 8);
     l.rou = take((size_t)16 << R.tb);
@@ -500,7 +493,6 @@ std::vector<char> pack_tables(const Resolved& R, const HostTables& T) {
     memcpy(&h[tl.sigma_inv], R.sigma_inv.data(), (size_t)R.L * 4);
     memcpy(&h[tl.tau], R.tau.data(), (size_t)R.L * 4);
     if (R.S) memcpy(&h[tl.tpos], R.tpos.data(), (size_t)R.S * 4);
-    memcpy(&h[tl.gT], T.gT.data(), T.gT.size() * 4);
     memcpy(&h[tl.invG], T.invG.data(), T.invG.size() * 4);
     memcpy(&h[tl.tw], T.tw.data(), T.tw.size() * 4);
     memcpy(&h[tl.rou], T.rou.data(), T.rou.size() * 8);
