@@ -118,15 +118,15 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_kernel(Launch a) {
     }
 }
 
-// Strip form for the common shapes: each thread owns at most IPT (loop, column)
-// items of G4*4 window taps. All tile loads are issued first (branch-free:
+// Strip form for the common shapes: each of the NT threads owns at most IPT (loop,
+// column) items of G4*4 window taps. All tile loads are issued first (branch-free:
 // out-of-tile slots reload the last element); while they are in flight the
-// thread computes its items' buckets and fetches their window taps. The tile
+// thread computes its items' buckets and window taps. The tile
 // then passes through LDS in H row bands (LDS = tile/H, so more workgroups fit
 // per CU); each band delivers the taps whose rows it holds, and the taps are
 // summed in tap order at the end: same taps, same order as the other forms.
-template <int PER, int IPT, int G4, int H>
-__global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
+template <int PER, int IPT, int G4, int H, int NT = (int)kFoldNT, bool FULL = false>
+__global__ __launch_bounds__(NT) void fold_strip_pf_kernel(Launch a) {
     fold_priority();
     extern __shared__ f4v lds4[];
     uint32_t sig, unit;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
     f4v v[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const uint32_t k = min(threadIdx.x + j * kFoldNT, total - 1u);
+        const uint32_t k = min(threadIdx.x + j * NT, total - 1u);
         const uint32_t row = k >> log2h, c = k & ((1u << log2h) - 1u);
         v[j] = gld_nt(xs + ((((size_t)row << log2B) + col0) >> 1) + c);
     }
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
     f4v gi[IPT][G4];
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const uint32_t it = threadIdx.x + e * kFoldNT;
+        const uint32_t it = threadIdx.x + e * NT;
         ri[e] = it >> log2C;
         ci[e] = it & (C - 1u);
         si_[e] = sv[e] = tv[e] = 0u;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
     }
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const uint32_t it = threadIdx.x + e * kFoldNT;
+        const uint32_t it = threadIdx.x + e * NT;
         if (it < items) {
             const uint32_t b = (sv[e] * (col0 + ci[e] - tv[e])) & (B - 1u);
             bi[e] = b;
@@ -196,15 +196,23 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         if (h > 0) __syncthreads();   // the previous band has been read
+        if constexpr (FULL) {
+            // the tile is exactly PER loads per thread: band h is loads h PER/H .. (h+1) PER/H - 1,
+            // known at compile time, so each load's registers are free once its band is stored
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const uint32_t k = threadIdx.x + j * kFoldNT;
-            if (k < total && (k >> log2band) == (uint32_t)h) lds4[k - ((uint32_t)h << log2band)] = v[j];
+            for (int j = h * (PER / H); j < (h + 1) * (PER / H); ++j)
+                lds4[threadIdx.x + (uint32_t)j * NT - ((uint32_t)h << log2band)] = v[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const uint32_t k = threadIdx.x + j * NT;
+                if (k < total && (k >> log2band) == (uint32_t)h) lds4[k - ((uint32_t)h << log2band)] = v[j];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < IPT; ++e) {
-            const uint32_t it = threadIdx.x + e * kFoldNT;
+            const uint32_t it = threadIdx.x + e * NT;
             if (it < items) {
 #pragma unroll
                 for (int m = 0; m < TAPS; ++m) {
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_pf_kernel(Launch a) {
     }
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const uint32_t it = threadIdx.x + e * kFoldNT;
+        const uint32_t it = threadIdx.x + e * NT;
         if (it < items) {
             const uint32_t b = bi[e];
             float2 acc = make_float2(0.f, 0.f);
@@ -286,11 +294,20 @@ static hipError_t set_strip_attr() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
 }
 
+template <int IPT, int G4>
+static hipError_t set_pf512_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&fold_strip_pf_kernel<16, IPT, G4, 2, 512, true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+}
+
 hipError_t set_fold_attributes() {
     hipError_t e;
     if ((e = set_strip_attr<16>()) != hipSuccess) return e;
     if ((e = set_strip_attr<32>()) != hipSuccess) return e;
-    return hipSuccess;
+    if ((e = set_pf512_attr<1, 1>()) != hipSuccess) return e;
+    if ((e = set_pf512_attr<1, 2>()) != hipSuccess) return e;
+    if ((e = set_pf512_attr<2, 1>()) != hipSuccess) return e;
+    return set_pf512_attr<2, 2>();
 }
 
 uint32_t strip_per_thread(uint32_t lds_bytes) {
@@ -306,10 +323,17 @@ uint32_t fold_variant(uint32_t mode, uint32_t strip_lds, uint32_t items, uint32_
     uint32_t lp = 0;
     while ((1u << lp) < per) ++lp;
     const uint32_t ipt = (items + kFoldNT - 1) / kFoldNT;
-    if (per >= 4 && ipt >= 1 && ipt <= 2 && g4 >= 1 && g4 <= 2) return (1u << 16) | (lp << 8) | (ipt << 4) | g4;
+    // a tile of exactly `per` loads per thread lets the kernel store each band from loads
+    // known at compile time (their registers free once stored: 140 -> 96 VGPRs at 16 loads)
+    const uint32_t full = strip_lds == per * kFoldNT * 16u ? kFoldVariantFull : 0u;
+    if (per >= 4 && ipt >= 1 && ipt <= 2 && g4 >= 1 && g4 <= 2) return (1u << 16) | full | (lp << 8) | (ipt << 4) | g4;
     // up to four items per thread with a 32 KB tile (measured faster for N/B = 64; with a
     // 64 KB tile the plain strip kernel is as fast)
-    if (per == 8 && ipt <= 4 && g4 >= 1 && g4 <= 2) return (1u << 16) | (lp << 8) | (4u << 4) | g4;
+    if (per == 8 && ipt <= 4 && g4 >= 1 && g4 <= 2) return (1u << 16) | full | (lp << 8) | (4u << 4) | g4;
+    // a full 128 KB tile (e.g. 64 columns of 256 rows): 512 threads of 16 loads, two 64 KB
+    // bands, at most two items per thread
+    if (per == 32 && strip_lds == 32u * kFoldNT * 16u && items <= 1024u && g4 >= 1 && g4 <= 2)
+        return (1u << 16) | kFoldVariant512 | (4u << 8) | (((items + 511u) / 512u) << 4) | g4;
     return (1u << 16) | (lp << 8);
 }
 
@@ -318,17 +342,41 @@ constexpr uint32_t strip_bands(uint32_t per) { return per >= 16 ? per / 8 : 1; }
 
 #define SFFT_PF(PER, IPT, G4)                                                                              \
     case (PER << 8) | (IPT << 4) | G4:                                                                     \
-        hipLaunchKernelGGL((fold_strip_pf_kernel<PER, IPT, G4, strip_bands(PER)>), dim3(units), dim3(kFoldNT), \
-                           lds_bytes / strip_bands(PER), s, a);                                            \
+        if (full)                                                                                          \
+            hipLaunchKernelGGL((fold_strip_pf_kernel<PER, IPT, G4, strip_bands(PER), (int)kFoldNT, true>), \
+                               dim3(units), dim3(kFoldNT), lds_bytes / strip_bands(PER), s, a);            \
+        else                                                                                               \
+            hipLaunchKernelGGL((fold_strip_pf_kernel<PER, IPT, G4, strip_bands(PER)>), dim3(units),        \
+                               dim3(kFoldNT), lds_bytes / strip_bands(PER), s, a);                         \
         break;
 
 hipError_t launch_fold(const Launch& a, uint32_t variant, uint32_t units, uint32_t lds_bytes, hipStream_t s) {
+    if (variant & kFoldVariant512) {
+        // full 128 KB tile, 512 threads, two bands
+        switch (variant & 0xFFu) {
+            case 0x11:
+                hipLaunchKernelGGL((fold_strip_pf_kernel<16, 1, 1, 2, 512, true>), dim3(units), dim3(512), lds_bytes / 2, s, a);
+                break;
+            case 0x12:
+                hipLaunchKernelGGL((fold_strip_pf_kernel<16, 1, 2, 2, 512, true>), dim3(units), dim3(512), lds_bytes / 2, s, a);
+                break;
+            case 0x21:
+                hipLaunchKernelGGL((fold_strip_pf_kernel<16, 2, 1, 2, 512, true>), dim3(units), dim3(512), lds_bytes / 2, s, a);
+                break;
+            case 0x22:
+                hipLaunchKernelGGL((fold_strip_pf_kernel<16, 2, 2, 2, 512, true>), dim3(units), dim3(512), lds_bytes / 2, s, a);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (variant == 0) {
         hipLaunchKernelGGL(fold_gather_kernel, dim3(units), dim3(kFoldNT), 0, s, a);
         return hipGetLastError();
     }
-    const uint32_t per = 1u << ((variant >> 8) & 255u);
+    const uint32_t per = 1u << ((variant >> 8) & 15u);
     const uint32_t ipt = (variant >> 4) & 15u, g4 = variant & 15u;
+    const bool full = (variant & kFoldVariantFull) != 0;
     if (ipt == 0) {
         switch (per) {
             case 1: hipLaunchKernelGGL(fold_strip_kernel<1>, dim3(units), dim3(kFoldNT), lds_bytes, s, a); break;

@@ -9,6 +9,8 @@ namespace sfft {
 // with its tile size, items per thread and window-tap vectors encoded
 // (fold_variant). Every signal of one launch must share the variant.
 uint32_t fold_variant(uint32_t mode, uint32_t strip_lds, uint32_t items, uint32_t g4);
+constexpr uint32_t kFoldVariant512 = 1u << 20;   // variant bit: the 512-thread full-tile instance
+constexpr uint32_t kFoldVariantFull = 1u << 21;  // variant bit: the tile is exactly the threads' loads
 // lds_bytes = strip tile bytes (strip variants)
 hipError_t launch_fold(const Launch& a, uint32_t variant, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // one workgroup per (signal, loop); every signal of the launch has B = 2^log2B <= 16384
