@@ -53,6 +53,58 @@ __device__ __forceinline__ void append_wave(const uint32_t (&fv)[P], uint32_t em
 // L <= 16 (every test unconditional); VL = 32 covers 17..32 with the surplus tests
 // masked. STAGED: the L selected-bucket bitmaps are copied to LDS first.
 
+// Bit planes a count of at most n needs (at least one).
+__host__ __device__ constexpr int vote_planes(int n) {
+    int b = 1;
+    while ((1 << b) <= n) ++b;
+    return b;
+}
+
+// Vote counts of a thread's candidates, bit-sliced: bit qq of plane b is bit b of candidate
+// qq's count, so one add of a loop's vote mask (bit qq: the loop voted for candidate qq)
+// counts it for every candidate at once.
+template <int NP>
+struct VoteCount {
+    uint32_t c[NP];
+    __device__ __forceinline__ VoteCount() {
+#pragma unroll
+        for (int b = 0; b < NP; ++b) c[b] = 0u;
+    }
+    // x: the mask of the (k+1)-th loop added; a count of at most k+1 has no plane above
+    // bit log2(k+1), so the carry stops there
+    __device__ __forceinline__ void add(uint32_t x, int k) {
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            if (((k + 1) >> b) == 0) break;
+            const uint32_t t = c[b] & x;
+            c[b] ^= x;
+            x = t;
+        }
+    }
+    // bit qq: candidate qq's count is at least t
+    __device__ __forceinline__ uint32_t ge(uint32_t t) const {
+        if (t >= (1u << NP)) return 0u;
+        uint32_t gt = 0u, eq = 0xffffffffu;
+#pragma unroll
+        for (int b = NP - 1; b >= 0; --b) {
+            if ((t >> b) & 1u) {
+                eq &= c[b];
+            } else {
+                gt |= eq & c[b];
+                eq &= ~c[b];
+            }
+        }
+        return gt | eq;
+    }
+    // candidate qq's count
+    __device__ __forceinline__ uint32_t of(uint32_t qq) const {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) v |= ((c[b] >> qq) & 1u) << b;
+        return v;
+    }
+};
+
 // One chunk of kVoteUnit candidates (unit `unit` of signal `sig`). sdyn: the chunk's
 // selected-bucket slots (vote_slot_words(log2 N/B) words), then (staged) the L
 // selected-bucket bitmaps, which (like the comb residues) are copied only when `restage`
@@ -121,17 +173,18 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
         }
     }
     __syncthreads();
-    // bit j of the result: slot j's loop selected the bucket of hash argument qv, i.e. bits
+    // whether slot r's loop selected the bucket of hash argument qv, i.e. bits
     // [log2M, log2M + log2B) of qv: its bitmap word (bits above log2M + 5) and the bit in it
     const uint32_t wb_off = log2M + 5u, wb_w = (log2B > 5u ? log2B : 5u) - 5u, hb_w = log2B < 5u ? log2B : 5u;
-    auto test = [&](int r, uint32_t qv) -> uint32_t {
+    auto test1 = [&](int r, uint32_t qv) -> uint32_t {
         const uint32_t word = __builtin_amdgcn_ubfe(qv, wb_off, wb_w);
         const uint32_t hb = __builtin_amdgcn_ubfe(qv, log2M, hb_w);
         uint32_t wd;
         if constexpr (STAGED) wd = sbits[boff[r] + word];
         else wd = gld(jbits + boff[r] + word);
-        return (kExact || (uint32_t)r < L ? __builtin_amdgcn_ubfe(wd, hb, 1u) : 0u) << r;
+        return kExact || (uint32_t)r < L ? __builtin_amdgcn_ubfe(wd, hb, 1u) : 0u;
     };
+    auto test = [&](int r, uint32_t qv) -> uint32_t { return test1(r, qv) << r; };
     uint32_t* ctr = d.ctr;
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
@@ -145,64 +198,85 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
     uint32_t emask = 0;   // bit qq: candidate qq of this thread passes
     if (log2M >= kLog2PT) {
         // candidates ci0 .. ci0 + kVotePerThread - 1: consecutive positions of one bucket
-        // (the chunk bounds are multiples of kVotePerThread here)
+        // (the chunk bounds are multiples of kVotePerThread here). Each tested slot r keeps
+        // a mask m[r] (bit qq: its loop voted for candidate qq); the votes of the thread's
+        // candidates are then counted bit-sliced over those masks.
         const uint32_t ci0 = start + (threadIdx.x << kLog2PT);
+        uint32_t p0 = 0;
         if (ci0 < end) {
             const uint32_t h = s_slot[(ci0 >> log2M) - slot0];
-            const uint32_t p0 = (h << log2M) - half + (ci0 & (M - 1u));   // mod 2^32: N divides it
-            uint32_t f = sinv0 * p0;
-            if (kExact && VL >= 4 && d.vote_split) {
-                // Few selected buckets (dK/B small) and T = L/2 + 1: the first P1 = L - T + 2
-                // loops (r0 and every loop before it among them) are tested for all
-                // candidates; one with fewer than 2 votes there cannot reach T (the other
-                // L - P1 = T - 2 loops add at most T - 2), so only the rest test those loops.
-                constexpr int P1 = VL - VL / 2 + 1;   // slots 0 .. P1-1: loops 0 .. P1-1
-                uint32_t q[P1];
+            p0 = (h << log2M) - half + (ci0 & (M - 1u));   // mod 2^32: N divides it
+            constexpr uint32_t kAll = (1u << kVotePerThread) - 1u;   // the thread's candidates
+            uint32_t m[VL], q[VL];
 #pragma unroll
-                for (int r = 1; r < P1; ++r) q[r] = cr[r] * p0 + half;
-                uint32_t smask = 0;   // bit qq: candidate qq needs the other loops
-                uint64_t cnt1 = 0;    // 4 bits per candidate: its votes among the first P1 loops
+            for (int r = 1; r < VL; ++r) {
+                m[r] = 0u;
+                q[r] = cr[r] * p0 + half;
+            }
+            bool split = false;
+            if constexpr (kExact && VL >= 4) {
+                split = d.vote_split != 0u;
+                if (split) {
+                    constexpr int P1 = VL - VL / 2 + 1;   // slots 0 .. P1-1: loops 0 .. P1-1
+                    // Few selected buckets (dK/B small) and T = L/2 + 1: the first P1 = L - T + 2
+                    // loops (r0 and every loop before it among them) are tested for all
+                    // candidates; one with fewer than 2 votes there cannot reach T (the other
+                    // L - P1 = T - 2 loops add at most T - 2), so only the rest test those loops.
 #pragma unroll
-                for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-                    uint32_t votes = 1u;
+                    for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+#pragma unroll
+                        for (int r = 1; r < P1; ++r) {
+                            m[r] |= test1(r, q[r]) << qq;
+                            q[r] += cr[r];
+                        }
+                    }
+                    VoteCount<vote_planes(P1 - 1)> c1;
+                    uint32_t any = 0u, excl = 0u;
 #pragma unroll
                     for (int r = 1; r < P1; ++r) {
-                        votes |= test(r, q[r]);
-                        q[r] += cr[r];
+                        c1.add(m[r], r - 1);
+                        any |= m[r];
+                        if ((uint32_t)r <= r0) excl |= m[r];   // counted from a loop before r0
                     }
-                    fv[qq] = f & maskN;
-                    f += sinv0;
-                    const uint32_t c1 = (uint32_t)__popc(votes);
-                    const bool first = (votes & before_r0) == 0u;
-                    emask |= (first && c1 >= T ? 1u : 0u) << qq;
-                    smask |= (first && c1 >= 2u && c1 < T ? 1u : 0u) << qq;
-                    cnt1 |= (uint64_t)c1 << (4u * qq);
-                }
-                while (smask) {
-                    const uint32_t qq = (uint32_t)__builtin_ctz(smask);
-                    smask &= smask - 1u;
-                    const uint32_t p = p0 + qq;
-                    uint32_t v2 = 0;
+                    emask = c1.ge(T - 1u) & ~excl & kAll;
+                    uint32_t smask = any & ~excl & ~emask;   // 2 .. T-1 votes so far
+                    while (smask) {
+                        const uint32_t qq = (uint32_t)__builtin_ctz(smask);
+                        smask &= smask - 1u;
+                        const uint32_t p = p0 + qq;
+                        uint32_t v2 = c1.of(qq);
 #pragma unroll
-                    for (int r = P1; r < VL; ++r) v2 |= test(r, cr[r] * p + half);
-                    if (((uint32_t)(cnt1 >> (4u * qq)) & 15u) + (uint32_t)__popc(v2) >= T) emask |= 1u << qq;
+                        for (int r = P1; r < VL; ++r) v2 += test1(r, cr[r] * p + half);
+                        if (v2 >= T - 1u) emask |= 1u << qq;
+                    }
                 }
-            } else {
-                uint32_t q[VL];
-#pragma unroll
-                for (int r = 1; r < VL; ++r) q[r] = cr[r] * p0 + half;
+            }
+            if (!split) {
 #pragma unroll
                 for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
-                    uint32_t votes = 1u;
 #pragma unroll
                     for (int r = 1; r < VL; ++r) {
-                        votes |= test(r, q[r]);
+                        m[r] |= test1(r, q[r]) << qq;
                         q[r] += cr[r];
                     }
-                    fv[qq] = f & maskN;
-                    emask |= voted(votes) << qq;
-                    f += sinv0;
                 }
+                VoteCount<vote_planes(VL - 1)> c;
+                uint32_t excl = 0u;
+#pragma unroll
+                for (int r = 1; r < VL; ++r) {
+                    c.add(m[r], r - 1);
+                    if ((uint32_t)r <= r0) excl |= m[r];
+                }
+                emask = c.ge(T - 1u) & ~excl & kAll;   // T = 1: every candidate
+            }
+        }
+        // the frequencies, f = sigma_r0^{-1} p, only where some lane of the wave passes
+        if (__ballot(emask != 0u) != 0ull) {
+            uint32_t f = sinv0 * p0;
+#pragma unroll
+            for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+                fv[qq] = f & maskN;
+                f += sinv0;
             }
         } else {
 #pragma unroll
