@@ -168,6 +168,14 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const uint32_t i = i0 + e * kVoteNT;
+                if (log2B < 5u) {   // one word per loop: its B bits repeated (see test_hi)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        uint32_t v = t[e][c] & ((1u << d.B) - 1u);
+                        for (uint32_t sb = d.B; sb < 32u; sb <<= 1) v |= v << sb;
+                        t[e][c] = v;
+                    }
+                }
                 if (i < nw4) dst[i] = t[e];
             }
         }
@@ -185,6 +193,21 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
         return kExact || (uint32_t)r < L ? __builtin_amdgcn_ubfe(wd, hb, 1u) : 0u;
     };
     auto test = [&](int r, uint32_t qv) -> uint32_t { return test1(r, qv) << r; };
+    // The same test from hi = bits [log2M, log2M + 32) of the hash argument (bucket at bit 0):
+    // the bit-field extract takes the bit index from hi's low 5 bits. Below 32 buckets those
+    // bits hold log2B bits of the bucket and higher bits of the argument, so the LDS copy
+    // repeats each loop's B bits across its word; read from global memory the index is masked.
+    auto test_hi = [&](int r, uint32_t hi) -> uint32_t {
+        const uint32_t word = __builtin_amdgcn_ubfe(hi, 5u, wb_w);
+        uint32_t wd, hb = hi;
+        if constexpr (STAGED) {
+            wd = sbits[boff[r] + word];
+        } else {
+            wd = gld(jbits + boff[r] + word);
+            hb = __builtin_amdgcn_ubfe(hi, 0u, hb_w);
+        }
+        return kExact || (uint32_t)r < L ? __builtin_amdgcn_ubfe(wd, hb, 1u) : 0u;
+    };
     uint32_t* ctr = d.ctr;
     uint32_t* cand = d.cand;
     const uint32_t cap = d.cap;
@@ -207,11 +230,16 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
             const uint32_t h = s_slot[(ci0 >> log2M) - slot0];
             p0 = (h << log2M) - half + (ci0 & (M - 1u));   // mod 2^32: N divides it
             constexpr uint32_t kAll = (1u << kVotePerThread) - 1u;   // the thread's candidates
-            uint32_t m[VL], q[VL];
+            // q[r]: loop r's hash argument times 2^(32 - log2M) in 64 bits, so that its high
+            // word starts at the bucket; one 64-bit add per candidate
+            uint32_t m[VL];
+            uint64_t q[VL], cq[VL];
+            const uint32_t sh = 32u - log2M;
 #pragma unroll
             for (int r = 1; r < VL; ++r) {
                 m[r] = 0u;
-                q[r] = cr[r] * p0 + half;
+                q[r] = (uint64_t)(cr[r] * p0 + half) << sh;
+                cq[r] = (uint64_t)cr[r] << sh;
             }
             bool split = false;
             if constexpr (kExact && VL >= 4) {
@@ -226,8 +254,8 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
                     for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
 #pragma unroll
                         for (int r = 1; r < P1; ++r) {
-                            m[r] |= test1(r, q[r]) << qq;
-                            q[r] += cr[r];
+                            m[r] |= test_hi(r, (uint32_t)(q[r] >> 32)) << qq;
+                            q[r] += cq[r];
                         }
                     }
                     VoteCount<vote_planes(P1 - 1)> c1;
@@ -256,8 +284,8 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
                 for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
 #pragma unroll
                     for (int r = 1; r < VL; ++r) {
-                        m[r] |= test1(r, q[r]) << qq;
-                        q[r] += cr[r];
+                        m[r] |= test_hi(r, (uint32_t)(q[r] >> 32)) << qq;
+                        q[r] += cq[r];
                     }
                 }
                 VoteCount<vote_planes(VL - 1)> c;
