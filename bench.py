@@ -49,6 +49,11 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def vote_flags(args) -> int:
+    import paper_2012_08238_amd as S
+    return {"auto": 0, "loop": S.SFFT_FLAG_VOTE_BY_LOOP, "pair": S.SFFT_FLAG_VOTE_BY_PAIR}[args.vote]
+
+
 def committed_traffic(batch: int):
     """HBM bytes per bucketization launch from the committed counter summary,
     or None when it is absent, for another batch, or the kernel source changed."""
@@ -136,6 +141,7 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
                    n_streams=args.serve_streams)
     fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
     fflags |= S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" and 4096 <= B <= 16384 else 0
+    fflags |= vote_flags(args)
     h = srv.prepare(S.PlanParams(N, K, B, L, args.w_over_b * B, seed=PLAN_SEED, strip_cols=args.strip_cols,
                                  flags=fflags))
     n = max(1, int(args.serve_rate * args.serve_seconds))
@@ -638,6 +644,8 @@ def main() -> int:
     ap.add_argument("--fft", choices=["two-pass", "one-workgroup"], default="one-workgroup",
                     help="B-point FFT form of the step's plan (two passes of small workgroups share compute units "
                          "with the next step's bucketization)")
+    ap.add_argument("--vote", choices=["auto", "loop", "pair"], default="auto",
+                    help="vote enumeration: by loop, by loop pair, or the plan's choice")
     ap.add_argument("--xcd-order", action="store_true", help="XCD-grouped workgroup order for the bucketization")
     ap.add_argument("--single-passes", type=int, default=3, help="passes over the batch through sfft_execute alone")
     ap.add_argument("--branches", type=int, default=1, help="parallel stream branches of the step's batch graph")
@@ -695,7 +703,7 @@ def main() -> int:
     W = args.w_over_b * B
     fflags = {"auto": 0, "strip": S.SFFT_FLAG_FOLD_STRIP, "gather": S.SFFT_FLAG_FOLD_GATHER}[args.fold]
     plan = S.Plan(N, K, B, L, W, seed=PLAN_SEED, strip_cols=args.strip_cols,
-                  flags=fflags | (S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0) |
+                  flags=fflags | (S.SFFT_FLAG_XCD_ORDER if args.xcd_order else 0) | vote_flags(args) |
                   (S.SFFT_FLAG_FFT_TWO_PASS if args.fft == "two-pass" and 4096 <= B <= 16384 else 0))
     desc = plan.desc
     batch = S.Batch([plan] * M, branches=args.branches)
@@ -886,7 +894,7 @@ def main() -> int:
                    "N": N, "K": K, "B": B, "L": L, "w": W, "snr_db": SNR_DB, "batch": M,
                    "fold_mode": "strip" if desc["fold_mode"] == 1 else "gather",
                    "strip_cols": desc["strip_cols"], "graph_branches": args.branches, "steps_in_flight": nf,
-                   "fft": args.fft,
+                   "fft": args.fft, "vote_pairs": desc["vote_pairs"],
                    "parallelism": "single-gpu"},
         "latency": ({"p50_ms": serving["poisson"]["p50_ms"], "p99_ms": serving["poisson"]["p99_ms"],
                      "source": f"serving loop, Poisson arrivals at {serving['poisson']['rate_req_s']:.0f} req/s, "

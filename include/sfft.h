@@ -100,6 +100,19 @@ typedef enum {
                                          SFFT_FLAG_ITERATE or SFFT_FLAG_PHASE_LOCATION (SFFT_E_UNSUPPORTED);
                                          other B: SFFT_E_INVALID. */
 
+#define SFFT_MAX_VOTE_PAIRS 32
+#define SFFT_FLAG_VOTE_BY_LOOP 0x100u /* votes: enumerate the frequencies of the selected buckets of
+                                         loops 0..L-T (by the pigeonhole principle every frequency with
+                                         >= T votes is voted by one of them) and test each against the
+                                         other loops. The candidate set is the same in either form. */
+#define SFFT_FLAG_VOTE_BY_PAIR 0x200u /* votes: split the loops into T-1 groups of consecutive loops;
+                                         any T loops hold two of one group, so every frequency with >= T
+                                         votes is voted by both loops of a pair within a group. Each pair
+                                         enumerates its first loop's selected buckets and tests its
+                                         second loop; only those that pass are tested against the rest.
+                                         Needs T >= 2 and at most 32 pairs (else SFFT_E_INVALID). Without
+                                         either flag the plan takes the form with fewer expected tests. */
+
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {
     int64_t N;              /* signal length, power of two */
@@ -155,6 +168,11 @@ typedef struct {
      * gain (<= 1e-6; 0 when no bucket is left out). All three are 0 without the flag. */
     int32_t sub_reach_lo, sub_reach_hi;
     double sub_tail_bound;
+    /* Vote enumeration: vote_pairs = 0 by loop (loops 0..L-T), else the number of loop pairs,
+     * vote_pair[e] = first loop | second loop << 8, in the order in which a frequency voted
+     * by several pairs is counted from the first (see SFFT_FLAG_VOTE_BY_PAIR). */
+    int32_t vote_pairs;
+    uint16_t vote_pair[SFFT_MAX_VOTE_PAIRS];
 } sfft_plan_desc;
 
 /* Host copies of one execution's intermediates (all pointers host, caller-owned,

@@ -15,13 +15,14 @@ import numpy as np
 from . import _capi
 from ._capi import (SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, SFFT_FLAG_XCD_ORDER, SFFT_FLAG_NO_RESIDUAL,  # noqa: F401,E501
                     SFFT_FLAG_MEAN_ESTIMATE, SFFT_FLAG_ITERATE, SFFT_FLAG_PHASE_LOCATION, SFFT_FLAG_FFT_TWO_PASS,
+                    SFFT_FLAG_VOTE_BY_LOOP, SFFT_FLAG_VOTE_BY_PAIR,
                     SfftError, check,
                     load)
 
 __all__ = ["PlanParams", "Plan", "Batch", "Server", "host_tables", "params_describe", "load", "SfftError",
            "SFFT_FLAG_FOLD_GATHER", "SFFT_FLAG_FOLD_STRIP", "SFFT_FLAG_XCD_ORDER", "SFFT_FLAG_NO_RESIDUAL",
            "SFFT_FLAG_MEAN_ESTIMATE", "SFFT_FLAG_ITERATE", "SFFT_FLAG_PHASE_LOCATION",
-           "SFFT_FLAG_FFT_TWO_PASS"]
+           "SFFT_FLAG_FFT_TWO_PASS", "SFFT_FLAG_VOTE_BY_LOOP", "SFFT_FLAG_VOTE_BY_PAIR"]
 
 
 @dataclass
@@ -86,13 +87,20 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def _desc_dict(d) -> dict:
+    """A plan description as a dict; the loop pairs of the vote as a list of (first, second)."""
+    out = {f: getattr(d, f) for f, _ in _capi.PlanDesc._fields_ if f != "vote_pair"}
+    out["vote_pair"] = [(v & 255, v >> 8) for v in list(d.vote_pair)[:d.vote_pairs]]
+    return out
+
+
 def params_describe(params: PlanParams) -> dict:
     """The description sfft_plan_ex would give these parameters, without a device."""
     p, keep = params.to_c()
     d = _capi.PlanDesc()
     check(load().sfft_params_describe(C.byref(p), C.byref(d)), "sfft_params_describe")
     del keep
-    return {f: getattr(d, f) for f, _ in _capi.PlanDesc._fields_}
+    return _desc_dict(d)
 
 
 def host_tables(params: PlanParams) -> dict:
@@ -140,7 +148,7 @@ class Plan:
     def describe(self) -> dict:
         d = _capi.PlanDesc()
         check(load().sfft_plan_describe(self._h, C.byref(d)), "sfft_plan_describe")
-        return {f: getattr(d, f) for f, _ in _capi.PlanDesc._fields_}
+        return _desc_dict(d)
 
     def perms(self):
         """sigma, sigma^{-1}, tau of every loop (the estimation-only loops last)."""

@@ -22,6 +22,8 @@ SFFT_FLAG_MEAN_ESTIMATE = 0x10
 SFFT_FLAG_ITERATE = 0x20
 SFFT_FLAG_PHASE_LOCATION = 0x40
 SFFT_FLAG_FFT_TWO_PASS = 0x80
+SFFT_FLAG_VOTE_BY_LOOP = 0x100
+SFFT_FLAG_VOTE_BY_PAIR = 0x200
 
 
 class Params(C.Structure):
@@ -40,7 +42,8 @@ class PlanDesc(C.Structure):
                 ("fold_mode", C.c_int32), ("strip_cols", C.c_int32), ("cand_cap", C.c_int64),
                 ("table_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
                 ("sampled_fraction_expected", C.c_double),
-                ("sub_reach_lo", C.c_int32), ("sub_reach_hi", C.c_int32), ("sub_tail_bound", C.c_double)]
+                ("sub_reach_lo", C.c_int32), ("sub_reach_hi", C.c_int32), ("sub_tail_bound", C.c_double),
+                ("vote_pairs", C.c_int32), ("vote_pair", C.c_uint16 * 32)]
 
 
 class Trace(C.Structure):

@@ -103,6 +103,9 @@ SigDesc make_desc(const Resolved& R, char* tab, char* ws) {
     d.vote_units = R.vote_units;
     d.vote_upl = R.vote_upl;
     d.vote_split = R.vote_split;
+    d.vote_pairs = R.vote_pairs;
+    d.vote_sub = R.vote_sub;
+    memcpy(d.vote_pair, R.vote_pair, sizeof(d.vote_pair));
     d.resid_blocks = R.resid_blocks;
     d.resid_log2kl = R.resid_log2kl;
     d.est_units = R.est_units;
@@ -420,6 +423,8 @@ static void fill_desc(const Resolved& R, size_t tab_bytes, size_t ws_bytes, sfft
     out->sub_reach_lo = (int32_t)R.sub_rl;
     out->sub_reach_hi = (int32_t)R.sub_rh;
     out->sub_tail_bound = R.sub_bound;
+    out->vote_pairs = (int32_t)R.vote_pairs;
+    memcpy(out->vote_pair, R.vote_pair, sizeof(out->vote_pair));
 }
 
 sfft_status sfft_plan_describe(sfft_plan_t p, sfft_plan_desc* out) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/sfft.h"
+
 namespace sfft {
 
 constexpr int kMaxL = 32;        // loops supported (bitmaps, median sorting network)
@@ -62,6 +64,9 @@ struct SigDesc {
     uint32_t vote_units;        // vote workgroups
     uint32_t vote_upl;          // vote workgroups per enumerated loop (chunks of kVoteUnit candidates)
     uint32_t vote_split;        // 1: votes tested in two phases (few selected buckets, T = L/2 + 1)
+    uint32_t vote_pairs;        // 0: enumeration by loop; else by these loop pairs (vote_pair)
+    uint32_t vote_sub;          // kVoteUnit-candidate runs per vote chunk (by pair at N/B >= 16: kVotePairSub)
+    uint16_t vote_pair[SFFT_MAX_VOTE_PAIRS];   // first loop | second loop << 8
     uint32_t resid_blocks;      // residual workgroups
     uint32_t resid_log2kl;      // residual: lanes per run (the outputs split 2^resid_log2kl ways)
     uint32_t est_units;         // estimation workgroups (striding over the candidates)
@@ -107,7 +112,11 @@ constexpr uint32_t kVoteUnit = kVoteNT * kVotePerThread;  // candidates per vote
 constexpr uint32_t kVoteMaxGrid = 4u * 256u;
 // LDS words for the selected-bucket slots one vote workgroup enumerates (N/B = 2^log2M
 // candidates per slot), a multiple of 4 so the staged bitmaps after them stay 16-byte aligned
-__host__ __device__ constexpr uint32_t vote_slot_words(uint32_t log2M) { return ((kVoteUnit >> log2M) + 1u + 3u) & ~3u; }
+constexpr uint32_t kVotePairSub = 4;   // by pair (N/B >= 16): kVoteUnit-candidate runs per chunk
+// selected-bucket slot words of a chunk of sub * kVoteUnit candidates
+__host__ __device__ constexpr uint32_t vote_slot_words(uint32_t log2M, uint32_t sub = 1u) {
+    return (((sub * kVoteUnit) >> log2M) + 1u + 3u) & ~3u;
+}
 // Vote kernel instance of a plan with L location loops: L itself up to 16, else 32.
 __host__ __device__ constexpr uint32_t vote_key(uint32_t L) { return L <= 16u ? L : 32u; }
 constexpr uint32_t kVoteKeys = 17;   // distinct vote_key values

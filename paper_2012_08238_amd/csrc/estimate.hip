@@ -111,7 +111,7 @@ struct VoteCount {
 // (the workgroup's previous chunk was another signal's).
 template <int VL, bool STAGED>
 __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32_t unit, uint32_t round, bool restage,
-                                           uint32_t* sdyn, uint32_t* s_comb) {
+                                           uint32_t* sdyn, uint32_t* s_comb, uint32_t* s_pq) {
     constexpr bool kExact = VL <= 16;
     constexpr uint32_t kLog2PT = 4;
     static_assert((1u << kLog2PT) == kVotePerThread, "candidates per thread");
@@ -121,28 +121,49 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
     const uint32_t T = d.T, M = d.M, log2M = d.log2M, maskN = d.maskN, log2B = d.log2B, dK = d.dK;
     const uint32_t* jbits = d.jbits;
     // this workgroup: candidates [start, end) of enumerated loop r0, i.e. the
-    // permuted positions of selected-bucket slots slot0 .. slot0 + nslots - 1
+    // permuted positions of selected-bucket slots slot0 .. slot0 + nslots - 1. By loop the
+    // units run over loops r0 = 0..L-T; by pair over the pairs e = (r0, r1), r0 < r1.
     const uint32_t upl = d.vote_upl;
-    const uint32_t r0 = unit / upl;
+    const uint32_t npair = d.vote_pairs;
+    const uint32_t e = unit / upl;
+    const uint32_t pr = npair ? (uint32_t)d.vote_pair[e] : 0u;
+    const uint32_t r0 = npair ? (pr & 255u) : e;
+    const uint32_t r1 = pr >> 8;
     const uint32_t per_loop = dK * M;
-    const uint32_t start = (unit - r0 * upl) * kVoteUnit;
-    const uint32_t end = min(start + kVoteUnit, per_loop);
+    const uint32_t sub = d.vote_sub;   // runs of kVoteUnit candidates in this chunk
+    const uint32_t start = (unit - e * upl) * (sub * kVoteUnit);
+    const uint32_t end = min(start + sub * kVoteUnit, per_loop);
     const uint32_t slot0 = start >> log2M;
     const uint32_t nslots = ((end - 1u) >> log2M) - slot0 + 1u;
     const uint32_t sinv0 = ((CU32)d.sigma_inv)[r0];
     uint32_t* s_slot = sdyn;
-    uint32_t* sbits = sdyn + vote_slot_words(log2M);
+    uint32_t* sbits = sdyn + vote_slot_words(log2M, sub);
     const uint32_t* jl = d.jlist + (size_t)r0 * dK + slot0;
     for (uint32_t i = threadIdx.x; i < nslots; i += kVoteNT) s_slot[i] = gld(jl + i);
     // loop slots: slot 0 is r0 (it voted for every candidate it enumerates, so it is not
-    // tested), slots 1..r0 the loops before it, then the loops after it in order
-    uint32_t cr[VL], boff[VL];   // c_r and the bitmap offset of each slot's loop: uniform
+    // tested); by loop, slots 1..r0 the loops before it, then the loops after it in order;
+    // by pair, slot 1 the pair's second loop r1, then the other loops in order
+    uint32_t cr[VL], boff[VL], lp[VL];   // c_r, bitmap offset and loop of each slot: uniform
 #pragma unroll
     for (int j = 0; j < VL; ++j) {
-        const uint32_t r = j == 0 ? r0 : ((uint32_t)j <= r0 ? (uint32_t)j - 1u : (uint32_t)j);
+        uint32_t r;
+        if (j == 0) {
+            r = r0;
+        } else if (npair) {
+            if (j == 1) {
+                r = r1;
+            } else {
+                r = (uint32_t)j - 2u;
+                if (r >= r0) ++r;
+                if (r >= r1) ++r;
+            }
+        } else {
+            r = (uint32_t)j <= r0 ? (uint32_t)j - 1u : (uint32_t)j;
+        }
         const uint32_t rr = kExact ? r : min(r, L - 1u);
         cr[j] = ((CU32)d.sigma)[rr] * sinv0;
         boff[j] = rr * wpl;
+        lp[j] = rr;
     }
     const uint32_t ncomb = d.comb_loops, cmask = (1u << d.comb_log2b) - 1u;
     if (ncomb && restage) {
@@ -217,6 +238,27 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
     auto voted = [&](uint32_t votes) -> uint32_t {
         return ((votes & before_r0) == 0u && (uint32_t)__popc(votes) >= T) ? 1u : 0u;
     };
+    // By pair, a position p whose frequency the pair's two loops voted for: the other loops'
+    // tests; it passes with >= T votes, counted from the first pair whose loops both voted.
+    const bool n24 = d.log2N <= 24u;   // hash arguments mod N from 24-bit products
+    auto pair_passes = [&](uint32_t p) -> bool {
+        uint32_t cnt = 2u, vset = (1u << r0) | (1u << r1);
+        const uint32_t pm24 = p & maskN;
+#pragma unroll
+        for (int j = 2; j < VL; ++j) {
+            const uint32_t qv = (n24 ? __umul24(cr[j] & maskN, pm24) : cr[j] * p) + half;
+            const uint32_t b = test1(j, qv);
+            cnt += b;
+            vset |= b << lp[j];
+        }
+        if (cnt < T) return false;
+        for (uint32_t e2 = 0; e2 < e; ++e2) {
+            const uint32_t q2 = d.vote_pair[e2];
+            const uint32_t pm = (1u << (q2 & 255u)) | (1u << (q2 >> 8));
+            if ((vset & pm) == pm) return false;
+        }
+        return true;
+    };
     uint32_t fv[kVotePerThread];
     uint32_t emask = 0;   // bit qq: candidate qq of this thread passes
     if (log2M >= kLog2PT) {
@@ -226,15 +268,87 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
         // candidates are then counted bit-sliced over those masks.
         const uint32_t ci0 = start + (threadIdx.x << kLog2PT);
         uint32_t p0 = 0;
+        if (npair) {   // block-uniform
+            // Each of the chunk's runs of kVoteUnit candidates: the pair's second loop for this
+            // thread's 16 (bit 16 s + qq of m1: run s, candidate qq). Then the positions it voted
+            // for, compacted across the wave (an exclusive scan of the lanes' counts) and taken 64
+            // at a time, one per lane: the other loops' tests, the comb residue, the recovered
+            // set and the list.
+            static_assert(kVotePairSub == 4, "the run's base position is picked from four");
+            uint32_t p0s[kVotePairSub];
+            uint64_t m1 = 0u;
+            const uint32_t sh = 32u - log2M;
+#pragma unroll
+            for (uint32_t sr = 0; sr < kVotePairSub; ++sr) {
+                p0s[sr] = 0u;
+                const uint32_t cs = ci0 + sr * kVoteUnit;
+                if (sr < sub && cs < end) {
+                    const uint32_t h = s_slot[(cs >> log2M) - slot0];
+                    p0s[sr] = (h << log2M) - half + (cs & (M - 1u));
+                    uint64_t q1 = (uint64_t)(cr[1] * p0s[sr] + half) << sh;
+                    const uint64_t c1q = (uint64_t)cr[1] << sh;
+                    uint32_t mr = 0u;
+#pragma unroll
+                    for (uint32_t qq = 0; qq < kVotePerThread; ++qq) {
+                        mr |= test_hi(1, (uint32_t)(q1 >> 32)) << qq;
+                        q1 += c1q;
+                    }
+                    m1 |= (uint64_t)mr << (kVotePerThread * sr);
+                }
+            }
+            uint32_t* wq = s_pq + (threadIdx.x & ~63u);
+            const uint32_t lane = threadIdx.x & 63u;
+            const uint32_t c = (uint32_t)__popcll(m1);
+            const uint32_t incl = wave_incl_scan(c);
+            const uint32_t total = __shfl(incl, 63, 64);
+            const uint32_t base = incl - c;
+            const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;   // first-round frequencies
+            for (uint32_t done = 0; done < total; done += 64u) {   // wave-uniform
+                if (base + c > done && base < done + 64u) {
+                    uint64_t mm = m1;
+                    uint32_t k = base;
+                    while (mm) {
+                        const uint32_t b = (uint32_t)__builtin_ctzll(mm);
+                        mm &= mm - 1u;
+                        if (k >= done && k < done + 64u) {
+                            const uint32_t sr = b >> kLog2PT;
+                            const uint32_t pb = sr == 0u ? p0s[0] : (sr == 1u ? p0s[1] : (sr == 2u ? p0s[2] : p0s[3]));
+                            wq[k - done] = pb + (b & (kVotePerThread - 1u));
+                        }
+                        ++k;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                uint32_t fa[1] = {0u};
+                bool pass = false;
+                if (done + lane < total) {
+                    const uint32_t p = wq[lane];
+                    pass = pair_passes(p);
+                    fa[0] = (sinv0 * p) & maskN;
+                    if (pass && ncomb) {
+                        const uint32_t res = fa[0] & cmask;
+                        pass = (s_comb[res >> 5] >> (res & 31u)) & 1u;
+                    }
+                    if (pass && n1) pass = !in_sorted(d.rec_f, n1, fa[0]);
+                }
+                append_wave<1>(fa, pass ? 1u : 0u, ctr, cand, cap);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // this round's reads before the next writes
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            return;
+        }
         if (ci0 < end) {
             const uint32_t h = s_slot[(ci0 >> log2M) - slot0];
             p0 = (h << log2M) - half + (ci0 & (M - 1u));   // mod 2^32: N divides it
             constexpr uint32_t kAll = (1u << kVotePerThread) - 1u;   // the thread's candidates
-            // q[r]: loop r's hash argument times 2^(32 - log2M) in 64 bits, so that its high
-            // word starts at the bucket; one 64-bit add per candidate
+            // a loop's hash argument times 2^(32 - log2M) in 64 bits, so that its high word
+            // starts at the bucket; one 64-bit add per candidate
+            const uint32_t sh = 32u - log2M;
             uint32_t m[VL];
             uint64_t q[VL], cq[VL];
-            const uint32_t sh = 32u - log2M;
 #pragma unroll
             for (int r = 1; r < VL; ++r) {
                 m[r] = 0u;
@@ -319,11 +433,15 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
             if (ci < end) {
                 const uint32_t h = s_slot[(ci >> log2M) - slot0];
                 const uint32_t p = (h << log2M) - half + (ci & (M - 1u));
-                uint32_t votes = 1u;
-#pragma unroll
-                for (int r = 1; r < VL; ++r) votes |= test(r, cr[r] * p + half);
                 fv[qq] = (sinv0 * p) & maskN;
-                emask |= voted(votes) << qq;
+                if (npair) {
+                    if (test1(1, cr[1] * p + half) && pair_passes(p)) emask |= 1u << qq;
+                } else {
+                    uint32_t votes = 1u;
+#pragma unroll
+                    for (int r = 1; r < VL; ++r) votes |= test(r, cr[r] * p + half);
+                    emask |= voted(votes) << qq;
+                }
             }
         }
     }
@@ -356,6 +474,7 @@ template <int VL, bool STAGED>
 __global__ __launch_bounds__(kVoteNT, STAGED ? 6 : 1) void vote_kernel(Launch a, uint32_t round, uint32_t units) {
     extern __shared__ uint32_t sdyn[];
     __shared__ uint32_t s_comb[kMaxCombB / 32];       // residues kept by the comb prefilter (union)
+    __shared__ uint32_t s_pq[kVoteNT];                // by pair: each wave's queue of positions to finish
     const uint32_t b0 = (uint32_t)(((uint64_t)blockIdx.x * units) / gridDim.x);
     const uint32_t b1 = (uint32_t)(((uint64_t)(blockIdx.x + 1u) * units) / gridDim.x);
     uint32_t prev = 0xffffffffu;
@@ -363,7 +482,7 @@ __global__ __launch_bounds__(kVoteNT, STAGED ? 6 : 1) void vote_kernel(Launch a,
         uint32_t sig, unit;
         resolve_blk(a, blk, sig, unit);
         if (blk != b0) __syncthreads();   // the previous chunk's LDS reads are done
-        vote_chunk<VL, STAGED>(a, sig, unit, round, sig != prev, sdyn, s_comb);
+        vote_chunk<VL, STAGED>(a, sig, unit, round, sig != prev, sdyn, s_comb, s_pq);
         prev = sig;
     }
 }

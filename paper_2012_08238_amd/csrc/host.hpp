@@ -39,6 +39,9 @@ struct Resolved {
     uint32_t fold_units, vote_units, vote_upl, resid_blocks, vote_lds, strip_lds, resid_lds, fin_lds;
     uint32_t resid_log2kl;      // residual: lanes per run, log2
     uint32_t vote_split;        // votes in two phases (dK/B <= 1/32, T = L/2 + 1, 4 <= L <= 16)
+    uint32_t vote_pairs;        // 0: votes enumerated by loop; else the number of loop pairs
+    uint32_t vote_sub;          // kVoteUnit-candidate runs per vote chunk
+    uint16_t vote_pair[SFFT_MAX_VOTE_PAIRS];   // pair e: first loop | second loop << 8
     uint32_t vote_dyn_lds;      // vote dynamic LDS: slot words + staged bitmaps (vote_lds, 0 = not staged)
     uint32_t est_units;
     uint32_t L_est() const { return est ? est->L : 0u; }

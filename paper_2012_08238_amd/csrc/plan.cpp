@@ -278,10 +278,64 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     // two-phase vote tests where few buckets are selected (a random candidate rarely gets a
     // second vote among the first L - T + 2 loops) and the threshold is the default majority
     R.vote_split = (!phase && R.L >= 4 && R.L <= 16 && R.T == R.L / 2 + 1 && (uint64_t)R.dK * 32u <= R.B) ? 1u : 0u;
+    // Enumeration by loop pairs: the L loops split into T-1 groups of consecutive loops (sizes
+    // differ by at most one); any T loops hold two of one group (pigeonhole), so a frequency
+    // with >= T votes is voted by both loops of some pair within a group. A pair enumerates
+    // its first loop's selected buckets and tests its second loop; the few that pass take the
+    // other loops' tests. Cost per enumerated frequency, in bitmap tests: by loop L-1 (or, in
+    // two phases, the first phase's tests plus the rest for the share with a second vote), by
+    // pair 1 + 25 (L-2) q with q = dK/B (the rest is gathered across the wave, 64 positions
+    // per round, and tested one frequency per lane with a list reservation per round), each
+    // plus 6 for the chunk's fixed work (slots, barriers, list reservation) over the chunk's
+    // runs of kVoteUnit. The weights are fitted to vote timings at q = 1.2%, 3%, 9.8% and 12%:
+    // pairs pay off where few buckets are selected.
+    R.vote_pairs = 0;
+    R.vote_sub = 1;
+    memset(R.vote_pair, 0, sizeof(R.vote_pair));
+    if (!phase && R.T >= 2) {
+        const uint32_t g = R.T - 1, base = R.L / g, extra = R.L % g;
+        uint32_t np = 0, first = 0;
+        for (uint32_t i = 0; i < g; ++i) {
+            const uint32_t size = base + (i < extra ? 1u : 0u);
+            for (uint32_t a = first; a < first + size; ++a)
+                for (uint32_t b = a + 1; b < first + size; ++b) {
+                    if (np < SFFT_MAX_VOTE_PAIRS) R.vote_pair[np] = (uint16_t)(a | (b << 8));
+                    ++np;
+                }
+            first += size;
+        }
+        const double q = (double)R.dK / (double)R.B;
+        double by_loop = (double)(R.L - 1);
+        if (R.vote_split) {
+            const uint32_t P1 = R.L - R.T + 2;
+            by_loop = (double)(P1 - 1) + 3.0 * (1.0 - pow(1.0 - q, (double)(P1 - 1))) * (double)(R.L - P1);
+        }
+        const double sub = R.log2M >= 4 ? (double)kVotePairSub : 1.0;
+        const double cost_loop = (double)(R.L - R.T + 1) * (by_loop + 6.0);
+        const double cost_pair = (double)np * (1.0 + 25.0 * q * (double)(R.L - 2) + 6.0 / sub);
+        const bool fits = np >= 1 && np <= SFFT_MAX_VOTE_PAIRS;
+        if (p.flags & SFFT_FLAG_VOTE_BY_PAIR) {
+            if (!fits) return bad("vote by pairs needs T >= 2 and at most 32 loop pairs");
+            R.vote_pairs = np;
+        } else if (!(p.flags & SFFT_FLAG_VOTE_BY_LOOP) && fits && cost_pair < cost_loop) {
+            R.vote_pairs = np;
+        }
+        if (!R.vote_pairs) memset(R.vote_pair, 0, sizeof(R.vote_pair));
+    } else if (p.flags & SFFT_FLAG_VOTE_BY_PAIR) {
+        return bad("vote by pairs needs T >= 2 and location by votes");
+    }
+    if ((p.flags & SFFT_FLAG_VOTE_BY_PAIR) && (p.flags & SFFT_FLAG_VOTE_BY_LOOP))
+        return bad("SFFT_FLAG_VOTE_BY_PAIR and SFFT_FLAG_VOTE_BY_LOOP are exclusive");
+    if (R.vote_pairs) {
+        R.vote_sub = R.log2M >= 4 ? kVotePairSub : 1u;
+        const uint32_t chunk = R.vote_sub * kVoteUnit;
+        R.vote_upl = (R.dK * R.M + chunk - 1) / chunk;
+        R.vote_units = R.vote_pairs * R.vote_upl;
+    }
     const uint32_t wpl = (R.B + 31) / 32;
     const uint32_t vbytes = (R.L * wpl * 4u + 15u) & ~15u;
     R.vote_lds = vbytes <= 98304u ? vbytes : 0u;   // bitmaps staged in LDS up to 96 KB (B = 65536 at L <= 12)
-    R.vote_dyn_lds = vote_slot_words(R.log2M) * 4u + R.vote_lds;
+    R.vote_dyn_lds = vote_slot_words(R.log2M, R.vote_sub) * 4u + R.vote_lds;
     // B-point FFT: in one workgroup's LDS up to kMaxFftLds, else two passes
     // (B = B1 * B2, tiles of 16 sequences per workgroup) and a selection workgroup per loop
     R.fft_mode = (R.B > (uint32_t)kMaxFftLds || (p.flags & SFFT_FLAG_FFT_TWO_PASS)) ? 1u : 0u;

@@ -134,14 +134,15 @@ def test_edge_cases(dev, cfg):
 
 @pytest.mark.parametrize("L,T", [(4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (9, 6)])
 def test_vote_two_phase(dev, L, T):
-    """Few selected buckets (dK/B = 1/64) with the default majority: the vote tests the
-    first L - T + 2 loops for every candidate and the rest only for those that can still
-    reach T. Candidate sets, supports and values as the oracle; T = 6 of 9 (not the
+    """Few selected buckets (dK/B = 1/64) with the default majority, enumerated by loop: the
+    vote tests the first L - T + 2 loops for every candidate and the rest only for those that
+    can still reach T. Candidate sets, supports and values as the oracle; T = 6 of 9 (not the
     default) takes the one-phase tests."""
     N, K, B = 1 << 20, 16, 2048
     assert 2 * K * 32 <= B
     sig = make_signal(N, K, 20.0, seed=900 + L)
-    g = _run(dev, sig.x, K=K, B=B, L=L, w=8 * B, seed=L, vote_threshold=T)
+    import paper_2012_08238_amd as S
+    g = _run(dev, sig.x, K=K, B=B, L=L, w=8 * B, seed=L, vote_threshold=T, flags=S.SFFT_FLAG_VOTE_BY_LOOP)
     r = _oracle(sig.x, K, B, L, 8 * B, L, vote_threshold=T)
     compare(g, r, K, B, L, 8 * B, L)
     check_residual(g, sig.x, r.trace["tpos"])

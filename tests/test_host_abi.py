@@ -119,6 +119,49 @@ def test_two_pass_fft_validation():
     assert e.value.status == _capi.SFFT_E_UNSUPPORTED
 
 
+def test_vote_pairs_cover_every_threshold_set():
+    """By pair, every T-subset of the L loops holds one of the plan's pairs (so every frequency
+    with >= T votes is enumerated by a pair whose two loops voted for it); brute force over the
+    subsets."""
+    from itertools import combinations
+    for L in range(2, 13):
+        for T in range(2, L + 1):
+            g = T - 1
+            sizes = [L // g + (1 if i < L % g else 0) for i in range(g)]
+            if sum(z * (z - 1) // 2 for z in sizes) > 32:
+                continue
+            d = S.params_describe(S.PlanParams(N=1 << 14, K=4, B=128, L=L, w=512, vote_threshold=T,
+                                               flags=S.SFFT_FLAG_VOTE_BY_PAIR))
+            pairs = d["vote_pair"]
+            assert d["vote_pairs"] == len(pairs) >= 1
+            assert all(0 <= a < b < L for a, b in pairs) and len(set(pairs)) == len(pairs)
+            ps = [set(q) for q in pairs]
+            for sub in combinations(range(L), T):
+                ss = set(sub)
+                assert any(q <= ss for q in ps), (L, T, sub)
+
+
+def test_vote_mode_choice_and_validation():
+    def desc(**kw):
+        base = dict(N=1 << 22, K=100, B=16384, L=9, w=131072)
+        base.update(kw)
+        return S.params_describe(S.PlanParams(**base))
+    # the benchmark shape: 4 groups (3, 2, 2, 2) of consecutive loops, 6 pairs
+    assert desc()["vote_pair"] == [(0, 1), (0, 2), (1, 2), (3, 4), (5, 6), (7, 8)]
+    assert desc(flags=S.SFFT_FLAG_VOTE_BY_LOOP)["vote_pairs"] == 0
+    assert desc(vote_threshold=1)["vote_pairs"] == 0            # T = 1: no pair needed
+    assert desc(vote_threshold=2)["vote_pairs"] == 0            # one group of 9: 36 pairs
+    assert desc(vote_threshold=3, flags=S.SFFT_FLAG_VOTE_BY_PAIR)["vote_pairs"] == 16   # 5 + 4 loops
+    for kw in (dict(vote_threshold=1, flags=S.SFFT_FLAG_VOTE_BY_PAIR),
+               dict(vote_threshold=2, flags=S.SFFT_FLAG_VOTE_BY_PAIR),   # 36 pairs
+               dict(flags=S.SFFT_FLAG_VOTE_BY_PAIR | S.SFFT_FLAG_VOTE_BY_LOOP)):
+        with pytest.raises(S.SfftError) as e:
+            desc(**kw)
+        assert e.value.status == _capi.SFFT_E_INVALID
+    # phase location has no vote
+    assert desc(L=4, flags=S.SFFT_FLAG_PHASE_LOCATION)["vote_pairs"] == 0
+
+
 def test_iterate_validation_and_gain():
     # the subtraction round runs with the one-workgroup FFT only
     with pytest.raises(S.SfftError) as e:
