@@ -45,6 +45,12 @@ __device__ __forceinline__ void append_wave(const uint32_t (&fv)[P], uint32_t em
 // In the subtraction round (round 1) the frequencies recovered by the first
 // round are not candidates again.
 //
+// By loop pair (vote_pairs > 0): the loops split into T-1 groups of consecutive loops, so any
+// T loops hold two of one group and every frequency with >= T votes is voted by both loops of
+// some pair within a group. Pair (r0, r1) enumerates loop r0's selected buckets like a loop
+// does, tests loop r1 first, and finishes only those r1 voted for; a frequency is counted from
+// the first pair in list order whose two loops both voted for it. Same candidate set.
+//
 // Loop r hashes f = sigma_r0^{-1} p to bucket ((c_r p + N/2B) mod N) >> log2(N/B)
 // with c_r = sigma_r sigma_r0^{-1} (mod N, a workgroup constant). A thread takes
 // kVotePerThread consecutive positions p of one selected bucket (when N/B allows),
@@ -105,8 +111,8 @@ struct VoteCount {
     }
 };
 
-// One chunk of kVoteUnit candidates (unit `unit` of signal `sig`). sdyn: the chunk's
-// selected-bucket slots (vote_slot_words(log2 N/B) words), then (staged) the L
+// One chunk of vote_sub x kVoteUnit candidates (unit `unit` of signal `sig`). sdyn: the
+// chunk's selected-bucket slots (vote_slot_words(log2 N/B, vote_sub) words), then (staged) the L
 // selected-bucket bitmaps, which (like the comb residues) are copied only when `restage`
 // (the workgroup's previous chunk was another signal's).
 template <int VL, bool STAGED>
@@ -303,20 +309,16 @@ __device__ __forceinline__ void vote_chunk(const Launch& a, uint32_t sig, uint32
             const uint32_t total = __shfl(incl, 63, 64);
             const uint32_t base = incl - c;
             const uint32_t n1 = round ? min(gld(ctr + 2), d.K) : 0u;   // first-round frequencies
+            uint64_t mm = m1;   // this lane's positions not yet queued; the next has wave index k
+            uint32_t k = base;
             for (uint32_t done = 0; done < total; done += 64u) {   // wave-uniform
-                if (base + c > done && base < done + 64u) {
-                    uint64_t mm = m1;
-                    uint32_t k = base;
-                    while (mm) {
-                        const uint32_t b = (uint32_t)__builtin_ctzll(mm);
-                        mm &= mm - 1u;
-                        if (k >= done && k < done + 64u) {
-                            const uint32_t sr = b >> kLog2PT;
-                            const uint32_t pb = sr == 0u ? p0s[0] : (sr == 1u ? p0s[1] : (sr == 2u ? p0s[2] : p0s[3]));
-                            wq[k - done] = pb + (b & (kVotePerThread - 1u));
-                        }
-                        ++k;
-                    }
+                while (mm && k < done + 64u) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(mm);
+                    mm &= mm - 1u;
+                    const uint32_t sr = b >> kLog2PT;
+                    const uint32_t pb = sr == 0u ? p0s[0] : (sr == 1u ? p0s[1] : (sr == 2u ? p0s[2] : p0s[3]));
+                    wq[k - done] = pb + (b & (kVotePerThread - 1u));
+                    ++k;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
