@@ -719,6 +719,9 @@ def main() -> int:
     # outputs) on their own streams, so one step's last stages overlap the next step's
     # bucketization; every step still runs every stage over all M signals
     nf = max(1, args.inflight)
+    # each step in flight reads its own copy of the signals (distinct memory, same content), so
+    # that no step can find another's signals in a cache
+    xsets = [xs] + [[x.clone() for x in xs] for _ in range(nf - 1)]
     batches, outsets, streams = [batch], [(idxs, vals, ress)], [torch.cuda.current_stream()]
     for _ in range(nf - 1):
         batches.append(S.Batch([plan] * M, branches=args.branches))
@@ -729,7 +732,7 @@ def main() -> int:
         streams.append(torch.cuda.Stream(device=dev))
     for _ in range(args.warmup):
         for j in range(nf):
-            batches[j].run(xs, *outsets[j], stream=streams[j])
+            batches[j].run(xsets[j], *outsets[j], stream=streams[j])
     torch.cuda.synchronize()
     from paper_2012_08238_amd._hip import HipEvent
     ev = [(HipEvent(), HipEvent()) for _ in range(args.steps)]
@@ -740,12 +743,13 @@ def main() -> int:
             batch.run_timed(xs, idxs, vals, ress, ev[k][0], ev[k][1])
         else:
             j = k % nf
-            batches[j].run(xs, *outsets[j], stream=streams[j])
+            batches[j].run(xsets[j], *outsets[j], stream=streams[j])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     for b_ in batches[1:]:
         b_.close()
+    del xsets[1:]
     launch_source = "bucketization launches of the timed steps"
     if args.branches > 1 or nf > 1:
         # branches and steps in flight run the bucketization beside other stages:
