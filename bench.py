@@ -584,6 +584,8 @@ def uneven_measure(S, torch, dev, args) -> dict:
     # steps in flight as in the main step: batches with their own workspaces and outputs
     # alternate over streams
     nf = max(1, args.uneven_inflight)
+    # each step in flight reads its own copy of the signals (as in the main step)
+    xsets = [xs] + [[x.clone() for x in xs] for _ in range(nf - 1)]
     bs = [S.Batch(plans, branches=args.section_branches) for _ in range(nf)]
     outsets = [[p.outputs(dev) for p in plans] for _ in range(nf)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev) for _ in range(nf - 1)]
@@ -592,7 +594,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
 
     def run(j):
         o = outsets[j]
-        bs[j].run(xs, [q[0] for q in o], [q[1] for q in o], [q[2] for q in o], stream=streams[j])
+        bs[j].run(xsets[j], [q[0] for q in o], [q[1] for q in o], [q[2] for q in o], stream=streams[j])
     for _ in range(2):
         for j in range(nf):
             run(j)
@@ -616,6 +618,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
         b.close()
     for p in plans:
         p.close()
+    del xsets[1:]
     return {"signals": len(specs), "resident_bytes": nbytes, "steps": args.uneven_steps, "steps_in_flight": nf,
             "ms_per_step": round(el / args.uneven_steps * 1e3, 4),
             "signals_per_s": round(len(specs) * args.uneven_steps / el, 1),
