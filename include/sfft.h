@@ -112,6 +112,16 @@ typedef enum {
                                          second loop; only those that pass are tested against the rest.
                                          Needs T >= 2 and at most 32 pairs (else SFFT_E_INVALID). Without
                                          either flag the plan takes the form with fewer expected tests. */
+#define SFFT_FLAG_FUSED 0x400u        /* run the whole path of the signal (bucketization by gathering, FFT,
+                                         selection, votes, estimates, the K largest, residual) in one
+                                         workgroup of one launch, the stages separated by barriers instead
+                                         of kernel boundaries; in a batch every such signal shares one
+                                         launch of persistent workgroups (the batch section's one-launch
+                                         form for small signals). Results are those of the per-stage path.
+                                         Needs 32 <= B <= 4096, L <= 16, K <= 1024, and none of
+                                         SFFT_FLAG_ITERATE, SFFT_FLAG_PHASE_LOCATION, SFFT_FLAG_FFT_TWO_PASS,
+                                         SFFT_FLAG_FOLD_STRIP, the comb prefilter or estimation-only loops
+                                         (else SFFT_E_UNSUPPORTED). */
 
 /* Full parameter set. Fill with sfft_params_init() and then override fields. */
 typedef struct {

@@ -15,14 +15,14 @@ import numpy as np
 from . import _capi
 from ._capi import (SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, SFFT_FLAG_XCD_ORDER, SFFT_FLAG_NO_RESIDUAL,  # noqa: F401,E501
                     SFFT_FLAG_MEAN_ESTIMATE, SFFT_FLAG_ITERATE, SFFT_FLAG_PHASE_LOCATION, SFFT_FLAG_FFT_TWO_PASS,
-                    SFFT_FLAG_VOTE_BY_LOOP, SFFT_FLAG_VOTE_BY_PAIR,
+                    SFFT_FLAG_VOTE_BY_LOOP, SFFT_FLAG_VOTE_BY_PAIR, SFFT_FLAG_FUSED,
                     SfftError, check,
                     load)
 
 __all__ = ["PlanParams", "Plan", "Batch", "Server", "host_tables", "params_describe", "load", "SfftError",
            "SFFT_FLAG_FOLD_GATHER", "SFFT_FLAG_FOLD_STRIP", "SFFT_FLAG_XCD_ORDER", "SFFT_FLAG_NO_RESIDUAL",
            "SFFT_FLAG_MEAN_ESTIMATE", "SFFT_FLAG_ITERATE", "SFFT_FLAG_PHASE_LOCATION",
-           "SFFT_FLAG_FFT_TWO_PASS", "SFFT_FLAG_VOTE_BY_LOOP", "SFFT_FLAG_VOTE_BY_PAIR"]
+           "SFFT_FLAG_FFT_TWO_PASS", "SFFT_FLAG_VOTE_BY_LOOP", "SFFT_FLAG_VOTE_BY_PAIR", "SFFT_FLAG_FUSED"]
 
 
 @dataclass

@@ -24,6 +24,7 @@ SFFT_FLAG_PHASE_LOCATION = 0x40
 SFFT_FLAG_FFT_TWO_PASS = 0x80
 SFFT_FLAG_VOTE_BY_LOOP = 0x100
 SFFT_FLAG_VOTE_BY_PAIR = 0x200
+SFFT_FLAG_FUSED = 0x400
 
 
 class Params(C.Structure):

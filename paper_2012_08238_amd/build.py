@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsfft_mi355x.so")
-SOURCES = ["fold.hip", "fft.hip", "estimate.hip", "scratch.hip", "plan.cpp", "capi.cpp", "steps.cpp", "batch.cpp",
+SOURCES = ["fold.hip", "fft.hip", "estimate.hip", "fused_lo.hip", "fused_hi.hip", "scratch.hip", "plan.cpp", "capi.cpp", "steps.cpp", "batch.cpp",
            "serve.cpp"]
 ARCH = "gfx950"
 

@@ -272,6 +272,12 @@ static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* 
     for (int part = 0; part < 2; ++part) {
         if (b->exec[part]) continue;
         if (!b->branches.empty() && part == 0) continue;   // one graph holds every branch
+        if (b->branches.empty()) {
+            // no graph for a part without launches (a batch of fused signals has no bucketization launch)
+            bool any = false;
+            for (const Step& st : b->steps) any = any || ((st.kind == kStepFold) == (part == 0));
+            if (!any) continue;
+        }
         e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
         const sfft_status st = b->branches.empty() ? issue_part(b, b->cap_stream, part) : issue_branches(b, b->cap_stream);
@@ -301,8 +307,10 @@ static sfft_status batch_run(sfft_batch_t b, const void* const* x_dev, int64_t* 
         e = hipEventRecord(reinterpret_cast<hipEvent_t>(ev_fold_end), s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    e = hipGraphLaunch(b->exec[1], s);
-    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    if (b->exec[1]) {
+        e = hipGraphLaunch(b->exec[1], s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+    }
     e = hipEventRecord(b->done, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     b->last_stream = s;

@@ -143,6 +143,15 @@ static sfft_status launch_buckets(const Resolved& R, const SigDesc* d_desc, cons
 // Launch every stage for one signal (nsig == 0 form of Launch). d_desc[1] holds
 // the estimation-only loops when the plan has them.
 sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc& io, hipStream_t s) {
+    if (R.fused) {
+        Launch a{};
+        a.descs = d_desc;
+        a.nsig = 0;
+        a.xcd_order = 0;
+        a.one_io = io;
+        HIP_TRY(launch_fused(a, vote_key(R.L), 1, R.fused_lds, s), "fused launch");
+        return SFFT_OK;
+    }
     sfft_status st = launch_buckets(R, d_desc, io, s);
     if (st == SFFT_OK && R.est) st = launch_buckets(*R.est, d_desc + 1, io, s);
     if (st != SFFT_OK) return st;

@@ -130,5 +130,11 @@ constexpr uint32_t kSubNT = 256;
 constexpr uint32_t kDecPerThread = 4;                     // decoded buckets per thread
 constexpr uint32_t kDecUnit = kVoteNT * kDecPerThread;    // decoded buckets per workgroup
 constexpr uint32_t kStripLdsBytes = 65536;  // strip tile budget
+// fused single-launch form (small plans, one workgroup per signal)
+constexpr uint32_t kFusedNT = 256;          // threads of its workgroup
+constexpr uint32_t kFusedMaxK = 1024;       // K it supports (selected entries: 4 per thread)
+constexpr uint32_t kFusedLog2BMin = 5, kFusedLog2BMax = 12;   // B = 32 .. 4096
+constexpr uint32_t kFusedMaxL = 16;
+constexpr uint32_t kFusedMaxGrid = 2048;    // persistent workgroups of one launch (8 per compute unit)
 
 }  // namespace sfft

@@ -47,6 +47,7 @@ struct Resolved {
     uint32_t L_est() const { return est ? est->L : 0u; }
     uint32_t xcd_order;
     uint32_t fold_variant;      // bucketization kernel variant (kernels.hpp fold_variant)
+    uint32_t fused, fused_lds;  // the whole path in one workgroup of one launch; its dynamic LDS bytes
 };
 
 struct HostTables {

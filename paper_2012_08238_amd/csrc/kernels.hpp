@@ -42,6 +42,12 @@ hipError_t launch_reselect(const Launch& a, uint32_t log2B, uint32_t units, hipS
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // the residual's partial sums into the outputs: one workgroup per signal, after launch_residual
 hipError_t launch_residual_sum(const Launch& a, uint32_t units, hipStream_t s);
+// fused single-launch form: one persistent workgroup takes whole signals (units = signals of the
+// launch, each of one unit); key = vote_key(L) <= 16, the same for every signal; lds_bytes =
+// Resolved::fused_lds (max over the launch)
+hipError_t launch_fused(const Launch& a, uint32_t key, uint32_t units, uint32_t lds_bytes, hipStream_t s);
+// LDS bytes of the fused form's transform and selection at B = 2^log2B (0 outside its range)
+uint32_t fused_fft_lds(uint32_t log2B);
 // raises the dynamic-LDS limit of the kernels that use more than 64 KB
 hipError_t set_kernel_attributes_impl();
 hipError_t set_fold_attributes();

@@ -380,6 +380,24 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
     }
     R.xcd_order = (p.flags & SFFT_FLAG_XCD_ORDER) ? 1u : 0u;
     R.fold_variant = fold_variant(R.mode, R.strip_lds, R.L << R.log2C, R.Mw4 / 4);
+    R.fused = 0;
+    R.fused_lds = 0;
+    if (p.flags & SFFT_FLAG_FUSED) {
+        // one workgroup per signal: the transform in its LDS with B/16 <= 256, at most 4 selected
+        // outputs per thread, one vote kernel instance per L, the bitmaps staged in LDS; the
+        // buckets are gathered, and none of the extra rounds or loops
+        const uint32_t extra = SFFT_FLAG_ITERATE | SFFT_FLAG_PHASE_LOCATION | SFFT_FLAG_FFT_TWO_PASS | SFFT_FLAG_FOLD_STRIP;
+        if ((p.flags & extra) || R.comb_loops || R.est || R.log2B < kFusedLog2BMin || R.log2B > kFusedLog2BMax ||
+            R.L > kFusedMaxL || R.K > kFusedMaxK || !R.vote_lds) {
+            *err = "SFFT_FLAG_FUSED needs 32 <= B <= 4096, L <= 16, K <= 1024 and no subtraction round, phase "
+                   "location, two-pass FFT, strip bucketization, comb prefilter or estimation-only loops";
+            return SFFT_E_UNSUPPORTED;
+        }
+        R.fused = 1;
+        R.mode = 0;
+        R.fold_variant = fold_variant(0u, 0u, 0u, 0u);
+        R.fused_lds = std::max({fused_fft_lds(R.log2B), R.vote_dyn_lds, R.fin_lds, R.S ? R.resid_lds : 0u});
+    }
     *out = std::move(R);
     return SFFT_OK;
 }

@@ -19,20 +19,21 @@ size_t max_prefix_entries(size_t n) {
     // fold: at most one launch per distinct variant (<= n); fft: kFftLog2Max;
     // two-pass fft: 3 per size; comb prefilter: one per comb size (2^1 .. 2^14);
     // per round: vote 2 x kVoteKeys, phase decode 1, estimate kLmaxCount, top-K 1;
-    // subtraction 1, reselection kFftLog2Max; residual and its sum 2
+    // subtraction 1, reselection kFftLog2Max; residual and its sum 2; fused: one per L
     const size_t launches = n + kFftLog2Max + 3 * (kLargeLog2Max - kLargeLog2Min + 1) + kFftLog2Max +
-                            2 * (2 * kVoteKeys + kLmaxCount + 2) + 1 + kFftLog2Max + 2;
+                            2 * (2 * kVoteKeys + kLmaxCount + 2) + 1 + kFftLog2Max + 2 + kFusedMaxL;
     return launches * (n + 1);
 }
 
 void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* steps, std::vector<uint32_t>* prefix) {
     const size_t n = sig.size();
+    // a fused signal takes part in its fused launch only, every other signal in the others
     auto add_step = [&](StepKind kind, uint32_t param, uint32_t lds, auto units_of) {
         const size_t off = prefix->size();
         uint32_t acc = 0;
         prefix->push_back(0);
         for (size_t i = 0; i < n; ++i) {
-            acc += units_of(*sig[i]);
+            if ((kind == kStepFused) == (sig[i]->fused != 0)) acc += units_of(*sig[i]);
             prefix->push_back(acc);
         }
         if (acc == 0) {
@@ -47,8 +48,14 @@ void plan_steps(const std::vector<const Resolved*>& sig, std::vector<Step>* step
             if (pred(*sig[i])) v = std::max(v, field(*sig[i]));
         return v;
     };
+    for (uint32_t l = 1; l <= kFusedMaxL; ++l) {
+        auto in_group = [&](const Resolved& R) { return R.fused && R.L == l; };
+        add_step(kStepFused, l, max_of(in_group, [](const Resolved& R) { return R.fused_lds; }),
+                 [&](const Resolved& R) { return in_group(R) ? 1u : 0u; });
+    }
     std::set<uint32_t> variants;
-    for (size_t i = 0; i < n; ++i) variants.insert(sig[i]->fold_variant);
+    for (size_t i = 0; i < n; ++i)
+        if (!sig[i]->fused) variants.insert(sig[i]->fold_variant);
     for (const uint32_t v : variants) {
         const uint32_t lds = max_of([&](const Resolved& R) { return R.fold_variant == v && R.mode == 1; },
                                     [](const Resolved& R) { return R.strip_lds; });
@@ -122,6 +129,7 @@ hipError_t issue_steps(const std::vector<Step>& steps, const SigDesc* d_descs, c
             case kStepResSum: e = launch_residual_sum(a, st.units, s); break;
             case kStepFftLarge: e = launch_fft_large(a, st.param & 255u, st.param >> 8, st.units, s); break;
             case kStepComb: e = launch_comb(a, st.param, st.units, s); break;
+            case kStepFused: e = launch_fused(a, vote_key(st.param), st.units, st.lds, s); break;
         }
         if (e != hipSuccess) return e;
     }

@@ -14,13 +14,14 @@ namespace sfft {
 
 enum StepKind : uint32_t {
     kStepFold = 0, kStepFft = 1, kStepVote = 2, kStepFin = 3, kStepRes = 4, kStepFftLarge = 5, kStepComb = 6,
-    kStepSub = 7, kStepReselect = 8, kStepEst = 9, kStepDecode = 10, kStepResSum = 11
+    kStepSub = 7, kStepReselect = 8, kStepEst = 9, kStepDecode = 10, kStepResSum = 11, kStepFused = 12
 };
 
 struct Step {
     StepKind kind;
     uint32_t param;       // fold variant / log2B / (staged | lmax << 8 | round << 16) / round /
-                          // 0 / (log2B | pass << 8) / log2Bc / 0 / log2B / (lmax | round << 8) / round
+                          // 0 / (log2B | pass << 8) / log2Bc / 0 / log2B / (lmax | round << 8) / round /
+                          // 0 / L (fused)
     uint32_t units;       // workgroups of the launch
     uint32_t lds;         // dynamic LDS bytes
     size_t prefix_off;    // offset (in entries) of this launch's prefix of n+1 entries

@@ -162,6 +162,26 @@ def test_vote_mode_choice_and_validation():
     assert desc(L=4, flags=S.SFFT_FLAG_PHASE_LOCATION)["vote_pairs"] == 0
 
 
+def test_fused_validation():
+    def desc(**kw):
+        base = dict(N=1 << 16, K=20, B=512, L=7, w=4096, flags=S.SFFT_FLAG_FUSED)
+        base.update(kw)
+        return S.params_describe(S.PlanParams(**base))
+    # the fused form gathers its buckets, whatever the per-stage path would choose
+    assert desc()["fold_mode"] == 0   # 0 gather, 1 strip
+    assert S.params_describe(S.PlanParams(N=1 << 16, K=20, B=512, L=7, w=4096))["fold_mode"] == 1
+    assert desc(N=1 << 20, K=1000, B=4096, L=5, w=32768)["K"] == 1000
+    for kw in (dict(K=4, B=16, w=128), dict(N=1 << 20, B=8192, w=65536), dict(L=17), dict(N=1 << 20, K=1025, B=4096),
+               dict(flags=S.SFFT_FLAG_FUSED | S.SFFT_FLAG_ITERATE),
+               dict(L=4, flags=S.SFFT_FLAG_FUSED | S.SFFT_FLAG_PHASE_LOCATION),
+               dict(flags=S.SFFT_FLAG_FUSED | S.SFFT_FLAG_FOLD_STRIP),
+               dict(flags=S.SFFT_FLAG_FUSED | S.SFFT_FLAG_FFT_TWO_PASS, B=4096, N=1 << 18, w=32768),
+               dict(comb_b=256, comb_loops=2), dict(est_loops=2, est_B=2048)):
+        with pytest.raises(S.SfftError) as e:
+            desc(**kw)
+        assert e.value.status == _capi.SFFT_E_UNSUPPORTED, kw
+
+
 def test_iterate_validation_and_gain():
     # the subtraction round runs with the one-workgroup FFT only
     with pytest.raises(S.SfftError) as e:
