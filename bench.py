@@ -17,7 +17,8 @@ Also reported: the bucketization kernel's roofline against MI355X HBM peak
 Table 2 with log N -> L), beside its line-granular bound (the 128-byte lines
 holding a sample) and its measured traffic; p50/p99 latency through the serving
 loop under Poisson arrivals and its saturated throughput; the plain single-signal
-path's throughput; single-request latency; FP32-vs-FP64 parity on a sample; and
+path's throughput; single-request latency; FP32-vs-FP64 parity on a sample; the
+one-launch fused form against the graph of stage launches on small plans; and
 the FP64 CPU oracle timed on the host (one core, and a pool over every core).
 """
 from __future__ import annotations
@@ -489,6 +490,59 @@ def k_sweep_measure(S, torch, dev, args) -> dict:
     return out
 
 
+def fused_measure(S, torch, dev, args) -> dict:
+    """The one-launch form (SFFT_FLAG_FUSED: one workgroup per signal, every stage in
+    it) against the graph of batched stage launches, on small plans (the batch's
+    small signals): device time of one replay of a batch of n signals (HIP events,
+    median of five after two warm replays) and single-signal latency (sfft_execute +
+    stream sync, p50 of 30). Both forms give bitwise the same results (GPU test)."""
+    import numpy as np
+    from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
+    sizes = [int(v) for v in args.fused_batches.split(",") if v]
+    out = {"batches": sizes, "shapes": []}
+    for (ln, k, b, l, wb) in ((14, 10, 128, 5, 4), (16, 20, 512, 5, 8), (16, 50, 1024, 7, 8), (18, 100, 4096, 9, 8)):
+        n = 1 << ln
+        xs = [make_signal_torch(n, k, SNR_DB, derive_seed(170 + ln, i), dev)[0] for i in range(8)]
+        row = {"N": n, "K": k, "B": b, "L": l, "w": wb * b}
+        for name, fl in (("graph", 0), ("fused", S.SFFT_FLAG_FUSED)):
+            plan = S.Plan(n, k, b, l, wb * b, seed=31, flags=fl)
+            idx, val, res = plan.outputs(dev)
+            for _ in range(3):
+                plan.execute(xs[0], idx, val, res)
+            torch.cuda.synchronize()
+            lat = []
+            for i in range(30):
+                t0 = time.perf_counter()
+                plan.execute(xs[i % 8], idx, val, res)
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - t0)
+            r = {"single_p50_us": round(percentile(lat, 0.5) * 1e6, 1)}
+            for m in sizes:
+                bx = [xs[j % 8] for j in range(m)]
+                outs = [plan.outputs(dev) for _ in range(m)]
+                cols = ([o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+                bt = S.Batch([plan] * m)
+                for _ in range(2):
+                    bt.run(bx, *cols)
+                ts = []
+                for _ in range(5):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    bt.run(bx, *cols)
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e3)
+                bt.close()
+                us = float(np.median(ts))
+                r[f"batch{m}_us"] = round(us, 1)
+                r[f"batch{m}_signals_per_s"] = round(m / (us * 1e-6))
+            row[name] = r
+            plan.close()
+        out["shapes"].append(row)
+        print(f"# fused vs graph {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def serve_mix_measure(S, torch, dev, args) -> dict:
     """Serving mixed requests: a pool of --mix-pool signals resident in HBM with
     N = 2^18..2^24, K = 20..1000, SNR 0..30 dB and one parameter set each (the
@@ -673,6 +727,8 @@ def main() -> int:
     ap.add_argument("--est-steps", type=int, default=10)
     ap.add_argument("--ksweep-batch", type=int, default=16, help="signals per batch of the K sweep (0 = skip)")
     ap.add_argument("--ksweep-steps", type=int, default=5)
+    ap.add_argument("--fused-batches", default="16,256,1024",
+                    help="batch sizes of the fused-launch vs graph comparison on small plans (empty = skip)")
     ap.add_argument("--no-context", action="store_true", help="skip the copy-bandwidth and dense-FFT context")
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=60)
@@ -814,6 +870,7 @@ def main() -> int:
     phase = phase_measure(S, torch, dev, args) if args.phase_batch > 0 else None
     est_loops = est_loops_measure(S, torch, dev, args) if args.est_batch > 0 else None
     ksweep = k_sweep_measure(S, torch, dev, args) if args.ksweep_batch > 0 else None
+    fused = fused_measure(S, torch, dev, args) if args.fused_batches else None
     context = None
     if not args.no_context:
         context = dense_fft_context(torch, dev, xs)
@@ -920,6 +977,7 @@ def main() -> int:
         "phase_location": phase,
         "estimation_loops": est_loops,
         "k_sweep_c3": ksweep,
+        "fused_vs_graph_small": fused,
         "context": context,
         "roofline": roofline,
         "cpu_baseline": cpu,
