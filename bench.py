@@ -493,9 +493,10 @@ def k_sweep_measure(S, torch, dev, args) -> dict:
 def fused_measure(S, torch, dev, args) -> dict:
     """The one-launch form (SFFT_FLAG_FUSED: one workgroup per signal, every stage in
     it) against the graph of batched stage launches, on small plans (the batch's
-    small signals): device time of one replay of a batch of n signals (HIP events,
-    median of five after two warm replays) and single-signal latency (sfft_execute +
-    stream sync, p50 of 30). Both forms give bitwise the same results (GPU test)."""
+    small signals): time per replay of a batch of n signals, ten replays back to back
+    between HIP events (median of three such runs after two warm replays), and
+    single-signal latency (sfft_execute + stream sync, p50 of 30). Both forms give
+    bitwise the same results (GPU test)."""
     import numpy as np
     from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
     sizes = [int(v) for v in args.fused_batches.split(",") if v]
@@ -525,13 +526,14 @@ def fused_measure(S, torch, dev, args) -> dict:
                 for _ in range(2):
                     bt.run(bx, *cols)
                 ts = []
-                for _ in range(5):
+                for _ in range(3):
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record()
-                    bt.run(bx, *cols)
+                    for _ in range(10):
+                        bt.run(bx, *cols)
                     e1.record()
                     e1.synchronize()
-                    ts.append(e0.elapsed_time(e1) * 1e3)
+                    ts.append(e0.elapsed_time(e1) * 1e3 / 10)
                 bt.close()
                 us = float(np.median(ts))
                 r[f"batch{m}_us"] = round(us, 1)
