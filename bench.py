@@ -523,14 +523,15 @@ def fused_measure(S, torch, dev, args) -> dict:
                 outs = [plan.outputs(dev) for _ in range(m)]
                 cols = ([o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
                 bt = S.Batch([plan] * m)
+                bt.bind(bx, *cols)   # pointers marshalled once: the replays are not held up by the host
                 for _ in range(2):
-                    bt.run(bx, *cols)
+                    bt.run_bound()
                 ts = []
                 for _ in range(3):
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record()
                     for _ in range(10):
-                        bt.run(bx, *cols)
+                        bt.run_bound()
                     e1.record()
                     e1.synchronize()
                     ts.append(e0.elapsed_time(e1) * 1e3 / 10)
@@ -648,9 +649,12 @@ def uneven_measure(S, torch, dev, args) -> dict:
     outs = outsets[0]
     setup = time.perf_counter() - t0
 
-    def run(j):
+    for j in range(nf):   # resident buffers: their pointers are marshalled once
         o = outsets[j]
-        bs[j].run(xsets[j], [q[0] for q in o], [q[1] for q in o], [q[2] for q in o], stream=streams[j])
+        bs[j].bind(xsets[j], [q[0] for q in o], [q[1] for q in o], [q[2] for q in o])
+
+    def run(j):
+        bs[j].run_bound(stream=streams[j])
     for _ in range(2):
         for j in range(nf):
             run(j)
@@ -791,9 +795,11 @@ def main() -> int:
         orr = torch.empty((M, 2), dtype=torch.float64, device=dev)
         outsets.append(([oi[i] for i in range(M)], [ov[i] for i in range(M)], [orr[i] for i in range(M)]))
         streams.append(torch.cuda.Stream(device=dev))
+    for j in range(nf):   # resident buffers: their pointers are marshalled once
+        batches[j].bind(xsets[j], *outsets[j])
     for _ in range(args.warmup):
         for j in range(nf):
-            batches[j].run(xsets[j], *outsets[j], stream=streams[j])
+            batches[j].run_bound(stream=streams[j])
     torch.cuda.synchronize()
     from paper_2012_08238_amd._hip import HipEvent
     ev = [(HipEvent(), HipEvent()) for _ in range(args.steps)]
@@ -804,7 +810,7 @@ def main() -> int:
             batch.run_timed(xs, idxs, vals, ress, ev[k][0], ev[k][1])
         else:
             j = k % nf
-            batches[j].run(xsets[j], *outsets[j], stream=streams[j])
+            batches[j].run_bound(stream=streams[j])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0

@@ -251,6 +251,21 @@ class Batch:
         ra = _ptr_array([_ptr(r) for r in resids]) if resids is not None else None
         check(load().sfft_batch_run(self._h, xa, ia, va, ra, _stream_handle(stream)), "sfft_batch_run")
 
+    def bind(self, xs, idxs, vals, resids=None) -> None:
+        """Marshal the buffers' device pointers once for run_bound (which then skips the
+        per-call pointer arrays); the tensors are kept alive while bound."""
+        n = len(self.plans)
+        if not (len(xs) == len(idxs) == len(vals) == n):
+            raise ValueError("one x, idx and val per plan")
+        arrays = tuple(_ptr_array([_ptr(t) for t in ts]) if ts is not None else None
+                       for ts in (xs, idxs, vals, resids))
+        self._bound = (arrays, (list(xs), list(idxs), list(vals), list(resids) if resids is not None else None))
+
+    def run_bound(self, stream=None) -> None:
+        """run() on the buffers given to bind()."""
+        xa, ia, va, ra = self._bound[0]
+        check(load().sfft_batch_run(self._h, xa, ia, va, ra, _stream_handle(stream)), "sfft_batch_run")
+
     def run_timed(self, xs, idxs, vals, resids, ev_begin, ev_end, stream=None) -> None:
         """As run(); records HipEvent ev_begin / ev_end around the bucketization."""
         xa = _ptr_array([_ptr(x) for x in xs])
@@ -264,6 +279,7 @@ class Batch:
         if getattr(self, "_h", None):
             check(load().sfft_batch_destroy(self._h), "sfft_batch_destroy")
             self._h = None
+        self._bound = None
 
     def __del__(self):
         try:

@@ -344,8 +344,11 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         R.fft_p1_units = R.L * ((1u << lb2) / 16u);
         R.fft_p2_units = R.L * ((1u << lb1) / 16u);
     }
-    // residual: a wave's lanes are (run, output subset) pairs, 2^resid_log2kl subsets per run
-    R.resid_log2kl = R.K >= 512 ? 4u : 3u;
+    // residual: a wave's lanes are (run, output subset) pairs, 2^resid_log2kl subsets per run:
+    // 8 (16 from K = 512) for many outputs; below K = 64 about 16 outputs per lane, so that a
+    // small plan's residual takes a few workgroups per signal instead of 16 (each workgroup
+    // stages the outputs and their phase steps once)
+    R.resid_log2kl = R.K >= 512 ? 4u : (R.K > 64 ? 3u : (ilog2(R.K) > 4u ? ilog2(R.K) - 4u : 0u));
     {
         const uint32_t runs = (R.S + kResRun - 1) / kResRun;
         const uint32_t runs_per_wg = (kResNT / 64u) * (64u >> R.resid_log2kl);
