@@ -170,9 +170,11 @@ def serve_measure(S, torch, dev, xs, truth, args) -> dict:
     open_stats = srv.stats()
     ok = sum(set(idx[i].tolist()) == set(truth[i % M][0].tolist()) for i in range(min(n, 256)))
     # saturated: queue nb requests at once, time until the last completes
+    burst = ([xs[i % M] for i in range(nb)], [idx[i] for i in range(nb)], [val[i] for i in range(nb)],
+             [res[i] for i in range(nb)])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tickets = [srv.submit(h, xs[i % M], idx[i], val[i], res[i]) for i in range(nb)]
+    tickets = srv.submit_many(h, *burst)   # one call: the burst is admitted at once
     for t in tickets:
         srv.wait(t)
     t_sat = time.perf_counter() - t1

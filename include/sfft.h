@@ -348,6 +348,17 @@ sfft_status sfft_server_prepare(sfft_server_t s, const sfft_params* p);
 sfft_status sfft_server_submit(sfft_server_t s, const sfft_params* p, const void* x_dev,
                                int64_t* out_idx, void* out_val, double* out_resid, uint64_t* ticket);
 
+/* Queue n requests of one parameter set at once (a burst: one admission pass and one
+ * wake-up of the worker instead of n). Request i reads x_dev[i] and writes out_idx[i],
+ * out_val[i] and out_resid[i] (out_resid may be NULL, or hold NULL entries) under the
+ * rules of sfft_server_submit; tickets[i] receives its ticket, in submission order. All
+ * or none: a bad pointer in any request gives SFFT_E_INVALID, a parameter set that can
+ * never fit SFFT_E_NOMEM, and then no request is queued. n = 0 queues nothing. Thread
+ * safe. */
+sfft_status sfft_server_submit_batch(sfft_server_t s, const sfft_params* p, int32_t n, const void* const* x_dev,
+                                     int64_t* const* out_idx, void* const* out_val, double* const* out_resid,
+                                     uint64_t* tickets);
+
 /* Non-blocking status of a ticket: *done = 1 once its outputs are complete on
  * the device; then *latency_s = completion - submission time and *req_status
  * the request's own status (SFFT_OK or SFFT_E_DEVICE). Unknown or released

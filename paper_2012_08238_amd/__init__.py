@@ -312,6 +312,22 @@ class Server:
         del keep
         return t.value
 
+    def submit_many(self, params, xs, idxs, vals, resids=None) -> list:
+        """Queue one request per signal of `xs` with one parameter set (all or none);
+        returns their tickets in order."""
+        p, keep = params if isinstance(params, tuple) else params.to_c()
+        n = len(xs)
+        if not (len(idxs) == len(vals) == n) or (resids is not None and len(resids) != n):
+            raise ValueError("one x, idx and val (and resid) per request")
+        t = (C.c_uint64 * max(n, 1))()
+        xa = _ptr_array([_ptr(x) for x in xs])
+        ia = _ptr_array([_ptr(i) for i in idxs])
+        va = _ptr_array([_ptr(v) for v in vals])
+        ra = _ptr_array([_ptr(r) for r in resids]) if resids is not None else None
+        check(load().sfft_server_submit_batch(self._h, C.byref(p), n, xa, ia, va, ra, t), "sfft_server_submit_batch")
+        del keep
+        return list(t[:n])
+
     def poll(self, ticket: int):
         done, lat, st = C.c_int32(), C.c_double(), C.c_int32()
         check(load().sfft_server_poll(self._h, ticket, C.byref(done), C.byref(lat), C.byref(st)),

@@ -93,6 +93,9 @@ SIGNATURES = [
     ("sfft_server_prepare", C.c_int, [C.c_void_p, C.POINTER(Params)]),
     ("sfft_server_submit", C.c_int, [C.c_void_p, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("sfft_server_submit_batch", C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_uint64)]),
     ("sfft_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                    C.POINTER(C.c_int32)]),
     ("sfft_server_wait", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),

@@ -322,6 +322,37 @@ sfft_status sfft_server_submit(sfft_server_t s, const sfft_params* p, const void
     return core_status(s->core->submit(id, ws, io, ticket));
 }
 
+sfft_status sfft_server_submit_batch(sfft_server_t s, const sfft_params* p, int32_t n, const void* const* x_dev,
+                                     int64_t* const* out_idx, void* const* out_val, double* const* out_resid,
+                                     uint64_t* tickets) {
+    if (!s || !p || n < 0 || (n > 0 && (!x_dev || !out_idx || !out_val || !tickets))) {
+        if (s) s->invalid += n > 0 ? (uint64_t)n : 1u;
+        return set_error(SFFT_E_INVALID, "null argument or n < 0");
+    }
+    std::vector<IoDesc> io((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        double* res = out_resid ? out_resid[i] : nullptr;
+        if (!x_dev[i] || !out_idx[i] || !out_val[i] || (reinterpret_cast<uintptr_t>(x_dev[i]) & 15u) ||
+            (reinterpret_cast<uintptr_t>(out_idx[i]) & 7u) || (reinterpret_cast<uintptr_t>(out_val[i]) & 7u) ||
+            (reinterpret_cast<uintptr_t>(res) & 7u)) {
+            s->invalid += (uint64_t)n;
+            return set_error(SFFT_E_INVALID, "request " + std::to_string(i) +
+                                                 ": null pointer, or x_dev not 16-byte / outputs not 8-byte aligned");
+        }
+        io[i] = IoDesc{reinterpret_cast<const float2*>(x_dev[i]), out_idx[i], reinterpret_cast<float2*>(out_val[i]),
+                       res};
+    }
+    if (n == 0) return SFFT_OK;
+    uint32_t id;
+    size_t ws;
+    const sfft_status st = served_plan(s, *p, &id, &ws);
+    if (st != SFFT_OK) {
+        s->invalid += (uint64_t)n;
+        return st;
+    }
+    return core_status(s->core->submit_many(id, ws, io.data(), io.size(), tickets));
+}
+
 sfft_status sfft_server_poll(sfft_server_t s, uint64_t ticket, int32_t* done, double* latency_s, int32_t* req_status) {
     if (!s) return set_error(SFFT_E_INVALID, "null server");
     int d = 0, rs = 0;

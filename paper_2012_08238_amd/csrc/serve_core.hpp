@@ -164,6 +164,35 @@ public:
         return kCoreOk;
     }
 
+    // Queue n requests of one plan under one lock (one wake-up of the worker), in order;
+    // all or none: kCoreNoMem / kCoreNotFound as submit, with no ticket issued.
+    int submit_many(uint32_t plan, size_t ws_bytes, const Payload* io, size_t n, uint64_t* tickets) {
+        const double t0 = now();
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = plans_.find(plan);
+        if (it == plans_.end()) {
+            st_.rejected += n;
+            return kCoreNotFound;
+        }
+        if (arena_.round_up(it->second.tab_bytes) + arena_.round_up(ws_bytes) > arena_.capacity()) {
+            st_.rejected += n;
+            return kCoreNoMem;
+        }
+        for (size_t i = 0; i < n; ++i) {
+            const uint64_t t = next_ticket_++;
+            Req& r = reqs_[t];
+            r.plan = plan;
+            r.ws_bytes = ws_bytes;
+            r.io = io[i];
+            r.t_submit = t0;
+            queue_.push_back(t);
+            tickets[i] = t;
+        }
+        st_.submitted += n;
+        if (n) cv_work_.notify_one();
+        return kCoreOk;
+    }
+
     int poll(uint64_t ticket, int* done, double* latency, int* status) {
         std::lock_guard<std::mutex> lk(mu_);
         auto it = reqs_.find(ticket);

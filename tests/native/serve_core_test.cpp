@@ -370,8 +370,35 @@ static void test_drain_on_stop() {
     delete core;
 }
 
+static void test_submit_many() {
+    Env e;
+    e.tab = {{1, 512}};
+    e.ws = {{1, 2048}};
+    const size_t arena = 1 << 16;
+    FakeExec ex(2, arena, e.tab, e.ws, 500, 1);
+    ServerCore<Io> core(&ex, arena, 16, 2, 16);
+    core.add_plan(1, 512);
+    std::vector<Io> io(40, Io{0, 1});
+    std::vector<uint64_t> t(40, 0);
+    // all or none: an unknown plan or one that can never fit queues nothing
+    CHECK(core.submit_many(7, 2048, io.data(), io.size(), t.data()) == kCoreNotFound);
+    CHECK(core.submit_many(1, arena, io.data(), io.size(), t.data()) == kCoreNoMem);
+    CHECK(core.stats().submitted == 0);
+    CHECK(core.submit_many(1, 2048, io.data(), 0, t.data()) == kCoreOk);
+    CHECK(core.submit_many(1, 2048, io.data(), io.size(), t.data()) == kCoreOk);
+    for (size_t i = 1; i < t.size(); ++i) CHECK(t[i] == t[i - 1] + 1);   // tickets in submission order
+    for (uint64_t x : t) {
+        int st = 1;
+        CHECK(core.wait(x, nullptr, &st) == kCoreOk && st == 0);
+    }
+    const CoreStats s = core.stats();
+    CHECK(s.completed == 40 && s.submitted == 40 && s.rejected == 80);
+    CHECK(ex.max_inflight_seen <= 16 && s.peak <= arena);
+}
+
 int main() {
     test_allocator();
+    test_submit_many();
     test_batching_and_overlap();
     test_budget_and_eviction();
     test_inflight_limit_and_failure();

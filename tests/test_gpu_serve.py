@@ -222,3 +222,35 @@ def test_serve_errors(dev):
     s = srv.stats()
     assert s["rejected"] == 2 and s["submitted"] == 0
     srv.close()
+
+
+def test_serve_submit_many(dev):
+    """A burst queued in one call: results bitwise those of each request alone, tickets in
+    order, waves of several requests; all or none on a bad pointer."""
+    import torch
+    import paper_2012_08238_amd as S
+    cfg = MIX[1]
+    n = 48
+    xs = _signals(dev, [cfg] * n, 1200)
+    refs = _alone(S, dev, [cfg] * n, xs)
+    srv = S.Server(hbm_budget_bytes=1 << 30, max_inflight=32, n_streams=2)
+    outs = [_outputs(dev, cfg) for _ in range(n)]
+    torch.cuda.synchronize()
+    params = _params(S, cfg)
+    ts = srv.submit_many(params, xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+    assert len(set(ts)) == n and ts == sorted(ts)
+    for t in ts:
+        _, st = srv.wait(t)
+        assert st == 0
+    for o, r in zip(outs, refs):
+        _same(o, r, cfg)
+    s = srv.stats()
+    assert s["submitted"] == n and s["completed"] == n and s["max_batch"] > 1
+    bad = list(xs[:4])
+    bad[2] = xs[2][1:]   # 8 bytes off the 16-byte alignment
+    with pytest.raises(S.SfftError) as e:
+        srv.submit_many(params, bad, [o[0] for o in outs[:4]], [o[1] for o in outs[:4]])
+    assert e.value.status == -1
+    assert srv.stats()["submitted"] == n      # nothing of the refused burst was queued
+    assert srv.submit_many(params, [], [], []) == []
+    srv.close()
