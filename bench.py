@@ -645,7 +645,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
     nf = max(1, args.uneven_inflight)
     # each step in flight reads its own copy of the signals (as in the main step)
     xsets = [xs] + [[x.clone() for x in xs] for _ in range(nf - 1)]
-    bs = [S.Batch(plans, branches=args.section_branches) for _ in range(nf)]
+    bs = [S.Batch(plans, branches=args.uneven_branches) for _ in range(nf)]
     outsets = [[p.outputs(dev) for p in plans] for _ in range(nf)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev) for _ in range(nf - 1)]
     outs = outsets[0]
@@ -682,6 +682,7 @@ def uneven_measure(S, torch, dev, args) -> dict:
         p.close()
     del xsets[1:]
     return {"signals": len(specs), "resident_bytes": nbytes, "steps": args.uneven_steps, "steps_in_flight": nf,
+            "graph_branches": args.uneven_branches,
             "ms_per_step": round(el / args.uneven_steps * 1e3, 4),
             "signals_per_s": round(len(specs) * args.uneven_steps / el, 1),
             "single_signal_path_signals_per_s": round(single, 1),
@@ -741,6 +742,8 @@ def main() -> int:
     ap.add_argument("--uneven", type=int, default=256, help="signals of the uneven batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=60)
     ap.add_argument("--uneven-inflight", type=int, default=2, help="steps in flight of the uneven batch")
+    ap.add_argument("--uneven-branches", type=int, default=2,
+                    help="graph branches of the uneven batch (measured: 2 -> 257k, 4 -> 242k signals/s)")
     ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2012_08238_amd", "tuned", "mi355x_uneven.json"),
                     help="autotuner JSON table for the uneven batch ('' = the untuned rule; missing classes are tuned)")
     args = ap.parse_args()
