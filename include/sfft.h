@@ -326,7 +326,7 @@ typedef struct {
  * admitted or running; idle resident tables are evicted least recently used
  * first when space is short. Whenever one of the n_streams streams is free,
  * every admitted request leaves as one wave: a batched launch sequence (as
- * sfft_batch_run) on that stream. Requests that arrive while waves run are
+ * sfft_batch_run; a lone request, the sequence of sfft_execute_ex) on that stream. Requests that arrive while waves run are
  * batched into the next wave, and waves on different streams overlap on the
  * device. Each request's result is bitwise the one sfft_execute_ex gives for
  * its parameter set alone. Plans are cached by parameter set (host tables kept

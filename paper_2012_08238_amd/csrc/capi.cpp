@@ -177,10 +177,7 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
         HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 1, s), "second estimate launch");
         HIP_TRY(launch_finalize(a, 1, R.fin_lds, 1, s), "second top-K launch");
     }
-    if (R.S) {
-        HIP_TRY(launch_residual(a, R.resid_blocks, R.resid_lds, s), "residual launch");
-        HIP_TRY(launch_residual_sum(a, 1, s), "residual sum launch");
-    }
+    if (R.S) HIP_TRY(launch_residual_one(a, R.resid_blocks, R.resid_lds, s), "residual launch");
     return SFFT_OK;
 }
 

@@ -42,7 +42,8 @@ struct SigDesc {
     uint64_t* keys;             // [cap (+ K with iteration)] ordering keys of the estimates
     double* rpart;              // [2 * resid_blocks] residual partial sums
     double* resid_own;          // [2] residual when the caller gives no buffer
-    uint32_t* ctr;              // [4] counters: 0 candidates, 2 first-round outputs
+    uint32_t* ctr;              // [4] counters: 0 candidates, 2 first-round outputs, 3 residual workgroups
+                                // done (single-signal residual); 0 and 3 cleared by the bucketization
     float2* ubuf;               // [L][B] two-pass FFT intermediate (B > kMaxFftLds only)
     uint32_t* cbits;            // [comb_loops][max(1, Bc/32)] residues kept by each comb loop
     uint32_t* gmax;             // [L][B/16] largest energy of each 16 consecutive DFT outputs (idem)

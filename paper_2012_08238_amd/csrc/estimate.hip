@@ -218,6 +218,31 @@ __global__ __launch_bounds__(kResNT) void residual_sum_kernel(Launch a) {
     residual_sum_body(a, sig);
 }
 
+// Single-signal form of the residual in one launch: residual_kernel's workgroups, and the one
+// that finishes last (counted in ctr[3], which the bucketization cleared) reduces the partial
+// sums as residual_sum_kernel does, in the same fixed order. The partials cross workgroups on
+// different dies: each workgroup's partials are written back to memory (device-scope release)
+// before it is counted, and the last one drops stale cached copies (device-scope acquire)
+// before it reads them. Batches keep the two launches: there the step is bound by the
+// bucketization, and a device-scope release per workgroup would write back each die's L2
+// beside it.
+__global__ __launch_bounds__(kResNT) void residual_one_kernel(Launch a) {
+    __shared__ uint32_t s_last;
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    residual_body(a, sig, unit);
+    const auto& d = desc_of(a, sig);
+    if (threadIdx.x == 0) {   // the thread that wrote this workgroup's partials
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        s_last = atomicAdd(d.ctr + 3, 1u) == d.resid_blocks - 1u ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last) {   // block-uniform
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        residual_sum_body(a, sig);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 template <int VL>
 hipError_t launch_vote_vl(const Launch& a, uint32_t units, uint32_t lds_bytes, uint32_t staged, uint32_t round,
@@ -296,11 +321,19 @@ hipError_t set_estimate_attributes() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kMaxK * 28);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_one_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxK * 28);
     return e;
 }
 
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {
     hipLaunchKernelGGL(residual_kernel, dim3(units), dim3(kResNT), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_one(const Launch& a, uint32_t units, uint32_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(residual_one_kernel, dim3(units), dim3(kResNT), lds, s, a);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_strip_kernel(Launch a) {
     const float2* x = io_of(a, sig).x;
     if (unit == 0 && threadIdx.x == 0) {
         gst(d.ctr + 0, 0u);
+        gst(d.ctr + 3, 0u);   // residual workgroups done (single-signal residual)
     }
     const uint32_t log2C = d.log2C, C = 1u << log2C, R = d.M, B = d.B, log2B = d.log2B;
     const uint32_t col0 = unit << log2C;
@@ -100,6 +101,7 @@ __global__ __launch_bounds__(NT) void fold_strip_pf_kernel(Launch a) {
     const float2* x = io_of(a, sig).x;
     if (unit == 0 && threadIdx.x == 0) {
         gst(d.ctr + 0, 0u);
+        gst(d.ctr + 3, 0u);   // residual workgroups done (single-signal residual)
     }
     const uint32_t log2C = d.log2C, C = 1u << log2C, R = d.M, B = d.B, log2B = d.log2B;
     const uint32_t col0 = unit << log2C;
@@ -218,6 +220,7 @@ __global__ __launch_bounds__(kFoldNT) void fold_gather_kernel(Launch a) {
     const float2* x = io_of(a, sig).x;
     if (unit == 0 && threadIdx.x == 0) {
         gst(d.ctr + 0, 0u);
+        gst(d.ctr + 3, 0u);   // residual workgroups done (single-signal residual)
     }
     const uint32_t log2B = d.log2B, B = d.B;
     const uint32_t it = unit * kFoldNT + threadIdx.x;

@@ -40,6 +40,9 @@ hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds_bytes, 
 // selection of the residual buckets: one workgroup per (signal, loop); every signal has B = 2^log2B <= 16384
 hipError_t launch_reselect(const Launch& a, uint32_t log2B, uint32_t units, hipStream_t s);
 hipError_t launch_residual(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
+// one signal (nsig == 0): the residual and the sum of its partials in one launch (ctr[3] counts
+// the finished workgroups; the bucketization clears it)
+hipError_t launch_residual_one(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // the residual's partial sums into the outputs: one workgroup per signal, after launch_residual
 hipError_t launch_residual_sum(const Launch& a, uint32_t units, hipStream_t s);
 // fused single-launch form: one persistent workgroup takes whole signals (units = signals of the

@@ -106,10 +106,16 @@ public:
         if (total > stage_bytes_) return SFFT_E_INVALID;
         memcpy(sl.h_stage + o_pre, prefix.data(), prefix.size() * 4);
         hipError_t e = hipMemcpyAsync(sl.d_stage, sl.h_stage, total, hipMemcpyHostToDevice, sl.stream);
-        if (e == hipSuccess)
+        if (e == hipSuccess && nreq == 1) {
+            // a lone request takes the single-signal launch sequence (as sfft_execute_ex; its
+            // residual is one launch instead of two)
+            if (launch_single(*sig[0], reinterpret_cast<const SigDesc*>(sl.d_stage), items[0].io, sl.stream) != SFFT_OK)
+                e = hipErrorLaunchFailure;
+        } else if (e == hipSuccess) {
             e = issue_steps(steps, reinterpret_cast<const SigDesc*>(sl.d_stage),
                             reinterpret_cast<const IoDesc*>(sl.d_stage + o_io),
                             reinterpret_cast<const uint32_t*>(sl.d_stage + o_pre), (uint32_t)n, xcd, -1, sl.stream);
+        }
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
         if (e != hipSuccess) {
             // the staging buffer is reused by the slot's next wave: let this one drain first
