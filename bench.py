@@ -452,30 +452,38 @@ def dense_fft_context(torch, dev, xs) -> dict:
 def k_sweep_measure(S, torch, dev, args) -> dict:
     """The C3 sweep: N=2^22, SNR 20 dB, L=9, w=8B, K in {50, 100, 200, 500, 1000}
     with B = 2^round(log2 sqrt(N K)) (16384, 16384, 32768, 32768, 65536); batches of
-    resident signals: signals/s, tones missed per signal, median value error
-    against the planted tones (the FP32-vs-FP64 parity of these shapes is a GPU
-    test)."""
+    resident signals run as the benchmark step runs (--ksweep-inflight steps in flight on
+    their own streams, workspaces, outputs and copies of the signals): signals/s, tones
+    missed per signal, median value error against the planted tones (the FP32-vs-FP64
+    parity of these shapes is a GPU test)."""
     import numpy as np
     from paper_2012_08238_amd.signals import derive_seed, make_signal_torch
-    out = {"N": N, "L": L, "snr_db": SNR_DB, "batch": args.ksweep_batch, "points": []}
+    nf = max(1, args.ksweep_inflight)
+    out = {"N": N, "L": L, "snr_db": SNR_DB, "batch": args.ksweep_batch, "steps_in_flight": nf, "points": []}
     m = args.ksweep_batch
     for k in (50, 100, 200, 500, 1000):
         b = 1 << int(round(np.log2(np.sqrt(N * k))))
         sigs = [make_signal_torch(N, k, SNR_DB, derive_seed(150 + k, i), dev) for i in range(m)]
         xs = [q[0] for q in sigs]
+        xsets = [xs] + [[x.clone() for x in xs] for _ in range(nf - 1)]
         plan = S.Plan(N, k, b, L, 8 * b, seed=29)
-        bt = S.Batch([plan] * m, branches=args.section_branches)
-        outs = [plan.outputs(dev) for _ in range(m)]
+        bts = [S.Batch([plan] * m, branches=args.branches) for _ in range(nf)]
+        outsets = [[plan.outputs(dev) for _ in range(m)] for _ in range(nf)]
+        streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev) for _ in range(nf - 1)]
+        for j in range(nf):
+            bts[j].bind(xsets[j], [o[0] for o in outsets[j]], [o[1] for o in outsets[j]], [o[2] for o in outsets[j]])
         for _ in range(2):
-            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+            for j in range(nf):
+                bts[j].run_bound(stream=streams[j])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.ksweep_steps):
-            bt.run(xs, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+        for st in range(args.ksweep_steps):
+            j = st % nf
+            bts[j].run_bound(stream=streams[j])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         missed, errs = 0, []
-        for o, q in zip(outs, sigs):
+        for o, q in zip(outsets[0], sigs):
             got = dict(zip(o[0].cpu().numpy().tolist(), o[1].cpu().numpy().tolist()))
             for f, tone in zip(q[1].tolist(), q[2].tolist()):
                 if f in got:
@@ -485,9 +493,10 @@ def k_sweep_measure(S, torch, dev, args) -> dict:
         pt = {"K": k, "B": b, "w": 8 * b, "signals_per_s": round(m * args.ksweep_steps / el, 1),
               "missed_per_signal": round(missed / m, 3), "median_value_err": float(np.median(errs)) if errs else None}
         out["points"].append(pt)
-        bt.close()
+        for bt in bts:
+            bt.close()
         plan.close()
-        del sigs, xs, outs
+        del sigs, xs, xsets, outsets
         print(f"# K sweep {pt}", file=sys.stderr, flush=True)
     return out
 
@@ -734,8 +743,9 @@ def main() -> int:
     ap.add_argument("--phase-steps", type=int, default=10)
     ap.add_argument("--est-batch", type=int, default=32, help="signals per batch of the estimation-loop runs (0 = skip)")
     ap.add_argument("--est-steps", type=int, default=10)
-    ap.add_argument("--ksweep-batch", type=int, default=16, help="signals per batch of the K sweep (0 = skip)")
-    ap.add_argument("--ksweep-steps", type=int, default=5)
+    ap.add_argument("--ksweep-batch", type=int, default=64, help="signals per batch of the K sweep (0 = skip)")
+    ap.add_argument("--ksweep-steps", type=int, default=60)
+    ap.add_argument("--ksweep-inflight", type=int, default=3, help="steps in flight of the K sweep")
     ap.add_argument("--fused-batches", default="16,256,1024",
                     help="batch sizes of the fused-launch vs graph comparison on small plans (empty = skip)")
     ap.add_argument("--no-context", action="store_true", help="skip the copy-bandwidth and dense-FFT context")
