@@ -38,7 +38,7 @@ N, K, B, L, SNR_DB = 1 << 22, 100, 16384, 9, 20.0
 PLAN_SEED = 1
 HBM_PEAK_GBPS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_strip_pf_kernel_n22_k100_b64_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2012_08238_amd", "csrc", "fold.hip")   # the bucketization kernels
+KERNEL_SRC = [os.path.join(ROOT, "paper_2012_08238_amd", "csrc", f) for f in ("fold.hip", "fold_dev.hpp")]  # the bucketization
 
 
 def alg_bytes_per_signal(W: int) -> float:
@@ -46,8 +46,11 @@ def alg_bytes_per_signal(W: int) -> float:
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def vote_flags(args) -> int:
