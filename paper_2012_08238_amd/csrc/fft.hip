@@ -189,7 +189,10 @@ struct SeqFft {
 };
 
 // First pass: 16 columns j2 of the B1 x B2 view per workgroup -> ubuf, row-major
-// [k1][j2], twisted. Units per signal: L * B2/16.
+// [k1][j2], twisted. The twist W_B^m (m = j2 k1 mod B) is the product of two LDS table
+// entries, W_B^{m mod B1} W_B^{B1 (m div B1)}, instead of a gather from the B-entry table
+// per value (a 64-lane store instruction touched 64 table lines). Units per signal:
+// L * B2/16.
 template <int LB>
 __global__ __launch_bounds__(256) void fft_large_p1_kernel(Launch a) {
     using C = LargeCfg<LB>;
@@ -197,6 +200,8 @@ __global__ __launch_bounds__(256) void fft_large_p1_kernel(Launch a) {
     extern __shared__ f4v lds_raw[];
     float2* data = reinterpret_cast<float2*>(lds_raw);
     float2* tp = data + 16 * F::SP;
+    float2* tlo = tp + F::P;      // W_B^i, i < B1
+    float2* thi = tlo + C::B1;    // W_B^{B1 i}, i < B2
     uint32_t sig, unit;
     resolve(a, sig, unit);
     const auto& d = desc_of(a, sig);
@@ -223,13 +228,16 @@ __global__ __launch_bounds__(256) void fft_large_p1_kernel(Launch a) {
         }
     }
     for (int m = threadIdx.x; m < C::B1; m += C::NT) tp[m] = gld(tw + ((size_t)m << (LB - C::LB1)));
+    for (int m = threadIdx.x; m < C::B1; m += C::NT) tlo[m] = gld(tw + m);
+    for (int m = threadIdx.x; m < C::B2; m += C::NT) thi[m] = gld(tw + ((size_t)m << C::LB1));
     __syncthreads();
     F::run(data, tp);
 #pragma unroll 4
     for (int q = 0; q < NE; ++q) {
         const int e = (int)threadIdx.x + q * C::NT;
         const uint32_t k1 = (uint32_t)e >> 4, j2 = j20 + (uint32_t)(e & 15);
-        const float2 t = gld(tw + ((j2 * k1) & (uint32_t)(C::B - 1)));   // W_B^{j2 k1}
+        const uint32_t m = (j2 * k1) & (uint32_t)(C::B - 1);
+        const float2 t = cmul(thi[m >> C::LB1], tlo[m & (uint32_t)(C::B1 - 1)]);   // W_B^{j2 k1}
         gst(y + (size_t)k1 * C::B2 + j2, cmul(data[(e & 15) * F::SP + padi((int)k1)], t));
     }
 }
@@ -551,7 +559,7 @@ hipError_t launch_comb(const Launch& a, uint32_t log2b, uint32_t units, hipStrea
 template <int LB>
 constexpr size_t large_lds(uint32_t pass) {
     using C = LargeCfg<LB>;
-    return pass == 0   ? SeqFft<C::LB1, 16, C::NT>::lds_bytes()
+    return pass == 0   ? SeqFft<C::LB1, 16, C::NT>::lds_bytes() + (size_t)(C::B1 + C::B2) * sizeof(float2)
            : pass == 1 ? SeqFft<C::LB2, 16, C::NT>::lds_bytes()
                        : (size_t)(C::NW + 2 * C::SELCAP) * sizeof(uint32_t);
 }
