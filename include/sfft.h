@@ -55,7 +55,7 @@ typedef enum {
     SFFT_E_INVALID = -1,     /* bad argument or parameter set */
     SFFT_E_NOMEM = -2,       /* device or host allocation failed */
     SFFT_E_DEVICE = -3,      /* a HIP call failed (including sticky errors of earlier work) */
-    SFFT_E_UNSUPPORTED = -4, /* valid request this build does not implement */
+    SFFT_E_UNSUPPORTED = -4, /* valid request this library does not implement */
     SFFT_E_BUSY = -5,        /* plan still executing on another stream; or server full */
     SFFT_E_NOTFOUND = -6     /* unknown ticket */
 } sfft_status;

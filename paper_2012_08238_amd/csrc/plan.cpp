@@ -116,7 +116,7 @@ sfft_status resolve_params(const sfft_params& p, Resolved* out, std::string* err
         if (keep < 1 || keep > p.comb_b) return bad("comb_keep must be in [1, comb_b]");
     }
     if (p.B > kMaxB) {
-        *err = "B > 2^18 is not supported by this build";
+        *err = "B > 2^18 is not supported by this library";
         return SFFT_E_UNSUPPORTED;
     }
     if ((p.flags & SFFT_FLAG_ITERATE) && p.B > kMaxFftLds) {
