@@ -324,9 +324,10 @@ typedef struct {
  * request's footprint (its workspace, plus its plan tables when they are not
  * resident) fits in the arena and fewer than max_inflight requests are
  * admitted or running; idle resident tables are evicted least recently used
- * first when space is short. Whenever one of the n_streams streams is free,
- * every admitted request leaves as one wave: a batched launch sequence (as
- * sfft_batch_run; a lone request, the sequence of sfft_execute_ex) on that stream. Requests that arrive while waves run are
+ * first when space is short. Whenever one of the n_streams streams is free, the
+ * admitted requests (at most ceil(max_inflight / n_streams)) leave as one wave: a
+ * batched launch sequence (as sfft_batch_run; a lone request, the sequence of
+ * sfft_execute_ex) on that stream. Requests that arrive while waves run are
  * batched into the next wave, and waves on different streams overlap on the
  * device. Each request's result is bitwise the one sfft_execute_ex gives for
  * its parameter set alone. Plans are cached by parameter set (host tables kept

@@ -4,6 +4,7 @@
 // workspaces live in one device arena of the server's memory budget.
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <memory>
 #include <mutex>
@@ -303,8 +304,12 @@ sfft_status sfft_server_create(sfft_server_t* out, size_t hbm_budget_bytes, int3
         server_free(s);
         return st;
     }
+    // a wave takes at most max_inflight / n_streams requests, so that under a burst every stream
+    // holds a wave and consecutive waves overlap (as steps in flight do) instead of one stream
+    // running everything admitted
+    const int32_t wave = std::max<int32_t>(1, (max_inflight + n_streams - 1) / n_streams);
     s->core = std::make_unique<serve::ServerCore<IoDesc>>(s->ex.get(), hbm_budget_bytes, max_inflight, n_streams,
-                                                         max_inflight);
+                                                         wave);
     *out = s;
     return SFFT_OK;
 }
