@@ -16,6 +16,7 @@ CASES = [  # (N, K, B, L, w, extra plan arguments), largest first
     (1 << 20, 50, 1024, 7, 8192, {}),                                      # C2
     (1 << 18, 60, 512, 7, 4096, {"flags": 0x20}),                          # subtraction round
     (1 << 16, 20, 256, 5, 2048, {"est_loops": 4, "est_B": 1024}),          # estimation-only loops
+    (1 << 15, 8, 256, 7, 2048, {"flags": 0x400}),                          # fused one-launch form
     (1 << 14, 10, 128, 5, 512, {}),                                        # C1
 ]
 
