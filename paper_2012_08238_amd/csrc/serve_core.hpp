@@ -8,7 +8,8 @@
 // slot) -> running (part of a wave launched on a slot) -> done. Whenever a slot
 // is free, every admitted request (up to max_wave) leaves as one wave, so
 // requests that arrive while earlier waves run are batched together and their
-// waves overlap on the device.
+// waves overlap on the device. An idle worker polls the queue for a millisecond
+// before it blocks.
 #pragma once
 
 #include <stddef.h>
@@ -384,6 +385,8 @@ private:
         cv_done_.notify_all();
     }
 
+    static constexpr std::chrono::microseconds kIdleSpin{1000};
+
     void run() {
         ex_->thread_init();
         std::unique_lock<std::mutex> lk(mu_);
@@ -409,7 +412,17 @@ private:
                 std::this_thread::yield();
                 lk.lock();
             } else if (queue_.empty()) {
-                cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
+                // Idle: poll the queue for up to kIdleSpin before blocking, so that a request
+                // arriving soon after the last one (at 2000 req/s the next one comes within 1 ms
+                // 86% of the time) is picked up without waking the thread (several microseconds
+                // on the request's path). The cost is one host thread kept busy meanwhile.
+                const auto until = std::chrono::steady_clock::now() + kIdleSpin;
+                while (!stop_ && queue_.empty() && std::chrono::steady_clock::now() < until) {
+                    lk.unlock();
+                    std::this_thread::yield();
+                    lk.lock();
+                }
+                if (!stop_ && queue_.empty()) cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
             } else {
                 // a head that cannot be placed with nothing running does not occur
                 // (the arena then holds idle tables only); back off all the same
