@@ -100,17 +100,20 @@ public:
             }
             ++k;
         }
+        // A lone request reads only its descriptors from the staging buffer (its I/O pointers
+        // travel as kernel arguments) and needs no stage plan. Bytes the buffer already holds
+        // (the slot's previous wave staged the same descriptors: same plan, same arena
+        // placement) are not copied again: the copy is a device launch of its own on the
+        // request's path.
         std::vector<Step> steps;
         std::vector<uint32_t> prefix;
-        plan_steps(sig, &steps, &prefix);
-        const size_t total = o_pre + prefix.size() * 4;
-        if (total > stage_bytes_) return SFFT_E_INVALID;
-        memcpy(sl.h_stage + o_pre, prefix.data(), prefix.size() * 4);
-        // A lone request reads only its descriptors from the staging buffer (its I/O pointers
-        // travel as kernel arguments). Bytes the buffer already holds (the slot's previous wave
-        // staged the same descriptors: same plan, same arena placement) are not copied again:
-        // the copy is a device launch of its own on the request's path.
-        const size_t need = nreq == 1 ? sizeof(SigDesc) * n : total;
+        size_t need = sizeof(SigDesc) * n;
+        if (nreq > 1) {
+            plan_steps(sig, &steps, &prefix);
+            need = o_pre + prefix.size() * 4;
+            if (need > stage_bytes_) return SFFT_E_INVALID;
+            memcpy(sl.h_stage + o_pre, prefix.data(), prefix.size() * 4);
+        }
         hipError_t e = hipSuccess;
         if (!(need <= sl.held.size() && memcmp(sl.held.data(), sl.h_stage, need) == 0)) {
             e = hipMemcpyAsync(sl.d_stage, sl.h_stage, need, hipMemcpyHostToDevice, sl.stream);
