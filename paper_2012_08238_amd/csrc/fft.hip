@@ -21,7 +21,9 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
     const auto& d = desc_of(a, sig);
     {
         // the bucketization stored loop r's values in column order: column col
-        // holds bucket b = sigma_r^{-1} (col - tau_r) mod B; place them by bucket
+        // holds bucket b = sigma_r^{-1} (col - tau_r) mod B; place them by bucket.
+        // The twiddle entries are loaded first, so their loads are in flight with these.
+        const float2 twv = fft_twiddle_load<Cfg>(d);
         const float2* u = d.uhat + (size_t)r * B;
         const uint32_t sinv = d.sigma_inv[r], tu = d.tau[r];
         constexpr int LPT = (B + NT - 1) / NT;
@@ -36,8 +38,9 @@ __global__ __launch_bounds__(FftCfg<LOG2B>::NT) void fft_select_kernel(Launch a)
             const uint32_t col = threadIdx.x + q * NT;
             if (col < (uint32_t)B) sm.data[padi((int)((sinv * (col - tu)) & (uint32_t)(B - 1)))] = tmp[q];
         }
+        fft_twiddle_store(sm, twv);
     }
-    fft_select_loop<Cfg>(d, r, sm);
+    fft_select_staged<Cfg>(d, r, sm);
 }
 
 // Selection of the residual buckets of the subtraction round: loop r's B bucket

@@ -488,21 +488,44 @@ struct FftLds {
     }
 };
 
-// Loop r's B bucket values, placed in sm.data in bucket order by the caller (not yet
+// One twiddle table entry per thread (threads TL .. TL+TH-1 the hi table), loaded into a
+// register so that the load can be in flight with the bucket values' loads.
+template <class Cfg, class Desc>
+__device__ __forceinline__ float2 fft_twiddle_load(const Desc& d) {
+    static_assert(Cfg::TL + Cfg::TH <= Cfg::NT, "one twiddle entry per thread");
+    const int j = (int)threadIdx.x;
+    float2 t = make_float2(0.f, 0.f);
+    if (j < Cfg::TL) t = gld(d.tw + j);
+    else if (j < Cfg::TL + Cfg::TH) t = gld(d.tw + ((j - Cfg::TL) << Cfg::LOG2TL));
+    return t;
+}
+
+template <class Cfg>
+__device__ __forceinline__ void fft_twiddle_store(const FftLds<Cfg>& sm, float2 t) {
+    const int j = (int)threadIdx.x;
+    if (j < Cfg::TL) sm.tlo[j] = t;
+    else if (j < Cfg::TL + Cfg::TH) sm.thi[j - Cfg::TL] = t;
+}
+
+// Loop r's B bucket values and the twiddle tables, placed in sm by the caller (not yet
 // synchronised): their forward B-point DFT goes to uhat[r] (bucket order), and the dK
 // largest energies to the loop's bitmap and ascending list.
 template <class Cfg, class Desc>
-__device__ __forceinline__ void fft_select_loop(const Desc& d, uint32_t r, const FftLds<Cfg>& sm) {
+__device__ __forceinline__ void fft_select_staged(const Desc& d, uint32_t r, const FftLds<Cfg>& sm) {
     constexpr int B = Cfg::B, NT = Cfg::NT, NW = Cfg::NW;
     float2* u = d.uhat + (size_t)r * B;
-    const float2* tw = d.tw;
-    for (int j = threadIdx.x; j < Cfg::TL; j += NT) sm.tlo[j] = gld(tw + j);
-    for (int j = threadIdx.x; j < Cfg::TH; j += NT) sm.thi[j] = gld(tw + (j << Cfg::LOG2TL));
     __syncthreads();
     fft_passes<Cfg, 0>(sm.data, sm.tlo, sm.thi);
     for (int h = threadIdx.x; h < B; h += NT) gst(u + h, sm.data[padi(h)]);
     select_top<Cfg>(sm.data, d.dK, sm.hist, sm.scan, sm.bcast, sm.bits, d.jlist + (size_t)r * d.dK,
                     d.jbits + (size_t)r * NW);
+}
+
+// As fft_select_staged, the twiddle tables loaded here (after the caller's bucket values).
+template <class Cfg, class Desc>
+__device__ __forceinline__ void fft_select_loop(const Desc& d, uint32_t r, const FftLds<Cfg>& sm) {
+    fft_twiddle_store(sm, fft_twiddle_load<Cfg>(d));
+    fft_select_staged<Cfg>(d, r, sm);
 }
 
 }  // namespace sfft
