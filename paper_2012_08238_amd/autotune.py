@@ -10,9 +10,10 @@ reference SNR:
 * speed: device time of one batched execution of the probes, repeated to
   about 256 MB of signal (graph replay, median of a few), the fastest kept
   configuration wins;
-* bucketization tile: for the winner, the gather form and strip widths around
-  the default are timed. They never change results (every form sums the same
-  taps in the same order), so only time decides.
+* execution form: for the winner, the gather form, strip widths around the
+  default and (small plans) the fused one-launch form are timed. They never
+  change results (every form sums the same taps in the same order and runs the
+  same stage code), so only time decides.
 
 The table persists as JSON: {"<log2N>:<K octave>": {"B":, "wB":, "L":,
 "strip_cols":, "flags":, "ms":, "recall":}}. Tuning runs the library's kernels
@@ -24,7 +25,7 @@ import json
 import math
 import os
 
-from . import SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, Batch, Plan, PlanParams
+from . import SFFT_FLAG_FOLD_GATHER, SFFT_FLAG_FOLD_STRIP, SFFT_FLAG_FUSED, Batch, Plan, PlanParams
 
 MAX_B = 1 << 18
 
@@ -129,7 +130,7 @@ def tune_class(N: int, K: int, device, L: int = 9, snr_db: float = 10.0, probes:
     for t in trials:
         if t is not win:
             t["plan"].close()
-    # bucketization form and tile: results are identical, time decides
+    # bucketization form and tile, fused form: results are identical, time decides
     B, wB = win["B"], win["wB"]
     base = win["plan"]
     default_c = base.desc["strip_cols"]
@@ -138,6 +139,7 @@ def tune_class(N: int, K: int, device, L: int = 9, snr_db: float = 10.0, probes:
     for c in (default_c // 2, default_c * 2):
         if 2 <= c <= B:
             alt.append((SFFT_FLAG_FOLD_STRIP, c))
+    alt.append((SFFT_FLAG_FUSED, 0))   # refused (skipped) outside the fused form's scope
     base.close()
     for flags, c in alt:
         try:
