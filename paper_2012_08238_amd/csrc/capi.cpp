@@ -165,8 +165,13 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
         HIP_TRY(launch_decode(a, R.vote_units, 0, s), "phase decode launch");
     else
         HIP_TRY(launch_vote(a, vote_key(R.L), R.vote_units, R.vote_dyn_lds, R.vote_lds > 0, 0, s), "vote launch");
-    HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 0, s), "estimate launch");
-    HIP_TRY(launch_finalize(a, 1, R.fin_lds, 0, s), "top-K launch");
+    // the estimates and the K largest: one launch when one workgroup covers the candidates
+    auto tail = [&](uint32_t round) -> hipError_t {
+        if (R.est_units == 1) return launch_tail_one(a, R.lmax, R.fin_lds, round, s);
+        hipError_t e = launch_estimate(a, R.lmax, R.est_units, round, s);
+        return e == hipSuccess ? launch_finalize(a, 1, R.fin_lds, round, s) : e;
+    };
+    HIP_TRY(tail(0), "estimate / top-K launch");
     if (R.iterate) {
         HIP_TRY(launch_subtract(a, R.L, R.sub_lds, s), "subtraction launch");
         HIP_TRY(launch_reselect(a, R.log2B, R.L, s), "reselection launch");
@@ -174,8 +179,7 @@ sfft_status launch_single(const Resolved& R, const SigDesc* d_desc, const IoDesc
             HIP_TRY(launch_decode(a, R.vote_units, 1, s), "second phase decode launch");
         else
             HIP_TRY(launch_vote(a, vote_key(R.L), R.vote_units, R.vote_dyn_lds, R.vote_lds > 0, 1, s), "second vote launch");
-        HIP_TRY(launch_estimate(a, R.lmax, R.est_units, 1, s), "second estimate launch");
-        HIP_TRY(launch_finalize(a, 1, R.fin_lds, 1, s), "second top-K launch");
+        HIP_TRY(tail(1), "second estimate / top-K launch");
     }
     if (R.S) HIP_TRY(launch_residual_one(a, R.resid_blocks, R.resid_lds, s), "residual launch");
     return SFFT_OK;

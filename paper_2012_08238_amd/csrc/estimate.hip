@@ -109,6 +109,19 @@ __global__ __launch_bounds__(kSelNT) void finalize_kernel(Launch a, uint32_t rou
     finalize_body<kSelNT, kMaxK / kSelNT>(a, sig, round);
 }
 
+// One signal whose candidates one estimation workgroup covers (est_units = 1): the estimates
+// and then, after a barrier (this workgroup wrote them), the K largest, in one launch. The
+// top-K runs on the estimation workgroup's 256 threads (16 selected entries each, K <= 4096)
+// and gives the same outputs as finalize_kernel (they are unique: the K largest in f order).
+template <int LMAX>
+__global__ __launch_bounds__(kFinNT) void tail_one_kernel(Launch a, uint32_t round) {
+    uint32_t sig, unit;
+    resolve(a, sig, unit);
+    estimate_body<LMAX>(a, sig, 0u, round);
+    __syncthreads();
+    finalize_body<kFinNT, kMaxK / kFinNT>(a, sig, round);
+}
+
 // ---------------------------------------------------------------- subtraction round
 // Iterative framework (frameworks section), subtraction step for loop r: a
 // recovered coefficient (f, v) with p = sigma_r f mod N in bucket h0 at offset
@@ -300,6 +313,17 @@ hipError_t launch_estimate(const Launch& a, uint32_t lmax, uint32_t units, uint3
 
 hipError_t launch_finalize(const Launch& a, uint32_t units, uint32_t lds, uint32_t round, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(units), dim3(kSelNT), lds, s, a, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_one(const Launch& a, uint32_t lmax, uint32_t lds, uint32_t round, hipStream_t s) {
+    switch (lmax) {
+        case 4: hipLaunchKernelGGL(tail_one_kernel<4>, dim3(1), dim3(kFinNT), lds, s, a, round); break;
+        case 8: hipLaunchKernelGGL(tail_one_kernel<8>, dim3(1), dim3(kFinNT), lds, s, a, round); break;
+        case 16: hipLaunchKernelGGL(tail_one_kernel<16>, dim3(1), dim3(kFinNT), lds, s, a, round); break;
+        case 32: hipLaunchKernelGGL(tail_one_kernel<32>, dim3(1), dim3(kFinNT), lds, s, a, round); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -35,6 +35,9 @@ hipError_t launch_estimate(const Launch& a, uint32_t lmax, uint32_t units, uint3
 // the K largest estimates: one workgroup per signal; lds_bytes = Resolved::fin_lds (max over the launch);
 // round 0 of an iterating signal keeps them in the workspace, otherwise they go to the outputs
 hipError_t launch_finalize(const Launch& a, uint32_t units, uint32_t lds_bytes, uint32_t round, hipStream_t s);
+// one signal (nsig == 0) with est_units = 1: the estimates and the K largest in one launch of one
+// workgroup; lds_bytes = Resolved::fin_lds
+hipError_t launch_tail_one(const Launch& a, uint32_t lmax, uint32_t lds_bytes, uint32_t round, hipStream_t s);
 // subtraction round: one workgroup per (signal, loop); lds_bytes = Resolved::sub_lds (max over the launch)
 hipError_t launch_subtract(const Launch& a, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 // selection of the residual buckets: one workgroup per (signal, loop); every signal has B = 2^log2B <= 16384
