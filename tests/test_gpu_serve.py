@@ -16,6 +16,7 @@ MIX = [  # (N, K, B, L, w, seed, snr, flags)
     (1 << 18, 30, 2048, 9, 16384, 7, 20.0, 0x2),   # gather form
     (1 << 12, 4, 64, 4, 256, 8, 30.0, 0x1),        # even L, no residual
     (1 << 22, 100, 16384, 9, 131072, 1, 20.0, 0),  # strip form, the benchmark shape
+    (1 << 15, 8, 256, 7, 2048, 9, 20.0, 0x400),    # fused one-launch form
 ]
 
 
