@@ -47,8 +47,9 @@ __device__ __forceinline__ void fused_loops(const __attribute__((address_space(4
 }  // namespace fused_detail
 
 // VL = vote_key(L) (L <= 16, so VL = L); estimates over LMAX = 4, 8 or 16 >= L. The
-// estimation body sets its register count (224-252 VGPRs): one workgroup per compute unit
-// (a cap at 128 per lane for more workgroups spilled to scratch).
+// compiler gives each instance 256 VGPRs and about 185 AGPRs: one wave per SIMD, one
+// workgroup per compute unit (a cap at 128 registers per lane for more workgroups spilled
+// to scratch).
 template <int VL>
 __global__ __launch_bounds__(kFusedNT) void fused_kernel(Launch a, uint32_t units) {
     constexpr int LMAX = VL <= 4 ? 4 : (VL <= 8 ? 8 : 16);
