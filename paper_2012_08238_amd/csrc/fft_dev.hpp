@@ -521,11 +521,4 @@ __device__ __forceinline__ void fft_select_staged(const Desc& d, uint32_t r, con
                     d.jbits + (size_t)r * NW);
 }
 
-// As fft_select_staged, the twiddle tables loaded here (after the caller's bucket values).
-template <class Cfg, class Desc>
-__device__ __forceinline__ void fft_select_loop(const Desc& d, uint32_t r, const FftLds<Cfg>& sm) {
-    fft_twiddle_store(sm, fft_twiddle_load<Cfg>(d));
-    fft_select_staged<Cfg>(d, r, sm);
-}
-
 }  // namespace sfft

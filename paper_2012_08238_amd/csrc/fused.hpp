@@ -37,10 +37,12 @@ __device__ __forceinline__ void fused_loops(const __attribute__((address_space(4
     const uint32_t L = d.L;
     for (uint32_t r = 0; r < L; ++r) {
         if (r) __syncthreads();   // the previous loop's selection is done with the LDS
+        const float2 twv = fft_twiddle_load<Cfg>(d);   // in flight with the gathers
         const uint32_t s = gld(d.sigma + r), tu = gld(d.tau + r);
         for (uint32_t b = threadIdx.x; b < (uint32_t)Cfg::B; b += kFusedNT)
             sm.data[padi((int)b)] = gather_bucket(d, x, s, tu, b);
-        fft_select_loop<Cfg>(d, r, sm);
+        fft_twiddle_store(sm, twv);
+        fft_select_staged<Cfg>(d, r, sm);
     }
 }
 
