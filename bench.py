@@ -765,7 +765,7 @@ def main() -> int:
     metric_shape = (N, K, B, L) == (1 << 22, 100, 16384, 9)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding of this path is a design note, not a build", file=sys.stderr)
+              "how the path would shard over GPUs is described, not implemented", file=sys.stderr)
         return 2
 
     import numpy as np
