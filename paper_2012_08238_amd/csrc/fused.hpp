@@ -117,7 +117,7 @@ struct FusedTable {
     }
 };
 
-// the instances of L = 9..16 (fused_hi.hip; compiled apart to halve the build's longest step)
+// the instances of L = 9..16 (fused_hi.hip; a translation unit of their own, so the two halves compile in parallel)
 hipError_t launch_fused_hi(const Launch& a, uint32_t key, uint32_t units, uint32_t lds_bytes, hipStream_t s);
 
 }  // namespace sfft
