@@ -329,7 +329,17 @@ static void test_concurrent_clients() {
             for (int i = 0; i < 150; ++i) {
                 const uint32_t p = 1 + rng() % 5;
                 uint64_t k = 0;
-                if (core.submit(p, e.ws[p], Io{0, (int)p}, &k) != kCoreOk) ++bad;
+                if (c == 3 && i % 3 == 0) {   // this client queues bursts of three with one call
+                    const Io io[3] = {Io{0, (int)p}, Io{0, (int)p}, Io{0, (int)p}};
+                    uint64_t ks[3];
+                    if (core.submit_many(p, e.ws[p], io, 3, ks) != kCoreOk) ++bad;
+                    mine.push_back(ks[0]);
+                    mine.push_back(ks[1]);
+                    k = ks[2];
+                    i += 2;
+                } else if (core.submit(p, e.ws[p], Io{0, (int)p}, &k) != kCoreOk) {
+                    ++bad;
+                }
                 mine.push_back(k);
                 if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 300));
                 if (mine.size() > 5) {
