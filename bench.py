@@ -731,7 +731,8 @@ def main() -> int:
     ap.add_argument("--section-branches", type=int, default=4, help="graph branches of the other sections' batches")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="duration of the Poisson serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-burst", type=int, default=1024, help="requests of the saturated serving run")
+    ap.add_argument("--serve-burst", type=int, default=4096,
+                    help="requests of the saturated serving run (enough waves that start-up and drain weigh little)")
     ap.add_argument("--serve-budget-gib", type=int, default=8)
     ap.add_argument("--serve-inflight", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
